@@ -1,0 +1,199 @@
+/*
+ * dbp.h - C ABI of the MI355X (gfx950) digital-backpropagation library.
+ *
+ * The library backpropagates a dual- (or single-) polarization optical field
+ * through a fibre link with the split-step Fourier method (SSFM) or the
+ * enhanced SSFM (ESSFM) of Secondini et al., "Coherent 100G Nonlinear
+ * Compensation with Single-Step Digital Backpropagation":
+ *   - each step is a linear chromatic-dispersion substep, Sec. II Eq. (1),
+ *     X_k <- X_k exp(-j 2 pi^2 beta2 f_k^2 dz), done on overlapping blocks with
+ *     FFTs (overlap-and-save, Sec. III), followed by
+ *   - a nonlinear substep, Sec. II Eqs. (2)-(3): every polarization is rotated
+ *     by -gamma dz_eff J_k with J = I (SSFM) or J = the tap-filtered total
+ *     intensity I = |x|^2 + |y|^2 (ESSFM, taps c_i of Eq. (3)).
+ *
+ * Conventions shared by every entry point:
+ *   Fields   complex64 (float re, float im interleaved) in device memory,
+ *            C-contiguous [batch][n_pol][n_samples].  Caller-owned.
+ *   DFT      X_k = sum_n x_n exp(-j 2 pi k n / L); f_k = k fs / L for
+ *            k < L/2, (k - L) fs / L otherwise.
+ *   Units    ps, km, THz, W.  beta2 in ps^2/km (negative: anomalous), gamma
+ *            in 1/(W km), alpha in dB/km, fs in THz (samples per ps).
+ *   Link     n_spans identical spans of span_km with ideal amplifiers, the
+ *            field power-normalized: attenuation enters only the nonlinear
+ *            weight phi = gamma exp(-alpha z_a) (1 - exp(-alpha dz)) / alpha of
+ *            a segment starting z_a km into its span (Sec. II effective
+ *            length).  Backpropagation negates beta2 dz and phi and takes the
+ *            segments from the receiver end, applying each segment's
+ *            nonlinear phase at its transmitter-side end.  DBP_FLAG_FORWARD
+ *            runs the physical direction instead (channel simulation).
+ *   Taps     2Nc+1 real taps w, centre index Nc: J_n = sum_m w[m] I[n-(m-Nc)]
+ *            (the paper's symmetric c_i is w[Nc+i] = w[Nc-i] = c_i).
+ *   Blocks   overlap-and-save (Sec. III): block b covers samples
+ *            (b V - O/2 + m) mod L, m < Nb, V = Nb - O; k steps are applied
+ *            circularly inside each block per pass over the signal, and the
+ *            centre V samples are kept.  DBP_FLAG_WHOLE uses one block of the
+ *            whole signal (Nb = L, O = 0).
+ *   Streams  every device call is asynchronous on the given hipStream_t
+ *            (passed as void*; NULL = the null stream).  No call synchronizes
+ *            unless documented.
+ *   Errors   every call returns a dbp_status; nothing aborts or throws across
+ *            the ABI.  Validation errors are returned before any device work.
+ *   Threads  a plan is immutable after creation; concurrent calls on one plan
+ *            are safe when each call has its own workspace.
+ */
+#ifndef DBP_H
+#define DBP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum dbp_status {
+    DBP_OK = 0,
+    DBP_ERR_INVALID_ARG = 1,   /* a descriptor field, pointer or size is invalid */
+    DBP_ERR_UNSUPPORTED = 2,   /* valid but not built (e.g. a block size without a kernel) */
+    DBP_ERR_WORKSPACE = 3,     /* workspace missing or smaller than dbp_workspace_size */
+    DBP_ERR_OOM = 4,           /* host or device allocation failed */
+    DBP_ERR_HIP = 5            /* a HIP runtime call failed (no device, launch error, ...) */
+} dbp_status;
+
+typedef enum dbp_method { DBP_SSFM = 0, DBP_ESSFM = 1 } dbp_method;
+
+/* Linear substep: FFT filter of Eq. (1) on overlap-and-save blocks, or a
+ * time-domain complex FIR (learnable dispersion taps). */
+typedef enum dbp_linear { DBP_LINEAR_FFT = 0, DBP_LINEAR_FIR = 1 } dbp_linear;
+
+/* DBP_FP32: dispersion tables and nonlinear phase argument in FP32.
+ * DBP_FP32_FP64PHASE: dispersion tables generated in FP64, nonlinear phase
+ *   argument formed and reduced to [-pi, pi] in FP64, all else FP32.
+ * DBP_BF16X3: as DBP_FP32_FP64PHASE, with the block DFTs as split-precision
+ *   bfloat16 matrix products (hi*hi + hi*lo + lo*hi, FP32 accumulation). */
+typedef enum dbp_precision {
+    DBP_FP32 = 0, DBP_FP32_FP64PHASE = 1, DBP_BF16X3 = 2
+} dbp_precision;
+
+#define DBP_FLAG_FORWARD 0x1u   /* physical direction (forward propagation) */
+#define DBP_FLAG_WHOLE   0x2u   /* one circular block of the whole signal */
+
+typedef struct dbp_desc {
+    int32_t n_pol;            /* 1 or 2 */
+    int32_t batch;            /* >= 1 signals of equal length, back to back */
+    int64_t n_samples;        /* L, samples per polarization (>= block) */
+    double fs_thz;            /* sampling rate, > 0 */
+    int32_t n_spans;          /* >= 1 */
+    int32_t steps_per_span;   /* >= 1; N_s = n_spans * steps_per_span */
+    double span_km;           /* > 0 */
+    double beta2_ps2_km;
+    double gamma_w_km;        /* >= 0 */
+    double alpha_db_km;       /* >= 0 */
+    int32_t method;           /* dbp_method */
+    int32_t n_taps;           /* ESSFM: odd, 1..DBP_MAX_TAPS; SSFM: ignored (1) */
+    const float* taps;        /* host; ESSFM: [n_taps] (every step) or [N_s][n_taps] */
+    int32_t taps_per_step;    /* 0: taps holds one vector, 1: one per step */
+    int32_t linear;           /* dbp_linear */
+    int32_t n_fir;            /* FIR: odd, 1..DBP_MAX_FIR */
+    const float* fir;         /* host complex64 [n_fir] or [N_s][n_fir]; NULL: ideal taps
+                                 (centre n_fir samples of the impulse response of Eq. (1)) */
+    int32_t fir_per_step;     /* 0: fir holds one vector, 1: one per step */
+    int32_t block;            /* Nb, power of two; 0: chosen by the planner */
+    int32_t overlap;          /* O, even, < Nb (ignored when block == 0) */
+    int32_t steps_per_pass;   /* k >= 1; 0: chosen by the planner */
+    int32_t precision;        /* dbp_precision */
+    uint32_t flags;           /* DBP_FLAG_* */
+} dbp_desc;
+
+#define DBP_MAX_TAPS 129
+#define DBP_MAX_FIR 129
+
+typedef struct dbp_plan_s* dbp_plan_t;
+
+/* Fill *d with defaults: one dual-polarization signal, SSFM, FFT linear step,
+ * planner-chosen geometry, FP32_FP64PHASE.  Caller sets the link and size. */
+void dbp_desc_init(dbp_desc* d);
+
+/* Create a plan: validate, build the step schedule in FP64, choose the
+ * geometry, build the dispersion and twiddle tables and copy them to the
+ * current HIP device.  The plan owns its device tables.  Returns
+ * DBP_ERR_INVALID_ARG for an invalid descriptor (no device work done),
+ * DBP_ERR_UNSUPPORTED for a geometry without a kernel, DBP_ERR_HIP or
+ * DBP_ERR_OOM if the device upload fails.  *out is NULL on error. */
+dbp_status dbp_plan(const dbp_desc* desc, dbp_plan_t* out);
+
+/* Release a plan and its device tables (NULL is a no-op).  The caller must
+ * ensure no call using the plan is still running on any stream. */
+void dbp_destroy(dbp_plan_t plan);
+
+/* Geometry the plan uses: block Nb, overlap O, steps per pass k, total steps
+ * N_s, number of passes.  Any pointer may be NULL. */
+dbp_status dbp_plan_geometry(dbp_plan_t plan, int32_t* block, int32_t* overlap,
+                             int32_t* steps_per_pass, int32_t* n_steps, int32_t* n_passes);
+
+/* Host-only: the geometry dbp_plan would choose for desc, without touching
+ * the device (same validation as dbp_plan). */
+dbp_status dbp_choose_geometry(const dbp_desc* desc, int32_t* block, int32_t* overlap,
+                               int32_t* steps_per_pass);
+
+/* Host-only: the FP64 step schedule for desc: b[s] = +-beta2 dz and
+ * phi[s] = +-gamma exp(-alpha z_a) dz_eff for s < N_s (arrays of n entries;
+ * returns DBP_ERR_INVALID_ARG if n < N_s). */
+dbp_status dbp_schedule(const dbp_desc* desc, double* b, double* phi, int32_t n);
+
+/* Bytes of device workspace dbp_backprop (grad = 0) or dbp_backprop_grad
+ * (grad = 1) needs with this plan.  0 for an invalid plan. */
+size_t dbp_workspace_size(dbp_plan_t plan, int32_t grad);
+
+/* Backpropagate (or, with DBP_FLAG_FORWARD, propagate) in -> out.
+ *   in, out   device complex64 [batch][n_pol][n_samples]; in == out is
+ *             allowed, any other overlap is DBP_ERR_INVALID_ARG.
+ *   taps      device float32 [N_s][n_taps] overriding the plan's taps, or
+ *             NULL for the plan's own (ESSFM only).
+ *   fir       device complex64 [N_s][n_fir] overriding the plan's FIR taps, or
+ *             NULL (FIR linear step only).
+ *   ws        device workspace of ws_bytes >= dbp_workspace_size(plan, 0)
+ *             (may be NULL when that size is 0).
+ *   stream    hipStream_t. */
+dbp_status dbp_backprop(dbp_plan_t plan, const void* in, void* out, const float* taps,
+                        const void* fir, void* ws, size_t ws_bytes, void* stream);
+
+/* Gradient of a real loss through dbp_backprop (reverse mode).  Given
+ * grad_out = dL/dRe(out) + j dL/dIm(out) (device complex64, same shape as
+ * in), writes grad_in (same convention; may be NULL), grad_taps (device
+ * float32 [N_s][n_taps], ESSFM; may be NULL) and grad_fir (device complex64
+ * [N_s][n_fir], FIR linear step; may be NULL).  The forward pass is recomputed
+ * from in with checkpoints at every pass boundary.  ws_bytes >=
+ * dbp_workspace_size(plan, 1).  Gradients are overwritten, not accumulated. */
+dbp_status dbp_backprop_grad(dbp_plan_t plan, const void* in, const float* taps,
+                             const void* fir, const void* grad_out, void* grad_in,
+                             float* grad_taps, void* grad_fir, void* ws, size_t ws_bytes,
+                             void* stream);
+
+/* Ragged batch: n descriptors (each batch == 1; any mix of lengths, links,
+ * methods and taps, same n_pol) planned together.  Signal i occupies
+ * [n_pol][L_i] at element offset offsets[i] of one packed buffer. */
+dbp_status dbp_plan_batch(const dbp_desc* descs, int32_t n, dbp_plan_t* out);
+
+/* Element (complex64) offsets of every signal of a batch plan in the packed
+ * buffer, host array of n + 1 entries (the last is the total). */
+dbp_status dbp_batch_offsets(dbp_plan_t plan, int64_t* offsets, int32_t n_plus_1);
+
+/* Backpropagate every signal of a batch plan: in_packed -> out_packed (device
+ * complex64, layout of dbp_batch_offsets; in == out allowed).  All passes of
+ * all signals run in one persistent launch, replayed from a HIP graph. */
+dbp_status dbp_backprop_batch(dbp_plan_t plan, const void* in_packed, void* out_packed,
+                              void* ws, size_t ws_bytes, void* stream);
+
+/* Short static description of a status code. */
+const char* dbp_status_string(dbp_status s);
+
+/* Library version, e.g. 0x000100 for 0.1.0. */
+int32_t dbp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DBP_H */

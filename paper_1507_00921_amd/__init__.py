@@ -1,0 +1,236 @@
+"""Python binding of libdbp (MI355X digital backpropagation), argument marshalling only.
+
+Every step of the split-step path runs in the HIP kernels of lib/libdbp.so;
+this module converts Python/torch arguments into the C ABI of include/dbp.h
+(pointers, sizes and the current HIP stream).  PyTorch provides device memory
+and streams.  There is no fallback: if the library is not built, or a call
+fails, an exception is raised.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_double, c_float, c_int32, c_int64, c_size_t, c_uint32, c_void_p
+from typing import Optional
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "lib", "libdbp.so")
+
+SSFM, ESSFM = 0, 1
+LINEAR_FFT, LINEAR_FIR = 0, 1
+FP32, FP32_FP64PHASE, BF16X3 = 0, 1, 2
+FLAG_FORWARD, FLAG_WHOLE = 0x1, 0x2
+MAX_TAPS = 129
+MAX_FIR = 129
+
+STATUS = {0: "ok", 1: "invalid argument", 2: "unsupported configuration",
+          3: "workspace missing or too small", 4: "out of memory", 5: "HIP runtime error"}
+
+
+class DbpError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what}: {STATUS.get(status, status)} (status {status})")
+        self.status = status
+
+
+class Desc(ctypes.Structure):
+    _fields_ = [
+        ("n_pol", c_int32), ("batch", c_int32), ("n_samples", c_int64), ("fs_thz", c_double),
+        ("n_spans", c_int32), ("steps_per_span", c_int32), ("span_km", c_double),
+        ("beta2_ps2_km", c_double), ("gamma_w_km", c_double), ("alpha_db_km", c_double),
+        ("method", c_int32), ("n_taps", c_int32), ("taps", POINTER(c_float)), ("taps_per_step", c_int32),
+        ("linear", c_int32), ("n_fir", c_int32), ("fir", POINTER(c_float)), ("fir_per_step", c_int32),
+        ("block", c_int32), ("overlap", c_int32), ("steps_per_pass", c_int32),
+        ("precision", c_int32), ("flags", c_uint32),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libdbp.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                               "(python paper_1507_00921_amd/_build.py)")
+        L = ctypes.CDLL(LIB_PATH)
+        L.dbp_desc_init.argtypes = [POINTER(Desc)]
+        L.dbp_desc_init.restype = None
+        L.dbp_plan.argtypes = [POINTER(Desc), POINTER(c_void_p)]
+        L.dbp_plan.restype = c_int32
+        L.dbp_destroy.argtypes = [c_void_p]
+        L.dbp_destroy.restype = None
+        L.dbp_plan_geometry.argtypes = [c_void_p] + [POINTER(c_int32)] * 5
+        L.dbp_plan_geometry.restype = c_int32
+        L.dbp_choose_geometry.argtypes = [POINTER(Desc)] + [POINTER(c_int32)] * 3
+        L.dbp_choose_geometry.restype = c_int32
+        L.dbp_schedule.argtypes = [POINTER(Desc), POINTER(c_double), POINTER(c_double), c_int32]
+        L.dbp_schedule.restype = c_int32
+        L.dbp_workspace_size.argtypes = [c_void_p, c_int32]
+        L.dbp_workspace_size.restype = c_size_t
+        L.dbp_backprop.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                   c_size_t, c_void_p]
+        L.dbp_backprop.restype = c_int32
+        L.dbp_backprop_grad.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                        c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]
+        L.dbp_backprop_grad.restype = c_int32
+        L.dbp_plan_batch.argtypes = [POINTER(Desc), c_int32, POINTER(c_void_p)]
+        L.dbp_plan_batch.restype = c_int32
+        L.dbp_batch_offsets.argtypes = [c_void_p, POINTER(c_int64), c_int32]
+        L.dbp_batch_offsets.restype = c_int32
+        L.dbp_backprop_batch.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]
+        L.dbp_backprop_batch.restype = c_int32
+        L.dbp_status_string.argtypes = [c_int32]
+        L.dbp_status_string.restype = ctypes.c_char_p
+        L.dbp_version.argtypes = []
+        L.dbp_version.restype = c_int32
+        _lib = L
+    return _lib
+
+
+def _check(status: int, what: str):
+    if status != 0:
+        raise DbpError(status, what)
+
+
+def make_desc(n_samples: int, n_spans: int, steps_per_span: int = 1, *, n_pol: int = 2,
+              batch: int = 1, fs_thz: float = 0.056, span_km: float = 80.0,
+              beta2_ps2_km: float = -21.682619, gamma_w_km: float = 1.3, alpha_db_km: float = 0.2,
+              taps=None, taps_per_step: bool = False, fir=None, fir_per_step: bool = False,
+              n_fir: int = 0, linear: int = LINEAR_FFT, block: int = 0, overlap: int = 0,
+              steps_per_pass: int = 0, precision: int = FP32_FP64PHASE, forward: bool = False,
+              whole: bool = False):
+    """Build a Desc.  taps (ESSFM) and fir are host arrays kept alive on the returned object."""
+    d = Desc()
+    lib().dbp_desc_init(ctypes.byref(d))
+    d.n_pol, d.batch, d.n_samples, d.fs_thz = n_pol, batch, n_samples, fs_thz
+    d.n_spans, d.steps_per_span, d.span_km = n_spans, steps_per_span, span_km
+    d.beta2_ps2_km, d.gamma_w_km, d.alpha_db_km = beta2_ps2_km, gamma_w_km, alpha_db_km
+    keep = []
+    if taps is not None:
+        t = np.ascontiguousarray(np.asarray(taps, dtype=np.float32))
+        keep.append(t)
+        d.method = ESSFM
+        d.n_taps = t.shape[-1]
+        d.taps = t.ctypes.data_as(POINTER(c_float))
+        d.taps_per_step = 1 if taps_per_step else 0
+    else:
+        d.method = SSFM
+        d.n_taps = 1
+    d.linear = linear
+    if linear == LINEAR_FIR:
+        if fir is not None:
+            f = np.ascontiguousarray(np.asarray(fir, dtype=np.complex64))
+            keep.append(f)
+            d.n_fir = f.shape[-1]
+            d.fir = f.ctypes.data_as(POINTER(c_float))
+            d.fir_per_step = 1 if fir_per_step else 0
+        else:
+            d.n_fir = n_fir
+    d.block, d.overlap, d.steps_per_pass = block, overlap, steps_per_pass
+    d.precision = precision
+    d.flags = (FLAG_FORWARD if forward else 0) | (FLAG_WHOLE if whole else 0)
+    d._keep = keep
+    return d
+
+
+def schedule(desc: Desc):
+    """Host-only FP64 step schedule (b, phi) the planner builds for desc."""
+    ns = desc.n_spans * desc.steps_per_span
+    b = (c_double * ns)()
+    p = (c_double * ns)()
+    _check(lib().dbp_schedule(ctypes.byref(desc), b, p, ns), "dbp_schedule")
+    return np.array(b[:]), np.array(p[:])
+
+
+def choose_geometry(desc: Desc):
+    """Host-only (block, overlap, steps_per_pass) the planner would choose."""
+    nb, o, k = c_int32(), c_int32(), c_int32()
+    _check(lib().dbp_choose_geometry(ctypes.byref(desc), ctypes.byref(nb), ctypes.byref(o),
+                                     ctypes.byref(k)), "dbp_choose_geometry")
+    return nb.value, o.value, k.value
+
+
+def _stream_ptr(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """A dbp_plan: immutable geometry, schedule and device tables."""
+
+    def __init__(self, desc: Desc):
+        self.desc = desc
+        h = c_void_p()
+        _check(lib().dbp_plan(ctypes.byref(desc), ctypes.byref(h)), "dbp_plan")
+        self._h = h
+        nb, o, k, ns, npass = (c_int32() for _ in range(5))
+        _check(lib().dbp_plan_geometry(h, ctypes.byref(nb), ctypes.byref(o), ctypes.byref(k),
+                                       ctypes.byref(ns), ctypes.byref(npass)), "dbp_plan_geometry")
+        self.block, self.overlap, self.steps_per_pass = nb.value, o.value, k.value
+        self.n_steps, self.n_passes = ns.value, npass.value
+        self.shape = (desc.batch, desc.n_pol, desc.n_samples)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().dbp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def workspace_size(self, grad: bool = False) -> int:
+        return int(lib().dbp_workspace_size(self._h, 1 if grad else 0))
+
+    def _check_field(self, t, name):
+        import torch
+        if t.dtype != torch.complex64 or not t.is_cuda or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous complex64 CUDA tensor")
+        if t.numel() != self.shape[0] * self.shape[1] * self.shape[2]:
+            raise ValueError(f"{name} has {t.numel()} elements, plan expects {self.shape}")
+
+    def workspace(self, grad: bool = False):
+        import torch
+        n = self.workspace_size(grad)
+        return torch.empty(max(n, 1), dtype=torch.uint8, device="cuda")
+
+    def backprop(self, x, out=None, taps=None, fir=None, workspace=None, stream=None):
+        """Run the plan on x (complex64 [batch][n_pol][L] on the GPU); returns out."""
+        import torch
+        self._check_field(x, "input")
+        if out is None:
+            out = torch.empty_like(x)
+        self._check_field(out, "output")
+        if workspace is None:
+            workspace = self.workspace()
+        if taps is not None and (taps.dtype != torch.float32 or not taps.is_cuda or not taps.is_contiguous()):
+            raise ValueError("taps must be a contiguous float32 CUDA tensor [N_s][n_taps]")
+        st = lib().dbp_backprop(self._h, _ptr(x), _ptr(out), _ptr(taps), _ptr(fir), _ptr(workspace),
+                                workspace.numel(), _stream_ptr(stream))
+        _check(st, "dbp_backprop")
+        return out
+
+
+def plan(n_samples: int, n_spans: int, steps_per_span: int = 1, **kw) -> Plan:
+    return Plan(make_desc(n_samples, n_spans, steps_per_span, **kw))
+
+
+def version() -> int:
+    return int(lib().dbp_version())

@@ -1,0 +1,473 @@
+// C ABI of the digital-backpropagation library: validation, FP64 step
+// schedule and tables, geometry, workspace and kernel dispatch.
+// The declarations and conventions are documented in include/dbp.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <new>
+#include <vector>
+
+#include "dbp.h"
+#include "plan.hpp"
+#include "step_kernel.hpp"
+
+namespace dbp {
+
+// ------------------------------------------------------------------ kernel registry
+
+using LaunchFn = hipError_t (*)(const PassArgs&, int grid, hipStream_t);
+
+template <int NB, int E, int NPOL, bool P64>
+static hipError_t launch_pass(const PassArgs& a, int grid, hipStream_t s) {
+    hipLaunchKernelGGL((dbp_pass_kernel<NB, E, NPOL, P64>), dim3(grid), dim3(NB / E), 0, s, a);
+    return hipGetLastError();
+}
+
+struct KernelEntry {
+    int nb, e, npol;
+    bool p64;
+    LaunchFn fn;
+};
+
+#define DBP_K(NB, E)                                                                            \
+    {NB, E, 1, false, launch_pass<NB, E, 1, false>}, {NB, E, 1, true, launch_pass<NB, E, 1, true>}, \
+        {NB, E, 2, false, launch_pass<NB, E, 2, false>}, {NB, E, 2, true, launch_pass<NB, E, 2, true>}
+#define DBP_K1(NB, E) {NB, E, 1, false, launch_pass<NB, E, 1, false>}, {NB, E, 1, true, launch_pass<NB, E, 1, true>}
+
+static const KernelEntry kKernels[] = {
+    DBP_K(256, 4),   DBP_K(512, 8),   DBP_K(1024, 16), DBP_K(1024, 4), DBP_K(2048, 16),
+    DBP_K(4096, 16), DBP_K(8192, 16), DBP_K1(16384, 16),
+};
+
+static LaunchFn find_kernel(int nb, int e, int npol, bool p64) {
+    for (const auto& k : kKernels)
+        if (k.nb == nb && k.e == e && k.npol == npol && k.p64 == p64) return k.fn;
+    return nullptr;
+}
+
+// Values per thread: 16 (one wave per 1024-point block) when the launch has
+// enough blocks to fill the chip; with fewer than two blocks per CU, the
+// 256-thread variant spreads each block over all four SIMDs of its CU.
+int default_e(int nb, long long n_wg) {
+    if (nb == 1024 && n_wg < 512) return 4;
+    return nb <= 256 ? 4 : nb <= 512 ? 8 : 16;
+}
+
+bool have_kernel(int nb, int e, int npol) { return find_kernel(nb, e, npol, false) != nullptr; }
+
+int max_block(int npol) { return npol == 1 ? 16384 : 8192; }
+
+// ------------------------------------------------------------------ validation
+
+static bool finite(double x) { return std::isfinite(x); }
+static bool pow2(long long x) { return x > 0 && (x & (x - 1)) == 0; }
+
+dbp_status validate(const dbp_desc* d) {
+    if (!d) return DBP_ERR_INVALID_ARG;
+    if (d->n_pol != 1 && d->n_pol != 2) return DBP_ERR_INVALID_ARG;
+    if (d->batch < 1 || d->n_samples < 2) return DBP_ERR_INVALID_ARG;
+    if (!finite(d->fs_thz) || d->fs_thz <= 0) return DBP_ERR_INVALID_ARG;
+    if (d->n_spans < 1 || d->steps_per_span < 1) return DBP_ERR_INVALID_ARG;
+    if ((long long)d->n_spans * d->steps_per_span > (1 << 20)) return DBP_ERR_INVALID_ARG;
+    if (!finite(d->span_km) || d->span_km <= 0) return DBP_ERR_INVALID_ARG;
+    if (!finite(d->beta2_ps2_km) || !finite(d->gamma_w_km) || d->gamma_w_km < 0) return DBP_ERR_INVALID_ARG;
+    if (!finite(d->alpha_db_km) || d->alpha_db_km < 0) return DBP_ERR_INVALID_ARG;
+    if (d->method != DBP_SSFM && d->method != DBP_ESSFM) return DBP_ERR_INVALID_ARG;
+    if (d->method == DBP_ESSFM) {
+        if (d->n_taps < 1 || d->n_taps > DBP_MAX_TAPS || (d->n_taps % 2) == 0) return DBP_ERR_INVALID_ARG;
+        if (!d->taps) return DBP_ERR_INVALID_ARG;
+        if (d->taps_per_step != 0 && d->taps_per_step != 1) return DBP_ERR_INVALID_ARG;
+    }
+    if (d->linear != DBP_LINEAR_FFT && d->linear != DBP_LINEAR_FIR) return DBP_ERR_INVALID_ARG;
+    if (d->linear == DBP_LINEAR_FIR) {
+        if (d->n_fir < 1 || d->n_fir > DBP_MAX_FIR || (d->n_fir % 2) == 0) return DBP_ERR_INVALID_ARG;
+        if (d->fir_per_step != 0 && d->fir_per_step != 1) return DBP_ERR_INVALID_ARG;
+    }
+    if (d->precision < DBP_FP32 || d->precision > DBP_BF16X3) return DBP_ERR_INVALID_ARG;
+    if (d->flags & ~(DBP_FLAG_FORWARD | DBP_FLAG_WHOLE)) return DBP_ERR_INVALID_ARG;
+    if (d->steps_per_pass < 0) return DBP_ERR_INVALID_ARG;
+    if (d->block != 0 && !(d->flags & DBP_FLAG_WHOLE)) {
+        if (!pow2(d->block)) return DBP_ERR_INVALID_ARG;
+        if (d->overlap < 0 || (d->overlap % 2) != 0 || d->overlap >= d->block) return DBP_ERR_INVALID_ARG;
+        if (d->n_samples < d->block) return DBP_ERR_INVALID_ARG;
+    }
+    return DBP_OK;
+}
+
+// ------------------------------------------------------------------ schedule
+
+void build_schedule(const dbp_desc* d, std::vector<double>& b, std::vector<double>& phi) {
+    const int n = d->steps_per_span;
+    const int ns = d->n_spans * n;
+    const double dz = d->span_km / n;
+    const double alpha = d->alpha_db_km * std::log(10.0) / 10.0;
+    const double leff = alpha == 0.0 ? dz : -std::expm1(-alpha * dz) / alpha;
+    const bool fwd = (d->flags & DBP_FLAG_FORWARD) != 0;
+    b.resize(ns);
+    phi.resize(ns);
+    int s = 0;
+    for (int span = 0; span < d->n_spans; ++span) {
+        for (int i = 0; i < n; ++i, ++s) {
+            const double za = fwd ? i * dz : d->span_km - (i + 1) * dz;
+            const double sign = fwd ? 1.0 : -1.0;
+            b[s] = sign * d->beta2_ps2_km * dz;
+            phi[s] = sign * d->gamma_w_km * std::exp(-alpha * za) * leff;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ geometry
+
+// Samples of spread per side one step adds: half the dispersion memory
+// 2 pi |b| fs^2 (Sec. III) plus the Nc taps of the intensity filter.
+static double spread_per_side(double b, double fs, int nc) { return M_PI * std::fabs(b) * fs * fs + nc; }
+
+static constexpr int kMargin = 16;
+
+// Largest k whose accumulated spread fits the halo, at least 1.
+static int max_k(const std::vector<double>& b, double fs, int nc, int halo) {
+    double smax = 0;
+    for (double v : b) smax = std::max(smax, spread_per_side(v, fs, nc));
+    if (smax <= 0) return (int)b.size();
+    long long k = (long long)std::floor((halo - kMargin) / smax);
+    return (int)std::max<long long>(1, std::min<long long>(k, (long long)b.size()));
+}
+
+static int balance_k(int ns, int kmax) {
+    const int passes = (ns + kmax - 1) / kmax;
+    return (ns + passes - 1) / passes;
+}
+
+dbp_status choose_geometry(const dbp_desc* d, const std::vector<double>& b, Geometry& g) {
+    const int ns = (int)b.size();
+    const int nc = d->method == DBP_ESSFM ? (d->n_taps - 1) / 2 : 0;
+    if (d->linear == DBP_LINEAR_FIR) return DBP_ERR_UNSUPPORTED;
+    if (d->flags & DBP_FLAG_WHOLE) {
+        if (!pow2(d->n_samples) || d->n_samples > max_block(d->n_pol) || d->n_samples < 256)
+            return DBP_ERR_UNSUPPORTED;
+        g.block = (int)d->n_samples;
+        g.overlap = 0;
+        g.k = ns;
+    } else if (d->block != 0) {
+        g.block = d->block;
+        g.overlap = d->overlap;
+        g.k = d->steps_per_pass > 0 ? std::min(d->steps_per_pass, ns)
+                                    : balance_k(ns, max_k(b, d->fs_thz, nc, d->overlap / 2));
+    } else {
+        // cost per sample and step ~ Nb/(Nb-O) * (log2 Nb + 6 + 12/k), O the smallest
+        // overlap covering k steps
+        double best = 1e300;
+        double smax = 0;
+        for (double v : b) smax = std::max(smax, spread_per_side(v, d->fs_thz, nc));
+        for (int nb = 256; nb <= std::min<long long>(max_block(d->n_pol), d->n_samples); nb *= 2) {
+            for (int k = 1; k <= ns; ++k) {
+                int o = 2 * (int)std::ceil(k * smax + kMargin);
+                if (o > nb / 2) break;
+                int kb = balance_k(ns, k);
+                double cost = (double)nb / (nb - o) * (std::log2((double)nb) + 6.0 + 12.0 / kb);
+                if (cost < best - 1e-12) {
+                    best = cost;
+                    g.block = nb;
+                    g.overlap = o;
+                    g.k = kb;
+                }
+            }
+        }
+        if (best == 1e300) return DBP_ERR_UNSUPPORTED;
+        if (d->steps_per_pass > 0) g.k = std::min(d->steps_per_pass, ns);
+    }
+    {
+        const long long v = g.block - g.overlap;
+        const long long n_wg = (d->n_samples + v - 1) / v * d->batch;
+        g.e = default_e(g.block, n_wg);
+    }
+    if (!have_kernel(g.block, g.e, d->n_pol)) return DBP_ERR_UNSUPPORTED;
+    g.n_steps = ns;
+    g.n_passes = (ns + g.k - 1) / g.k;
+    return DBP_OK;
+}
+
+// ------------------------------------------------------------------ tables
+
+static void twiddle_table(int nb, std::vector<float2>& tw) {
+    tw.resize(nb);
+    for (int q = 0; q < nb; ++q) {
+        const double a = -2.0 * M_PI * (double)q / nb;
+        tw[q] = make_float2((float)std::cos(a), (float)std::sin(a));
+    }
+}
+
+// exp(-j 2 pi^2 b f_k^2) / nb in natural bin order, f_k = fftfreq(nb, 1/fs)
+static void dispersion_table(int nb, double b, double fs, bool fp64, float2* out) {
+    for (int k = 0; k < nb; ++k) {
+        const int kk = k < (nb + 1) / 2 ? k : k - nb;
+        if (fp64) {
+            const double f = kk * fs / nb;
+            double th = -2.0 * M_PI * M_PI * b * f * f;
+            th = std::remainder(th, 2.0 * M_PI);
+            out[k] = make_float2((float)(std::cos(th) / nb), (float)(std::sin(th) / nb));
+        } else {
+            const float f = (float)kk * (float)fs / (float)nb;
+            const float th = -2.0f * (float)(M_PI * M_PI) * (float)b * f * f;
+            out[k] = make_float2(std::cos(th) / (float)nb, std::sin(th) / (float)nb);
+        }
+    }
+}
+
+}  // namespace dbp
+
+using namespace dbp;
+
+// ------------------------------------------------------------------ C ABI
+
+extern "C" {
+
+void dbp_desc_init(dbp_desc* d) {
+    if (!d) return;
+    std::memset(d, 0, sizeof(*d));
+    d->n_pol = 2;
+    d->batch = 1;
+    d->fs_thz = 0.056;
+    d->n_spans = 1;
+    d->steps_per_span = 1;
+    d->span_km = 80.0;
+    d->method = DBP_SSFM;
+    d->n_taps = 1;
+    d->linear = DBP_LINEAR_FFT;
+    d->n_fir = 1;
+    d->precision = DBP_FP32_FP64PHASE;
+}
+
+const char* dbp_status_string(dbp_status s) {
+    switch (s) {
+        case DBP_OK: return "ok";
+        case DBP_ERR_INVALID_ARG: return "invalid argument";
+        case DBP_ERR_UNSUPPORTED: return "unsupported configuration";
+        case DBP_ERR_WORKSPACE: return "workspace missing or too small";
+        case DBP_ERR_OOM: return "out of memory";
+        case DBP_ERR_HIP: return "HIP runtime error";
+    }
+    return "unknown status";
+}
+
+int32_t dbp_version(void) { return 0x000100; }
+
+dbp_status dbp_schedule(const dbp_desc* desc, double* b, double* phi, int32_t n) {
+    dbp_status st = validate(desc);
+    if (st != DBP_OK) return st;
+    std::vector<double> vb, vp;
+    build_schedule(desc, vb, vp);
+    if (!b || !phi || n < (int32_t)vb.size()) return DBP_ERR_INVALID_ARG;
+    std::copy(vb.begin(), vb.end(), b);
+    std::copy(vp.begin(), vp.end(), phi);
+    return DBP_OK;
+}
+
+dbp_status dbp_choose_geometry(const dbp_desc* desc, int32_t* block, int32_t* overlap, int32_t* k) {
+    dbp_status st = validate(desc);
+    if (st != DBP_OK) return st;
+    std::vector<double> vb, vp;
+    build_schedule(desc, vb, vp);
+    Geometry g;
+    st = choose_geometry(desc, vb, g);
+    if (st != DBP_OK) return st;
+    if (block) *block = g.block;
+    if (overlap) *overlap = g.overlap;
+    if (k) *k = g.k;
+    return DBP_OK;
+}
+
+dbp_status dbp_plan(const dbp_desc* desc, dbp_plan_t* out) {
+    if (!out) return DBP_ERR_INVALID_ARG;
+    *out = nullptr;
+    dbp_status st = validate(desc);
+    if (st != DBP_OK) return st;
+    if (desc->precision == DBP_BF16X3) return DBP_ERR_UNSUPPORTED;
+    Plan* p = new (std::nothrow) Plan();
+    if (!p) return DBP_ERR_OOM;
+    p->desc = *desc;
+    p->desc.taps = nullptr;
+    p->desc.fir = nullptr;
+    build_schedule(desc, p->b, p->phi);
+    st = choose_geometry(desc, p->b, p->geo);
+    if (st != DBP_OK) {
+        delete p;
+        return st;
+    }
+    const int ns = p->geo.n_steps;
+    const int nb = p->geo.block;
+    const bool fp64 = desc->precision != DBP_FP32;
+    p->launch = (void*)find_kernel(nb, p->geo.e, desc->n_pol, fp64);
+
+    // distinct dispersion steps share one table
+    std::vector<float2> htab;
+    std::map<double, int> seen;
+    std::vector<StepDev> steps(ns);
+    for (int s = 0; s < ns; ++s) {
+        auto it = seen.find(p->b[s]);
+        int off;
+        if (it == seen.end()) {
+            off = (int)htab.size();
+            htab.resize(htab.size() + nb);
+            dispersion_table(nb, p->b[s], desc->fs_thz, fp64, htab.data() + off);
+            seen[p->b[s]] = off;
+        } else {
+            off = it->second;
+        }
+        steps[s].h_off = off;
+        steps[s].phi = (float)p->phi[s];
+        steps[s].phi64 = p->phi[s];
+    }
+    std::vector<float2> tw;
+    twiddle_table(nb, tw);
+    std::vector<float> taps;
+    if (desc->method == DBP_ESSFM) {
+        const int nt = desc->n_taps;
+        taps.resize((size_t)ns * nt);
+        for (int s = 0; s < ns; ++s)
+            for (int m = 0; m < nt; ++m)
+                taps[(size_t)s * nt + m] = desc->taps[(desc->taps_per_step ? (size_t)s * nt : 0) + m];
+    }
+
+    if (hipGetDevice(&p->device) != hipSuccess) {
+        delete p;
+        return DBP_ERR_HIP;
+    }
+    auto upload = [&](void** dptr, const void* src, size_t bytes) -> dbp_status {
+        if (bytes == 0) return DBP_OK;
+        hipError_t e = hipMalloc(dptr, bytes);
+        if (e == hipErrorOutOfMemory) return DBP_ERR_OOM;
+        if (e != hipSuccess) return DBP_ERR_HIP;
+        if (hipMemcpy(*dptr, src, bytes, hipMemcpyHostToDevice) != hipSuccess) return DBP_ERR_HIP;
+        return DBP_OK;
+    };
+    if ((st = upload((void**)&p->d_h, htab.data(), htab.size() * sizeof(float2))) != DBP_OK ||
+        (st = upload((void**)&p->d_tw, tw.data(), tw.size() * sizeof(float2))) != DBP_OK ||
+        (st = upload((void**)&p->d_steps, steps.data(), steps.size() * sizeof(StepDev))) != DBP_OK ||
+        (st = upload((void**)&p->d_taps, taps.data(), taps.size() * sizeof(float))) != DBP_OK) {
+        dbp_destroy(p);
+        return st;
+    }
+    p->h_taps = taps;
+    *out = p;
+    return DBP_OK;
+}
+
+void dbp_destroy(dbp_plan_t p) {
+    if (!p) return;
+    if (p->d_h) (void)hipFree(p->d_h);
+    if (p->d_tw) (void)hipFree(p->d_tw);
+    if (p->d_steps) (void)hipFree(p->d_steps);
+    if (p->d_taps) (void)hipFree(p->d_taps);
+    delete p;
+}
+
+dbp_status dbp_plan_geometry(dbp_plan_t p, int32_t* block, int32_t* overlap, int32_t* k,
+                             int32_t* n_steps, int32_t* n_passes) {
+    if (!p) return DBP_ERR_INVALID_ARG;
+    if (block) *block = p->geo.block;
+    if (overlap) *overlap = p->geo.overlap;
+    if (k) *k = p->geo.k;
+    if (n_steps) *n_steps = p->geo.n_steps;
+    if (n_passes) *n_passes = p->geo.n_passes;
+    return DBP_OK;
+}
+
+size_t dbp_workspace_size(dbp_plan_t p, int32_t grad) {
+    if (!p) return 0;
+    const size_t state = p->state_bytes();
+    if (grad) return 0;   // the gradient path is not built yet
+    return p->geo.n_passes == 1 ? state : 2 * state;
+}
+
+dbp_status dbp_backprop(dbp_plan_t p, const void* in, void* out, const float* taps, const void* fir,
+                        void* ws, size_t ws_bytes, void* stream) {
+    if (!p || !in || !out) return DBP_ERR_INVALID_ARG;
+    (void)fir;
+    const size_t state = p->state_bytes();
+    const char* ib = (const char*)in;
+    const char* ob = (const char*)out;
+    if (in != out && ib < ob + state && ob < ib + state) return DBP_ERR_INVALID_ARG;
+    const size_t need = dbp_workspace_size(p, 0);
+    if (ws_bytes < need || (need > 0 && !ws)) return DBP_ERR_WORKSPACE;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return DBP_ERR_HIP;
+    if (dev != p->device) return DBP_ERR_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    LaunchFn fn = (LaunchFn)p->launch;
+    if (!fn) return DBP_ERR_UNSUPPORTED;
+
+    const Geometry& g = p->geo;
+    PassArgs a{};
+    a.L = p->desc.n_samples;
+    a.V = g.block - g.overlap;
+    a.halo = g.overlap / 2;
+    a.n_blk = (int)((a.L + a.V - 1) / a.V);
+    a.n_wg = a.n_blk * p->desc.batch;
+    a.steps = p->d_steps;
+    a.H = p->d_h;
+    a.tw = p->d_tw;
+    a.taps = p->desc.method == DBP_ESSFM ? (taps ? taps : p->d_taps) : nullptr;
+    a.ntaps = p->desc.method == DBP_ESSFM ? p->desc.n_taps : 1;
+
+    float2* w0 = (float2*)ws;
+    float2* w1 = ws ? (float2*)((char*)ws + state) : nullptr;
+    const int P = g.n_passes;
+    const bool inplace = in == out;
+    const float2* src = (const float2*)in;
+    for (int pass = 0; pass < P; ++pass) {
+        float2* dst;
+        if (P == 1) {
+            dst = inplace ? w0 : (float2*)out;
+        } else if (pass == 0 && inplace) {
+            dst = w1;
+        } else {
+            dst = ((P - 1 - pass) % 2 == 0) ? (float2*)out : w0;
+        }
+        a.in = src;
+        a.out = dst;
+        a.s0 = pass * g.k;
+        a.ks = std::min(g.k, g.n_steps - a.s0);
+        if (fn(a, a.n_wg, s) != hipSuccess) return DBP_ERR_HIP;
+        src = dst;
+    }
+    if (P == 1 && inplace) {
+        if (hipMemcpyAsync(out, w0, state, hipMemcpyDeviceToDevice, s) != hipSuccess) return DBP_ERR_HIP;
+    }
+    return DBP_OK;
+}
+
+dbp_status dbp_backprop_grad(dbp_plan_t p, const void* in, const float* taps, const void* fir,
+                             const void* grad_out, void* grad_in, float* grad_taps, void* grad_fir,
+                             void* ws, size_t ws_bytes, void* stream) {
+    (void)in; (void)taps; (void)fir; (void)grad_out; (void)grad_in; (void)grad_taps;
+    (void)grad_fir; (void)ws; (void)ws_bytes; (void)stream;
+    if (!p) return DBP_ERR_INVALID_ARG;
+    return DBP_ERR_UNSUPPORTED;
+}
+
+dbp_status dbp_plan_batch(const dbp_desc* descs, int32_t n, dbp_plan_t* out) {
+    if (!descs || n < 1 || !out) return DBP_ERR_INVALID_ARG;
+    *out = nullptr;
+    return DBP_ERR_UNSUPPORTED;
+}
+
+dbp_status dbp_batch_offsets(dbp_plan_t p, int64_t* offsets, int32_t n_plus_1) {
+    (void)offsets; (void)n_plus_1;
+    if (!p) return DBP_ERR_INVALID_ARG;
+    return DBP_ERR_UNSUPPORTED;
+}
+
+dbp_status dbp_backprop_batch(dbp_plan_t p, const void* in_packed, void* out_packed, void* ws,
+                              size_t ws_bytes, void* stream) {
+    (void)in_packed; (void)out_packed; (void)ws; (void)ws_bytes; (void)stream;
+    if (!p) return DBP_ERR_INVALID_ARG;
+    return DBP_ERR_UNSUPPORTED;
+}
+
+}  // extern "C"

@@ -1,0 +1,147 @@
+// Fused split-step pass kernel: one workgroup propagates one overlap-and-save
+// block of both polarizations through k consecutive steps without leaving the
+// CU (Sec. II ops (i)-(iv), Sec. III overlap-and-save), then writes the
+// block's centre V samples.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "fft.hpp"
+
+namespace dbp {
+
+// Per-step constants prepared by the planner.
+struct StepDev {
+    int h_off;       // offset (complex elements) of this step's dispersion table
+    float phi;       // nonlinear weight gamma * dz_eff (signed), FP32
+    double phi64;    // the same in FP64 (phase-argument variant)
+};
+
+struct PassArgs {
+    const float2* in;       // [n_sig][NPOL][L]
+    float2* out;            // [n_sig][NPOL][L]
+    long long L;            // samples per polarization
+    int V;                  // valid samples per block (Nb - O)
+    int halo;               // O / 2
+    int n_blk;              // blocks per signal
+    int n_wg;               // n_blk * n_sig workgroups in the launch
+    const StepDev* steps;   // per-step constants (device)
+    int s0;                 // first step of this pass
+    int ks;                 // steps in this pass
+    const float2* H;        // dispersion tables: exp(-j 2 pi^2 b f_k^2) / Nb, natural bin order
+    const float2* tw;       // exp(-2 pi i q / Nb), q < Nb
+    const float* taps;      // [N_s][ntaps] or nullptr (SSFM: J = I)
+    int ntaps;              // odd
+};
+
+// Workgroups are dealt round-robin to the 8 XCDs; give each XCD a contiguous
+// range of blocks so that the halo a block shares with its neighbour is read
+// through the same L2.
+__device__ __forceinline__ int xcd_remap(int i, int n) {
+    const int q = n >> 3, r = n & 7;
+    const int xcd = i & 7, idx = i >> 3;
+    return xcd < r ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
+}
+
+template <bool PHASE64>
+__device__ __forceinline__ float2 phase_factor(float j, const StepDev& st) {
+    float s, c;
+    if constexpr (PHASE64) {
+        // argument -phi J formed and reduced to [-pi, pi] in FP64, rotated in FP32
+        const double th = -st.phi64 * (double)j;
+        const double k = rint(th * 0.15915494309189533577);
+        const float r = (float)fma(-k, 6.28318530717958647693, th);
+        sincosf(r, &s, &c);
+    } else {
+        sincosf(-st.phi * j, &s, &c);
+    }
+    return make_float2(c, s);
+}
+
+template <int NB, int E, int NPOL, bool PHASE64>
+__global__ __launch_bounds__(NB / E) void dbp_pass_kernel(PassArgs a) {
+    using S = FftShape<NB, E>;
+    constexpr int T = S::T;
+    __shared__ float2 lds[NPOL * S::PADDED];
+    float* ilds = reinterpret_cast<float*>(lds);   // intensity, aliases the FFT exchange buffer
+
+    const int t = threadIdx.x;
+    const int wg = xcd_remap(blockIdx.x, a.n_wg);
+    const int sig = wg / a.n_blk;
+    const int blk = wg - sig * a.n_blk;
+    const long long L = a.L;
+    const float2* __restrict__ src = a.in + (long long)sig * NPOL * L;
+    float2* __restrict__ dst = a.out + (long long)sig * NPOL * L;
+    const long long start = (long long)blk * a.V - a.halo;
+
+    float2 v[NPOL][E];
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+        long long i = start + t + T * q;
+        i = i < 0 ? i + L : (i >= L ? i - L : i);
+#pragma unroll
+        for (int p = 0; p < NPOL; ++p) v[p][q] = src[p * L + i];
+    }
+
+    TwReg<NB, E> twr;
+    load_twiddles<NB, E>(twr, a.tw, t);
+
+    const int c = (a.ntaps - 1) >> 1;
+    for (int s = a.s0; s < a.s0 + a.ks; ++s) {
+        const StepDev st = a.steps[s];
+        // (i) forward FFT of both polarizations
+        block_fft<NB, E, NPOL, false>(v, lds, twr, t);
+        // (ii) dispersion, Eq. (1), with the inverse FFT's 1/Nb folded in
+        const float2* __restrict__ hs = a.H + st.h_off;
+#pragma unroll
+        for (int q = 0; q < E; ++q) {
+            const float2 h = hs[t + T * q];
+#pragma unroll
+            for (int p = 0; p < NPOL; ++p) v[p][q] = cmul(v[p][q], h);
+        }
+        // (iii) inverse FFT
+        block_fft<NB, E, NPOL, true>(v, lds, twr, t);
+        // (iv) nonlinear phase driven by the total intensity, Eqs. (2)-(3)
+        float J[E];
+#pragma unroll
+        for (int q = 0; q < E; ++q) {
+            float in = 0.f;
+#pragma unroll
+            for (int p = 0; p < NPOL; ++p) in = fmaf(v[p][q].x, v[p][q].x, fmaf(v[p][q].y, v[p][q].y, in));
+            J[q] = in;
+        }
+        if (a.taps != nullptr) {
+            if constexpr (T > 64) __syncthreads();   // last FFT pass reads of lds are done
+#pragma unroll
+            for (int q = 0; q < E; ++q) ilds[t + T * q] = J[q];
+            __syncthreads();
+            const float* __restrict__ w = a.taps + (long long)s * a.ntaps;
+#pragma unroll
+            for (int q = 0; q < E; ++q) J[q] = 0.f;
+            for (int m = 0; m < a.ntaps; ++m) {
+                const float wm = w[m];
+#pragma unroll
+                for (int q = 0; q < E; ++q) J[q] = fmaf(wm, ilds[(t + T * q - m + c) & (NB - 1)], J[q]);
+            }
+            if constexpr (T > 64) __syncthreads();   // tap reads done before the next FFT writes lds
+        }
+#pragma unroll
+        for (int q = 0; q < E; ++q) {
+            const float2 r = phase_factor<PHASE64>(J[q], st);
+#pragma unroll
+            for (int p = 0; p < NPOL; ++p) v[p][q] = cmul(v[p][q], r);
+        }
+    }
+
+    // keep the centre V samples of the block
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+        const int pos = t + T * q;
+        const long long o = (long long)blk * a.V + pos - a.halo;
+        if (pos >= a.halo && pos < a.halo + a.V && o < L) {
+#pragma unroll
+            for (int p = 0; p < NPOL; ++p) dst[p * L + o] = v[p][q];
+        }
+    }
+}
+
+}  // namespace dbp

@@ -1,0 +1,151 @@
+"""Host-side checks of the C ABI: exports, validation, schedule and geometry (CPU only)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import siggen
+from oracle import dbp_ref as R
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dbp.h")
+
+
+def _lib_or_skip():
+    import paper_1507_00921_amd as dbp
+    if not os.path.exists(dbp.LIB_PATH):
+        pytest.skip("libdbp.so not built")
+    return dbp
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(dbp_[a-z_0-9]+)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_core_entry_points():
+    names = declared_functions()
+    for n in ["dbp_plan", "dbp_backprop", "dbp_backprop_grad", "dbp_destroy", "dbp_workspace_size",
+              "dbp_plan_batch", "dbp_backprop_batch", "dbp_status_string"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    dbp = _lib_or_skip()
+    lib = dbp.lib()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    out = os.popen(f"nm -D --defined-only {dbp.LIB_PATH}").read()
+    for name in declared_functions():
+        assert re.search(rf"\bT {name}$", out, flags=re.M), name
+
+
+def test_status_strings_and_version():
+    dbp = _lib_or_skip()
+    lib = dbp.lib()
+    for s in range(6):
+        assert lib.dbp_status_string(s).decode() == dbp.STATUS[s]
+    assert lib.dbp_version() == 0x000100
+
+
+def test_desc_struct_layout_matches_header(tmp_path):
+    # compile a probe against the header and compare every field offset with the ctypes mirror
+    dbp = _lib_or_skip()
+    fields = [f[0] for f in dbp.Desc._fields_]
+    body = "\n".join(f'printf("%zu\\n", offsetof(dbp_desc, {f}));' for f in fields)
+    src = tmp_path / "probe.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "dbp.h"\nint main(void){'
+                   + body + 'printf("%zu\\n", sizeof(dbp_desc));return 0;}\n')
+    exe = tmp_path / "probe"
+    assert os.system(f"gcc -std=c99 -I{ROOT}/include {src} -o {exe}") == 0
+    got = [int(v) for v in os.popen(str(exe)).read().split()]
+    want = [getattr(dbp.Desc, f).offset for f in fields] + [ctypes.sizeof(dbp.Desc)]
+    assert got == want
+
+
+def _desc(**kw):
+    dbp = _lib_or_skip()
+    args = dict(n_samples=262144, n_spans=40, steps_per_span=1, beta2_ps2_km=siggen.beta2_ps2_km())
+    args.update(kw)
+    n = args.pop("n_samples")
+    s = args.pop("n_spans")
+    k = args.pop("steps_per_span")
+    return dbp.make_desc(n, s, k, **args)
+
+
+@pytest.mark.parametrize("mutate", [
+    lambda d: setattr(d, "n_pol", 3),
+    lambda d: setattr(d, "batch", 0),
+    lambda d: setattr(d, "n_samples", 1),
+    lambda d: setattr(d, "fs_thz", 0.0),
+    lambda d: setattr(d, "n_spans", 0),
+    lambda d: setattr(d, "steps_per_span", 0),
+    lambda d: setattr(d, "span_km", -1.0),
+    lambda d: setattr(d, "gamma_w_km", -1.0),
+    lambda d: setattr(d, "alpha_db_km", float("nan")),
+    lambda d: setattr(d, "method", 7),
+    lambda d: (setattr(d, "method", 1), setattr(d, "n_taps", 4)),
+    lambda d: (setattr(d, "method", 1), setattr(d, "n_taps", 9)),          # taps pointer NULL
+    lambda d: setattr(d, "linear", 5),
+    lambda d: (setattr(d, "linear", 1), setattr(d, "n_fir", 8)),
+    lambda d: setattr(d, "precision", 9),
+    lambda d: setattr(d, "flags", 0x80),
+    lambda d: (setattr(d, "block", 1000), setattr(d, "overlap", 100)),     # not a power of two
+    lambda d: (setattr(d, "block", 1024), setattr(d, "overlap", 255)),     # odd overlap
+    lambda d: (setattr(d, "block", 1024), setattr(d, "overlap", 1024)),    # overlap >= block
+    lambda d: (setattr(d, "block", 1024), setattr(d, "overlap", 256), setattr(d, "n_samples", 512)),
+    lambda d: setattr(d, "steps_per_pass", -1),
+])
+def test_invalid_descriptors_rejected_without_device(mutate):
+    dbp = _lib_or_skip()
+    d = _desc()
+    mutate(d)
+    lib = dbp.lib()
+    assert lib.dbp_choose_geometry(ctypes.byref(d), None, None, None) == 1
+    h = ctypes.c_void_p(123)
+    assert lib.dbp_plan(ctypes.byref(d), ctypes.byref(h)) == 1     # returned before any HIP call
+    assert h.value is None
+
+
+def test_null_arguments():
+    dbp = _lib_or_skip()
+    lib = dbp.lib()
+    assert lib.dbp_plan(None, None) == 1
+    assert lib.dbp_backprop(None, None, None, None, None, None, 0, None) == 1
+    assert lib.dbp_workspace_size(None, 0) == 0
+    lib.dbp_destroy(None)
+
+
+@pytest.mark.parametrize("steps_per_span,forward", [(1, False), (20, False), (7, True)])
+def test_planner_schedule_matches_oracle(steps_per_span, forward):
+    dbp = _lib_or_skip()
+    d = _desc(steps_per_span=steps_per_span, forward=forward)
+    b, phi = dbp.schedule(d)
+    ref = R.schedule(40, 80.0, steps_per_span, siggen.beta2_ps2_km(), 1.3, 0.2, backward=not forward)
+    assert np.allclose(b, [s.b for s in ref], rtol=1e-15, atol=0)
+    assert np.allclose(phi, [s.phi for s in ref], rtol=1e-14, atol=0)
+
+
+def test_geometry_rules():
+    dbp = _lib_or_skip()
+    taps = siggen.symmetric_taps(siggen.rng(1, 0), 4)
+    # ESSFM 1 step/span, Nb=1024, O=256: spread per side 17.1 + 4 samples, margin 16 -> k = 5
+    assert dbp.choose_geometry(_desc(taps=taps, block=1024, overlap=256)) == (1024, 256, 5)
+    # SSFM 20 steps/span: spread 0.855 per step -> k_max 130, balanced over 7 passes -> 115
+    assert dbp.choose_geometry(_desc(steps_per_span=20, block=1024, overlap=256)) == (1024, 256, 115)
+    # explicit k is kept (clamped to N_s)
+    assert dbp.choose_geometry(_desc(block=1024, overlap=256, steps_per_pass=3))[2] == 3
+    assert dbp.choose_geometry(_desc(block=1024, overlap=256, steps_per_pass=99))[2] == 40
+    # whole signal: one block, no overlap, every step in one pass
+    d = _desc(n_samples=16384, n_spans=4, n_pol=1, whole=True)
+    assert dbp.choose_geometry(d) == (16384, 0, 4)
+    # auto geometry covers the accumulated spread of each pass
+    nb, o, k = dbp.choose_geometry(_desc(taps=taps))
+    assert o // 2 >= k * (np.pi * 21.6826 * 80 * 0.056 ** 2 + 4) + 16 - 1e-9 and nb > o
+    # whole-signal sizes without a kernel are refused as unsupported, not invalid
+    d = _desc(n_samples=12288, whole=True)
+    assert dbp.lib().dbp_choose_geometry(ctypes.byref(d), None, None, None) == 2
