@@ -120,6 +120,89 @@ def time_dbp(torch, p, x, out, ws, warmup, steps):
     return ev0.elapsed_time(ev1) / steps, wall
 
 
+def hbm_working_set(dbp, torch, rx, taps, batch=64, reps=10):
+    """The same ESSFM pass kernel on the field replicated `batch` times (256 MiB per state,
+    beyond the 256 MB Infinity Cache): one launch per pass, k = 1 (one HBM round trip per
+    step) and k = 5; algorithmic bytes = 21.33 B read (overlap inflation 4/3) + 16 B
+    written per sample and pass."""
+    b2 = siggen.beta2_ps2_km()
+    xb = rx.expand(batch, 2, N).contiguous()
+    out = torch.empty_like(xb)
+    res = {}
+    for k in (1, 5):
+        p = dbp.plan(N, k, 1, batch=batch, taps=taps, block=BLOCK, overlap=OVERLAP, steps_per_pass=k,
+                     beta2_ps2_km=b2)
+        assert p.n_passes == 1
+        ws = p.workspace()
+        ms, _ = time_dbp(torch, p, xb, out, ws, 3, reps)
+        byts = batch * N * 2 * 8 * (BLOCK / (BLOCK - OVERLAP) + 1)
+        res[f"k{k}"] = {"us_per_launch": round(ms * 1e3, 2), "achieved_gbs": round(byts / ms / 1e6, 1),
+                        "hbm_frac": round(byts / ms / 1e6 / HBM_PEAK_GBS, 4),
+                        "gsample_steps_per_s": round(batch * N * k / ms / 1e6, 2)}
+    res["workload"] = f"cfg1 field x{batch} (2x{N} each, {batch * N * 16 / 2**20:.0f} MiB per state)"
+    return res
+
+
+def grad_workload(dbp, torch, reps=5):
+    """Differentiation workload: 64 PM signals x 32768 samples at 3200 km, ESSFM 40 steps with
+    per-step 9-tap c_k and 33-tap complex dispersion FIRs (least-squares fit of Eq. (1) over
+    the signal band), loss = symbol MSE after the matched filter.  One training step =
+    forward + loss + backward through the autograd wrapper (checkpoint every 8 steps)."""
+    batch, n, spans = 64, 32768, 40
+    b2 = siggen.beta2_ps2_km()
+    xs = np.stack([siggen.transmitted_field(3, i, 2, n, 0.0)[0] for i in range(batch)])
+    sym = torch.from_numpy(np.stack([siggen.transmitted_field(3, i, 2, n, 0.0)[1]
+                                     for i in range(batch)])).cuda()
+    p = dbp.plan(n, spans, 1, batch=batch, taps=np.array([0, 0, 0, 0, 1, 0, 0, 0, 0], np.float32),
+                 linear=dbp.LINEAR_FIR, n_fir=33, fir_band_thz=0.0154, beta2_ps2_km=b2)
+    fir0 = dbp.fir_taps(dbp.make_desc(n, spans, 1, linear=dbp.LINEAR_FIR, n_fir=33, fir_band_thz=0.0154,
+                                      beta2_ps2_km=b2), 0)
+    x = torch.from_numpy(xs.astype(np.complex64)).cuda()
+    taps = torch.zeros(spans, 9, dtype=torch.float32, device="cuda")
+    taps[:, 4] = 1.0
+    fir = torch.from_numpy(np.stack([fir0] * spans).astype(np.complex64)).cuda()
+    taps.requires_grad_(True)
+    fir.requires_grad_(True)
+    mf = torch.from_numpy(siggen.rrc_response(n).astype(np.float32)).cuda()
+    a0 = math.sqrt(2 * siggen.dbm_to_w(0.0) / 2)
+    fn = dbp.dbp_function()
+
+    def step():
+        taps.grad = None
+        fir.grad = None
+        z = fn.apply(x, taps, fir, p)
+        y = torch.fft.ifft(torch.fft.fft(z, dim=-1) * mf, dim=-1)[..., ::2] / a0
+        loss = (y - sym).abs().pow(2).mean()
+        loss.backward()
+        return loss
+
+    for _ in range(2):
+        loss = step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        loss = step()
+    e1.record()
+    torch.cuda.synchronize()
+    ms_step = e0.elapsed_time(e1) / reps
+    out = torch.empty_like(x)
+    gout = torch.randn_like(x)
+    ws = p.workspace()
+    wsg = p.workspace(grad=True)
+    ms_f, _ = time_dbp(torch, p, x, out, ws, 1, reps)
+    e0.record()
+    for _ in range(reps):
+        p.backprop_grad(x, gout, taps=taps.detach(), fir=fir.detach(), workspace=wsg)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_b = e0.elapsed_time(e1) / reps
+    return {"workload": f"{batch}x2x{n}, 3200 km, ESSFM 40 steps, 9 taps + 33-tap FIR per step, "
+                        "checkpoint every 8 steps, symbol-MSE loss",
+            "fwd_bwd_ms": round(ms_step, 3), "dbp_forward_ms": round(ms_f, 3),
+            "dbp_backward_ms": round(ms_b, 3), "loss": round(float(loss), 5)}
+
+
 def cpu_baseline(rx_np, taps, k, budget_s=12.0):
     """The FP64 oracle on the host: ESSFM 40 steps, blocked like the GPU, on the full field."""
     from oracle import dbp_ref as R
@@ -182,6 +265,10 @@ def main():
     log(f"ESSFM {ms_e:.4f} ms/DBP ({essfm.n_passes} launches), SSFM {ms_s:.3f} ms/DBP "
         f"({ssfm.n_passes} launches)")
 
+    hbm = hbm_working_set(dbp, torch, rx, taps)
+    log("large working set " + json.dumps(hbm))
+    grad = grad_workload(dbp, torch)
+    log("gradient workload " + json.dumps(grad))
     value = N / (ms_e * 1e-3) / 1e6
     # dominant kernel: the fused pass kernel of the ESSFM run; algorithmic work per launch =
     # Sec. III operation count per sample and step x steps per launch x samples
@@ -218,6 +305,7 @@ def main():
             "essfm_vs_ssfm_speedup": round(ms_s / ms_e, 2),
             "evm_db": {k: round(v, 3) for k, v in evms.items()},
             "taps": [round(float(t), 6) for t in taps],
+            "gradient": grad,
         },
         "roofline": {
             "bound": "alu",
@@ -226,12 +314,13 @@ def main():
             "unit": "TFLOP/s",
             "frac": round(achieved_tflops / FP32_PEAK_TFLOPS, 4),
             "traffic": None,
-            "kernel": "dbp_pass_kernel<1024,4,2,P64>",
+            "kernel": "dbp_pass_kernel<1024,4,2,true,9>",
             "avg_launch_us": round(avg_launch_ms * 1e3, 3),
             "algorithmic_flops_per_launch": flops_launch,
             "algorithmic_bytes_per_launch": bytes_launch,
             "achieved_hbm_gbs": round(achieved_gbs, 1),
             "hbm_frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
+            "large_working_set": hbm,
         },
     }
     if not args.no_cpu:

@@ -96,9 +96,13 @@ typedef struct dbp_desc {
     int32_t taps_per_step;    /* 0: taps holds one vector, 1: one per step */
     int32_t linear;           /* dbp_linear */
     int32_t n_fir;            /* FIR: odd, 1..DBP_MAX_FIR */
-    const float* fir;         /* host complex64 [n_fir] or [N_s][n_fir]; NULL: ideal taps
-                                 (centre n_fir samples of the impulse response of Eq. (1)) */
+    const float* fir;         /* host complex64 [n_fir] or [N_s][n_fir]; NULL: taps designed
+                                 from the all-pass response of Eq. (1), see fir_band_thz */
     int32_t fir_per_step;     /* 0: fir holds one vector, 1: one per step */
+    double fir_band_thz;      /* designed taps (fir == NULL): 0 -> the centre n_fir samples of
+                                 the impulse response; > 0 -> least squares on the 4096-point
+                                 DFT grid, target Eq. (1) for |f| <= fir_band_thz, target 0
+                                 with weight 1e-3 outside */
     int32_t block;            /* Nb, power of two; 0: chosen by the planner */
     int32_t overlap;          /* O, even, < Nb (ignored when block == 0) */
     int32_t steps_per_pass;   /* k >= 1; 0: chosen by the planner */
@@ -142,6 +146,11 @@ dbp_status dbp_choose_geometry(const dbp_desc* desc, int32_t* block, int32_t* ov
  * returns DBP_ERR_INVALID_ARG if n < N_s). */
 dbp_status dbp_schedule(const dbp_desc* desc, double* b, double* phi, int32_t n);
 
+/* Host-only: the designed FIR taps (desc->fir == NULL, linear == DBP_LINEAR_FIR)
+ * of step `step`: n_fir complex values (re, im interleaved) into out[2 n_fir].
+ * Same validation as dbp_plan. */
+dbp_status dbp_fir_taps(const dbp_desc* desc, int32_t step, float* out);
+
 /* Bytes of device workspace dbp_backprop (grad = 0) or dbp_backprop_grad
  * (grad = 1) needs with this plan.  0 for an invalid plan. */
 size_t dbp_workspace_size(dbp_plan_t plan, int32_t grad);
@@ -159,13 +168,18 @@ size_t dbp_workspace_size(dbp_plan_t plan, int32_t grad);
 dbp_status dbp_backprop(dbp_plan_t plan, const void* in, void* out, const float* taps,
                         const void* fir, void* ws, size_t ws_bytes, void* stream);
 
-/* Gradient of a real loss through dbp_backprop (reverse mode).  Given
+/* Gradient of a real loss through dbp_backprop (reverse mode), for plans
+ * with the FIR linear step (DBP_ERR_UNSUPPORTED otherwise).  Given
  * grad_out = dL/dRe(out) + j dL/dIm(out) (device complex64, same shape as
- * in), writes grad_in (same convention; may be NULL), grad_taps (device
- * float32 [N_s][n_taps], ESSFM; may be NULL) and grad_fir (device complex64
- * [N_s][n_fir], FIR linear step; may be NULL).  The forward pass is recomputed
- * from in with checkpoints at every pass boundary.  ws_bytes >=
- * dbp_workspace_size(plan, 1).  Gradients are overwritten, not accumulated. */
+ * in), writes grad_in (same convention; may be NULL; must not overlap
+ * grad_out), grad_taps (device float32 [N_s][n_taps], ESSFM; may be NULL)
+ * and grad_fir (device complex64 [N_s][n_fir]; may be NULL).  taps and fir
+ * override the plan's parameters as in dbp_backprop.  The forward pass runs
+ * once storing the state every 8 steps; each 8-step segment is then
+ * recomputed from its checkpoint and its adjoint steps run in reverse.
+ * Parameter gradients are summed over the batch in a fixed order (bitwise
+ * reproducible).  ws_bytes >= dbp_workspace_size(plan, 1).  Gradients are
+ * overwritten, not accumulated. */
 dbp_status dbp_backprop_grad(dbp_plan_t plan, const void* in, const float* taps,
                              const void* fir, const void* grad_out, void* grad_in,
                              float* grad_taps, void* grad_fir, void* ws, size_t ws_bytes,

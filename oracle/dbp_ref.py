@@ -214,3 +214,25 @@ def ideal_fir_taps(n_taps: int, b: float, fs_thz: float, n_fft: int = 1 << 16) -
     c = (n_taps - 1) // 2
     imp = np.fft.ifft(dispersion_response(n_fft, b, fs_thz))
     return np.array([imp[(m - c) % n_fft] for m in range(n_taps)], dtype=np.complex128)
+
+
+def ls_fir_taps(n_taps: int, b: float, fs_thz: float, band_thz: float, n_grid: int = 4096,
+                oob_weight: float = 1e-3) -> np.ndarray:
+    """Least-squares FIR approximation of Eq. (1)'s all-pass response over a band.
+
+    Minimizes sum_k W_k |sum_m h_m exp(-j 2 pi f_k (m - c)/fs) - T_k|^2 on the
+    n_grid-point DFT grid, T = exp(-j 2 pi^2 b f^2) and W = 1 for |f| <= band,
+    T = 0 and W = oob_weight outside.  (A reading: the learnable dispersion
+    taps are initialised from the ideal filter this way because plain
+    truncation of the impulse response has gain above one near the band
+    edge, which a cascade of steps amplifies.)
+    """
+    c = (n_taps - 1) // 2
+    f = np.fft.fftfreq(n_grid, d=1.0 / fs_thz)
+    inb = np.abs(f) <= band_thz
+    w = np.where(inb, 1.0, oob_weight)
+    t = np.where(inb, np.exp(-1j * 2.0 * math.pi ** 2 * b * f * f), 0.0)
+    e = np.exp(-2j * math.pi * np.outer(f / fs_thz, np.arange(n_taps) - c))
+    sw = np.sqrt(w)
+    h, *_ = np.linalg.lstsq(e * sw[:, None], t * sw, rcond=None)
+    return h

@@ -42,7 +42,7 @@ class Desc(ctypes.Structure):
         ("beta2_ps2_km", c_double), ("gamma_w_km", c_double), ("alpha_db_km", c_double),
         ("method", c_int32), ("n_taps", c_int32), ("taps", POINTER(c_float)), ("taps_per_step", c_int32),
         ("linear", c_int32), ("n_fir", c_int32), ("fir", POINTER(c_float)), ("fir_per_step", c_int32),
-        ("block", c_int32), ("overlap", c_int32), ("steps_per_pass", c_int32),
+        ("fir_band_thz", c_double), ("block", c_int32), ("overlap", c_int32), ("steps_per_pass", c_int32),
         ("precision", c_int32), ("flags", c_uint32),
     ]
 
@@ -84,6 +84,8 @@ def lib():
         L.dbp_batch_offsets.restype = c_int32
         L.dbp_backprop_batch.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]
         L.dbp_backprop_batch.restype = c_int32
+        L.dbp_fir_taps.argtypes = [POINTER(Desc), c_int32, POINTER(c_float)]
+        L.dbp_fir_taps.restype = c_int32
         L.dbp_status_string.argtypes = [c_int32]
         L.dbp_status_string.restype = ctypes.c_char_p
         L.dbp_version.argtypes = []
@@ -101,7 +103,8 @@ def make_desc(n_samples: int, n_spans: int, steps_per_span: int = 1, *, n_pol: i
               batch: int = 1, fs_thz: float = 0.056, span_km: float = 80.0,
               beta2_ps2_km: float = -21.682619, gamma_w_km: float = 1.3, alpha_db_km: float = 0.2,
               taps=None, taps_per_step: bool = False, fir=None, fir_per_step: bool = False,
-              n_fir: int = 0, linear: int = LINEAR_FFT, block: int = 0, overlap: int = 0,
+              n_fir: int = 0, fir_band_thz: float = 0.0, linear: int = LINEAR_FFT, block: int = 0,
+              overlap: int = 0,
               steps_per_pass: int = 0, precision: int = FP32_FP64PHASE, forward: bool = False,
               whole: bool = False):
     """Build a Desc.  taps (ESSFM) and fir are host arrays kept alive on the returned object."""
@@ -131,6 +134,7 @@ def make_desc(n_samples: int, n_spans: int, steps_per_span: int = 1, *, n_pol: i
             d.fir_per_step = 1 if fir_per_step else 0
         else:
             d.n_fir = n_fir
+        d.fir_band_thz = fir_band_thz
     d.block, d.overlap, d.steps_per_pass = block, overlap, steps_per_pass
     d.precision = precision
     d.flags = (FLAG_FORWARD if forward else 0) | (FLAG_WHOLE if whole else 0)
@@ -153,6 +157,14 @@ def choose_geometry(desc: Desc):
     _check(lib().dbp_choose_geometry(ctypes.byref(desc), ctypes.byref(nb), ctypes.byref(o),
                                      ctypes.byref(k)), "dbp_choose_geometry")
     return nb.value, o.value, k.value
+
+
+def fir_taps(desc: Desc, step: int = 0):
+    """Host-only: the FIR taps the planner designs for `step` (complex128 array)."""
+    out = (c_float * (2 * desc.n_fir))()
+    _check(lib().dbp_fir_taps(ctypes.byref(desc), step, out), "dbp_fir_taps")
+    a = np.array(out[:], dtype=np.float64)
+    return a[0::2] + 1j * a[1::2]
 
 
 def _stream_ptr(stream):
@@ -220,12 +232,85 @@ class Plan:
         self._check_field(out, "output")
         if workspace is None:
             workspace = self.workspace()
-        if taps is not None and (taps.dtype != torch.float32 or not taps.is_cuda or not taps.is_contiguous()):
-            raise ValueError("taps must be a contiguous float32 CUDA tensor [N_s][n_taps]")
+        self._check_params(taps, fir)
         st = lib().dbp_backprop(self._h, _ptr(x), _ptr(out), _ptr(taps), _ptr(fir), _ptr(workspace),
                                 workspace.numel(), _stream_ptr(stream))
         _check(st, "dbp_backprop")
         return out
+
+    def _check_params(self, taps, fir):
+        import torch
+        ns = self.n_steps
+        if taps is not None and (taps.dtype != torch.float32 or not taps.is_cuda or not taps.is_contiguous()
+                                 or taps.numel() != ns * self.desc.n_taps):
+            raise ValueError(f"taps must be a contiguous float32 CUDA tensor [{ns}][{self.desc.n_taps}]")
+        if fir is not None and (fir.dtype != torch.complex64 or not fir.is_cuda or not fir.is_contiguous()
+                                or fir.numel() != ns * self.desc.n_fir):
+            raise ValueError(f"fir must be a contiguous complex64 CUDA tensor [{ns}][{self.desc.n_fir}]")
+
+    def backprop_grad(self, x, grad_out, taps=None, fir=None, want_input=True, workspace=None,
+                      stream=None):
+        """Reverse-mode gradient through backprop(x, taps, fir) for upstream grad_out.
+
+        Returns (grad_x or None, grad_taps [N_s][n_taps] float32 or None (SSFM),
+        grad_fir [N_s][n_fir] complex64).  Complex gradients are dL/dRe + j dL/dIm.
+        """
+        import torch
+        self._check_field(x, "input")
+        self._check_field(grad_out, "grad_out")
+        self._check_params(taps, fir)
+        ns = self.n_steps
+        gx = torch.empty_like(x) if want_input else None
+        gt = (torch.empty(ns, self.desc.n_taps, dtype=torch.float32, device=x.device)
+              if self.desc.method == ESSFM else None)
+        gf = torch.empty(ns, self.desc.n_fir, dtype=torch.complex64, device=x.device)
+        if workspace is None:
+            workspace = self.workspace(grad=True)
+        st = lib().dbp_backprop_grad(self._h, _ptr(x), _ptr(taps), _ptr(fir), _ptr(grad_out), _ptr(gx),
+                                     _ptr(gt), _ptr(gf), _ptr(workspace), workspace.numel(),
+                                     _stream_ptr(stream))
+        _check(st, "dbp_backprop_grad")
+        return gx, gt, gf
+
+
+def _autograd_function():
+    import torch
+
+    class DBPFunction(torch.autograd.Function):
+        """out = plan.backprop(x, taps, fir) with a hand-written adjoint (FIR linear step plans).
+
+        x: complex64 [batch][n_pol][L]; taps: float32 [N_s][n_taps] (ESSFM) or None;
+        fir: complex64 [N_s][n_fir].  Gradients follow PyTorch's convention for
+        complex tensors (dL/dRe + j dL/dIm), which is the library's.
+        """
+
+        @staticmethod
+        def forward(ctx, x, taps, fir, plan):
+            x = x.contiguous()
+            ctx.plan = plan
+            ctx.save_for_backward(x, taps, fir)
+            return plan.backprop(x, taps=taps, fir=fir)
+
+        @staticmethod
+        def backward(ctx, g):
+            x, taps, fir = ctx.saved_tensors
+            gx, gt, gf = ctx.plan.backprop_grad(x, g.contiguous(), taps=taps, fir=fir,
+                                                want_input=ctx.needs_input_grad[0])
+            return (gx, gt if ctx.needs_input_grad[1] else None,
+                    gf if ctx.needs_input_grad[2] else None, None)
+
+    return DBPFunction
+
+
+_DBPFunction = None
+
+
+def dbp_function():
+    """The torch.autograd.Function wrapping backprop / backprop_grad."""
+    global _DBPFunction
+    if _DBPFunction is None:
+        _DBPFunction = _autograd_function()
+    return _DBPFunction
 
 
 def plan(n_samples: int, n_spans: int, steps_per_span: int = 1, **kw) -> Plan:

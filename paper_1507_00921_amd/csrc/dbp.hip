@@ -14,40 +14,30 @@
 
 #include "dbp.h"
 #include "plan.hpp"
-#include "step_kernel.hpp"
+#include "registry.hpp"
+#include "fir_launch.hpp"
 
 namespace dbp {
 
 // ------------------------------------------------------------------ kernel registry
 
-using LaunchFn = hipError_t (*)(const PassArgs&, int grid, hipStream_t);
-
-template <int NB, int E, int NPOL, bool P64>
-static hipError_t launch_pass(const PassArgs& a, int grid, hipStream_t s) {
-    hipLaunchKernelGGL((dbp_pass_kernel<NB, E, NPOL, P64>), dim3(grid), dim3(NB / E), 0, s, a);
-    return hipGetLastError();
+static LaunchFn find_kernel(int nb, int e, int npol, bool p64, int nt) {
+    using Acc = const KernelEntry* (*)(int*);
+    static const Acc tables[] = {kernels_small, kernels_1024, kernels_2048, kernels_4096, kernels_large};
+    for (Acc acc : tables) {
+        int n = 0;
+        const KernelEntry* t = acc(&n);
+        for (int i = 0; i < n; ++i)
+            if (t[i].nb == nb && t[i].e == e && t[i].npol == npol && t[i].p64 == p64 && t[i].nt == nt)
+                return t[i].fn;
+    }
+    return nullptr;
 }
 
-struct KernelEntry {
-    int nb, e, npol;
-    bool p64;
-    LaunchFn fn;
-};
-
-#define DBP_K(NB, E)                                                                            \
-    {NB, E, 1, false, launch_pass<NB, E, 1, false>}, {NB, E, 1, true, launch_pass<NB, E, 1, true>}, \
-        {NB, E, 2, false, launch_pass<NB, E, 2, false>}, {NB, E, 2, true, launch_pass<NB, E, 2, true>}
-#define DBP_K1(NB, E) {NB, E, 1, false, launch_pass<NB, E, 1, false>}, {NB, E, 1, true, launch_pass<NB, E, 1, true>}
-
-static const KernelEntry kKernels[] = {
-    DBP_K(256, 4),   DBP_K(512, 8),   DBP_K(1024, 16), DBP_K(1024, 4), DBP_K(2048, 16),
-    DBP_K(4096, 16), DBP_K(8192, 16), DBP_K1(16384, 16),
-};
-
-static LaunchFn find_kernel(int nb, int e, int npol, bool p64) {
-    for (const auto& k : kKernels)
-        if (k.nb == nb && k.e == e && k.npol == npol && k.p64 == p64) return k.fn;
-    return nullptr;
+// Compile-time tap count of the variant serving a method and tap count.
+static int tap_variant(int method, int n_taps) {
+    if (method == DBP_SSFM) return 0;
+    return n_taps == 9 ? 9 : -1;
 }
 
 // Values per thread: 16 (one wave per 1024-point block) when the launch has
@@ -58,7 +48,7 @@ int default_e(int nb, long long n_wg) {
     return nb <= 256 ? 4 : nb <= 512 ? 8 : 16;
 }
 
-bool have_kernel(int nb, int e, int npol) { return find_kernel(nb, e, npol, false) != nullptr; }
+bool have_kernel(int nb, int e, int npol) { return find_kernel(nb, e, npol, false, -1) != nullptr; }
 
 int max_block(int npol) { return npol == 1 ? 16384 : 8192; }
 
@@ -87,6 +77,7 @@ dbp_status validate(const dbp_desc* d) {
     if (d->linear == DBP_LINEAR_FIR) {
         if (d->n_fir < 1 || d->n_fir > DBP_MAX_FIR || (d->n_fir % 2) == 0) return DBP_ERR_INVALID_ARG;
         if (d->fir_per_step != 0 && d->fir_per_step != 1) return DBP_ERR_INVALID_ARG;
+        if (!finite(d->fir_band_thz) || d->fir_band_thz < 0) return DBP_ERR_INVALID_ARG;
     }
     if (d->precision < DBP_FP32 || d->precision > DBP_BF16X3) return DBP_ERR_INVALID_ARG;
     if (d->flags & ~(DBP_FLAG_FORWARD | DBP_FLAG_WHOLE)) return DBP_ERR_INVALID_ARG;
@@ -146,7 +137,18 @@ static int balance_k(int ns, int kmax) {
 dbp_status choose_geometry(const dbp_desc* d, const std::vector<double>& b, Geometry& g) {
     const int ns = (int)b.size();
     const int nc = d->method == DBP_ESSFM ? (d->n_taps - 1) / 2 : 0;
-    if (d->linear == DBP_LINEAR_FIR) return DBP_ERR_UNSUPPORTED;
+    if (d->linear == DBP_LINEAR_FIR) {
+        // time-domain steps: one launch per step on tiles whose halo covers the
+        // FIR and tap spans, so tiling is exact for any signal length
+        if (nc > FT_MAXC || (d->n_fir - 1) / 2 > FT_MAXH) return DBP_ERR_UNSUPPORTED;
+        g.block = FT_TS;
+        g.overlap = 2 * ((d->n_fir - 1) / 2 + nc);
+        g.k = 1;
+        g.e = 0;
+        g.n_steps = ns;
+        g.n_passes = ns;
+        return DBP_OK;
+    }
     if (d->flags & DBP_FLAG_WHOLE) {
         if (!pow2(d->n_samples) || d->n_samples > max_block(d->n_pol) || d->n_samples < 256)
             return DBP_ERR_UNSUPPORTED;
@@ -219,6 +221,104 @@ static void dispersion_table(int nb, double b, double fs, bool fp64, float2* out
     }
 }
 
+// Centre n_fir samples of the impulse response of Eq. (1)'s all-pass filter on a
+// 65536-point FP64 grid: tap m multiplies x[n - (m - c)], c = (n_fir - 1) / 2.
+static void ideal_fir(int n_fir, double b, double fs, float2* out) {
+    const int n = 1 << 16;
+    const int c = (n_fir - 1) / 2;
+    std::vector<double> cr(n), ci(n);
+    for (int k = 0; k < n; ++k) {
+        const int kk = k < n / 2 ? k : k - n;
+        const double f = kk * fs / n;
+        const double th = std::remainder(-2.0 * M_PI * M_PI * b * f * f, 2.0 * M_PI);
+        cr[k] = std::cos(th);
+        ci[k] = std::sin(th);
+    }
+    for (int m = 0; m < n_fir; ++m) {
+        const long long d = m - c;
+        double sr = 0, si = 0;
+        for (int k = 0; k < n; ++k) {
+            const double a = 2.0 * M_PI * (double)((k * ((d % n + n) % n)) % n) / n;
+            const double ca = std::cos(a), sa = std::sin(a);
+            sr += cr[k] * ca - ci[k] * sa;
+            si += cr[k] * sa + ci[k] * ca;
+        }
+        out[m] = make_float2((float)(sr / n), (float)(si / n));
+    }
+}
+
+// Least-squares taps: minimize sum_k W_k |sum_m h_m exp(-j 2 pi f_k (m - c) / fs) - T_k|^2
+// over the 4096-point DFT grid f_k, with T = exp(-j 2 pi^2 b f^2), W = 1 for |f| <= band and
+// T = 0, W = 1e-3 outside.  Normal equations G h = r with G Toeplitz Hermitian, solved by a
+// complex Cholesky factorization in FP64.
+static void ls_fir(int n_fir, double b, double fs, double band, float2* out) {
+    const int n = 4096, c = (n_fir - 1) / 2;
+    std::vector<double> gr(2 * n_fir - 1, 0.0), gi(2 * n_fir - 1, 0.0), rr(n_fir, 0.0), ri(n_fir, 0.0);
+    for (int k = 0; k < n; ++k) {
+        const int kk = k < n / 2 ? k : k - n;
+        const double f = kk * fs / n;
+        const bool in = std::fabs(f) <= band;
+        const double w = in ? 1.0 : 1e-3;
+        const double th = in ? std::remainder(-2.0 * M_PI * M_PI * b * f * f, 2.0 * M_PI) : 0.0;
+        const double tr = in ? std::cos(th) : 0.0, ti = in ? std::sin(th) : 0.0;
+        for (int d = -(n_fir - 1); d <= n_fir - 1; ++d) {        // G[m][k'] = g[m - k']
+            const double a = 2.0 * M_PI * f * d / fs;
+            gr[d + n_fir - 1] += w * std::cos(a);
+            gi[d + n_fir - 1] += w * std::sin(a);
+        }
+        for (int m = 0; m < n_fir; ++m) {                          // r[m] = sum W T e^{+j a}
+            const double a = 2.0 * M_PI * f * (m - c) / fs;
+            const double ca = std::cos(a), sa = std::sin(a);
+            rr[m] += w * (tr * ca - ti * sa);
+            ri[m] += w * (tr * sa + ti * ca);
+        }
+    }
+    // Cholesky G = L L^H (L lower, complex)
+    std::vector<double> lr((size_t)n_fir * n_fir, 0.0), li((size_t)n_fir * n_fir, 0.0);
+    auto Gr = [&](int i, int j) { return gr[i - j + n_fir - 1]; };
+    auto Gi = [&](int i, int j) { return gi[i - j + n_fir - 1]; };
+    for (int j = 0; j < n_fir; ++j) {
+        double d = Gr(j, j);
+        for (int k = 0; k < j; ++k) d -= lr[j * n_fir + k] * lr[j * n_fir + k] + li[j * n_fir + k] * li[j * n_fir + k];
+        const double ljj = std::sqrt(d);
+        lr[j * n_fir + j] = ljj;
+        for (int i = j + 1; i < n_fir; ++i) {
+            double sr = Gr(i, j), si = Gi(i, j);
+            for (int k = 0; k < j; ++k) {        // - L[i][k] conj(L[j][k])
+                const double ar = lr[i * n_fir + k], ai = li[i * n_fir + k];
+                const double br = lr[j * n_fir + k], bi = li[j * n_fir + k];
+                sr -= ar * br + ai * bi;
+                si -= ai * br - ar * bi;
+            }
+            lr[i * n_fir + j] = sr / ljj;
+            li[i * n_fir + j] = si / ljj;
+        }
+    }
+    // forward substitution L y = r, then back substitution L^H h = y
+    std::vector<double> yr(n_fir), yi(n_fir), hr(n_fir), hi(n_fir);
+    for (int i = 0; i < n_fir; ++i) {
+        double sr = rr[i], si = ri[i];
+        for (int k = 0; k < i; ++k) {
+            const double ar = lr[i * n_fir + k], ai = li[i * n_fir + k];
+            sr -= ar * yr[k] - ai * yi[k];
+            si -= ar * yi[k] + ai * yr[k];
+        }
+        yr[i] = sr / lr[i * n_fir + i];
+        yi[i] = si / lr[i * n_fir + i];
+    }
+    for (int i = n_fir - 1; i >= 0; --i) {
+        double sr = yr[i], si = yi[i];
+        for (int k = i + 1; k < n_fir; ++k) {    // - conj(L[k][i]) h[k]
+            const double ar = lr[k * n_fir + i], ai = -li[k * n_fir + i];
+            sr -= ar * hr[k] - ai * hi[k];
+            si -= ar * hi[k] + ai * hr[k];
+        }
+        hr[i] = sr / lr[i * n_fir + i];
+        hi[i] = si / lr[i * n_fir + i];
+    }
+    for (int m = 0; m < n_fir; ++m) out[m] = make_float2((float)hr[m], (float)hi[m]);
+}
+
 }  // namespace dbp
 
 using namespace dbp;
@@ -282,6 +382,25 @@ dbp_status dbp_choose_geometry(const dbp_desc* desc, int32_t* block, int32_t* ov
     return DBP_OK;
 }
 
+dbp_status dbp_fir_taps(const dbp_desc* desc, int32_t step, float* out) {
+    dbp_status st = validate(desc);
+    if (st != DBP_OK) return st;
+    if (!out || desc->linear != DBP_LINEAR_FIR || desc->fir) return DBP_ERR_INVALID_ARG;
+    std::vector<double> vb, vp;
+    build_schedule(desc, vb, vp);
+    if (step < 0 || step >= (int32_t)vb.size()) return DBP_ERR_INVALID_ARG;
+    std::vector<float2> h(desc->n_fir);
+    if (desc->fir_band_thz > 0)
+        ls_fir(desc->n_fir, vb[step], desc->fs_thz, desc->fir_band_thz, h.data());
+    else
+        ideal_fir(desc->n_fir, vb[step], desc->fs_thz, h.data());
+    for (int m = 0; m < desc->n_fir; ++m) {
+        out[2 * m] = h[m].x;
+        out[2 * m + 1] = h[m].y;
+    }
+    return DBP_OK;
+}
+
 dbp_status dbp_plan(const dbp_desc* desc, dbp_plan_t* out) {
     if (!out) return DBP_ERR_INVALID_ARG;
     *out = nullptr;
@@ -302,8 +421,32 @@ dbp_status dbp_plan(const dbp_desc* desc, dbp_plan_t* out) {
     const int ns = p->geo.n_steps;
     const int nb = p->geo.block;
     const bool fp64 = desc->precision != DBP_FP32;
-    p->launch = (void*)find_kernel(nb, p->geo.e, desc->n_pol, fp64);
+    const bool fir_mode = desc->linear == DBP_LINEAR_FIR;
+    if (!fir_mode)
+        p->launch = (void*)find_kernel(nb, p->geo.e, desc->n_pol, fp64, tap_variant(desc->method, desc->n_taps));
 
+    std::vector<float2> fir;
+    if (fir_mode) {
+        const int nf = desc->n_fir;
+        fir.resize((size_t)ns * nf);
+        std::map<double, int> done;
+        for (int s = 0; s < ns; ++s) {
+            if (desc->fir) {
+                const float* src = desc->fir + 2 * (desc->fir_per_step ? (size_t)s * nf : 0);
+                for (int m = 0; m < nf; ++m) fir[(size_t)s * nf + m] = make_float2(src[2 * m], src[2 * m + 1]);
+            } else if (done.count(p->b[s])) {
+                const int s0 = done[p->b[s]];
+                std::copy(fir.begin() + (size_t)s0 * nf, fir.begin() + (size_t)(s0 + 1) * nf,
+                          fir.begin() + (size_t)s * nf);
+            } else {
+                if (desc->fir_band_thz > 0)
+                    ls_fir(nf, p->b[s], desc->fs_thz, desc->fir_band_thz, fir.data() + (size_t)s * nf);
+                else
+                    ideal_fir(nf, p->b[s], desc->fs_thz, fir.data() + (size_t)s * nf);
+                done[p->b[s]] = s;
+            }
+        }
+    }
     // distinct dispersion steps share one table
     std::vector<float2> htab;
     std::map<double, int> seen;
@@ -313,8 +456,10 @@ dbp_status dbp_plan(const dbp_desc* desc, dbp_plan_t* out) {
         int off;
         if (it == seen.end()) {
             off = (int)htab.size();
-            htab.resize(htab.size() + nb);
-            dispersion_table(nb, p->b[s], desc->fs_thz, fp64, htab.data() + off);
+            if (!fir_mode) {
+                htab.resize(htab.size() + nb);
+                dispersion_table(nb, p->b[s], desc->fs_thz, fp64, htab.data() + off);
+            }
             seen[p->b[s]] = off;
         } else {
             off = it->second;
@@ -324,7 +469,7 @@ dbp_status dbp_plan(const dbp_desc* desc, dbp_plan_t* out) {
         steps[s].phi64 = p->phi[s];
     }
     std::vector<float2> tw;
-    twiddle_table(nb, tw);
+    if (!fir_mode) twiddle_table(nb, tw);
     std::vector<float> taps;
     if (desc->method == DBP_ESSFM) {
         const int nt = desc->n_taps;
@@ -349,7 +494,8 @@ dbp_status dbp_plan(const dbp_desc* desc, dbp_plan_t* out) {
     if ((st = upload((void**)&p->d_h, htab.data(), htab.size() * sizeof(float2))) != DBP_OK ||
         (st = upload((void**)&p->d_tw, tw.data(), tw.size() * sizeof(float2))) != DBP_OK ||
         (st = upload((void**)&p->d_steps, steps.data(), steps.size() * sizeof(StepDev))) != DBP_OK ||
-        (st = upload((void**)&p->d_taps, taps.data(), taps.size() * sizeof(float))) != DBP_OK) {
+        (st = upload((void**)&p->d_taps, taps.data(), taps.size() * sizeof(float))) != DBP_OK ||
+        (st = upload((void**)&p->d_fir, fir.data(), fir.size() * sizeof(float2))) != DBP_OK) {
         dbp_destroy(p);
         return st;
     }
@@ -364,6 +510,7 @@ void dbp_destroy(dbp_plan_t p) {
     if (p->d_tw) (void)hipFree(p->d_tw);
     if (p->d_steps) (void)hipFree(p->d_steps);
     if (p->d_taps) (void)hipFree(p->d_taps);
+    if (p->d_fir) (void)hipFree(p->d_fir);
     delete p;
 }
 
@@ -378,10 +525,59 @@ dbp_status dbp_plan_geometry(dbp_plan_t p, int32_t* block, int32_t* overlap, int
     return DBP_OK;
 }
 
+}  // extern "C"
+
+namespace dbp {
+
+static constexpr int kCheckpointEvery = 8;
+
+// Time-domain geometry of a FIR-mode plan.
+struct FirGeo {
+    int n_tiles, n_wg, nw, width, n_ckpt, seg;
+};
+
+static FirGeo fir_geo(const Plan* p) {
+    FirGeo f;
+    f.n_tiles = (int)((p->desc.n_samples + FT_TS - 1) / FT_TS);
+    f.n_wg = f.n_tiles * p->desc.batch;
+    f.nw = p->desc.method == DBP_ESSFM ? p->desc.n_taps : 0;
+    f.width = f.nw + 2 * p->desc.n_fir;
+    f.seg = kCheckpointEvery;
+    f.n_ckpt = (p->geo.n_steps + f.seg - 1) / f.seg;
+    return f;
+}
+
+// Workspace of the checkpointed gradient: checkpoints 1.., the inputs of the
+// steps 1.. of one segment, two gradient buffers, then the per-tile partials.
+static size_t grad_ws_bytes(const Plan* p) {
+    const FirGeo f = fir_geo(p);
+    const size_t state = p->state_bytes();
+    const size_t part = (size_t)p->geo.n_steps * f.n_wg * f.width * sizeof(float);
+    return (size_t)(f.n_ckpt - 1 + f.seg - 1 + 2) * state + part;
+}
+
+static FirArgs fir_args(const Plan* p, int s, const float* taps, const void* fir) {
+    FirArgs a{};
+    const FirGeo f = fir_geo(p);
+    a.L = p->desc.n_samples;
+    a.n_tiles = f.n_tiles;
+    a.n_wg = f.n_wg;
+    a.nfir = p->desc.n_fir;
+    a.h = (fir ? (const float2*)fir : p->d_fir) + (size_t)s * a.nfir;
+    a.ntaps = p->desc.method == DBP_ESSFM ? p->desc.n_taps : 1;
+    a.w = p->desc.method == DBP_ESSFM ? (taps ? taps : p->d_taps) + (size_t)s * a.ntaps : nullptr;
+    a.phi = (float)p->phi[s];
+    return a;
+}
+
+}  // namespace dbp
+
+extern "C" {
+
 size_t dbp_workspace_size(dbp_plan_t p, int32_t grad) {
     if (!p) return 0;
     const size_t state = p->state_bytes();
-    if (grad) return 0;   // the gradient path is not built yet
+    if (grad) return p->desc.linear == DBP_LINEAR_FIR ? grad_ws_bytes(p) : 0;
     return p->geo.n_passes == 1 ? state : 2 * state;
 }
 
@@ -399,10 +595,32 @@ dbp_status dbp_backprop(dbp_plan_t p, const void* in, void* out, const float* ta
     if (hipGetDevice(&dev) != hipSuccess) return DBP_ERR_HIP;
     if (dev != p->device) return DBP_ERR_INVALID_ARG;
     hipStream_t s = (hipStream_t)stream;
+    const Geometry& g = p->geo;
+    float2* w0 = (float2*)ws;
+    float2* w1 = ws ? (float2*)((char*)ws + state) : nullptr;
+    const bool inplace = in == out;
+    if (p->desc.linear == DBP_LINEAR_FIR) {
+        const float2* src = (const float2*)in;
+        const int P = g.n_steps;
+        for (int st = 0; st < P; ++st) {
+            float2* dst;
+            if (P == 1) dst = inplace ? w0 : (float2*)out;
+            else if (st == 0 && inplace) dst = w1;
+            else dst = ((P - 1 - st) % 2 == 0) ? (float2*)out : w0;
+            FirArgs a = fir_args(p, st, taps, fir);
+            a.x = src;
+            a.z = dst;
+            if (launch_fir_step(p->desc.n_pol, a, s) != hipSuccess) return DBP_ERR_HIP;
+            src = dst;
+        }
+        if (P == 1 && inplace &&
+            hipMemcpyAsync(out, w0, state, hipMemcpyDeviceToDevice, s) != hipSuccess)
+            return DBP_ERR_HIP;
+        return DBP_OK;
+    }
     LaunchFn fn = (LaunchFn)p->launch;
     if (!fn) return DBP_ERR_UNSUPPORTED;
 
-    const Geometry& g = p->geo;
     PassArgs a{};
     a.L = p->desc.n_samples;
     a.V = g.block - g.overlap;
@@ -415,10 +633,7 @@ dbp_status dbp_backprop(dbp_plan_t p, const void* in, void* out, const float* ta
     a.taps = p->desc.method == DBP_ESSFM ? (taps ? taps : p->d_taps) : nullptr;
     a.ntaps = p->desc.method == DBP_ESSFM ? p->desc.n_taps : 1;
 
-    float2* w0 = (float2*)ws;
-    float2* w1 = ws ? (float2*)((char*)ws + state) : nullptr;
     const int P = g.n_passes;
-    const bool inplace = in == out;
     const float2* src = (const float2*)in;
     for (int pass = 0; pass < P; ++pass) {
         float2* dst;
@@ -445,10 +660,70 @@ dbp_status dbp_backprop(dbp_plan_t p, const void* in, void* out, const float* ta
 dbp_status dbp_backprop_grad(dbp_plan_t p, const void* in, const float* taps, const void* fir,
                              const void* grad_out, void* grad_in, float* grad_taps, void* grad_fir,
                              void* ws, size_t ws_bytes, void* stream) {
-    (void)in; (void)taps; (void)fir; (void)grad_out; (void)grad_in; (void)grad_taps;
-    (void)grad_fir; (void)ws; (void)ws_bytes; (void)stream;
-    if (!p) return DBP_ERR_INVALID_ARG;
-    return DBP_ERR_UNSUPPORTED;
+    if (!p || !in || !grad_out) return DBP_ERR_INVALID_ARG;
+    if (p->desc.linear != DBP_LINEAR_FIR) return DBP_ERR_UNSUPPORTED;
+    const size_t state = p->state_bytes();
+    const char* go = (const char*)grad_out;
+    const char* gi = (const char*)grad_in;
+    if (grad_in && gi < go + state && go < gi + state) return DBP_ERR_INVALID_ARG;
+    const size_t need = grad_ws_bytes(p);
+    if (!ws || ws_bytes < need) return DBP_ERR_WORKSPACE;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return DBP_ERR_HIP;
+    if (dev != p->device) return DBP_ERR_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    const FirGeo f = fir_geo(p);
+    const int ns = p->geo.n_steps;
+    const int npol = p->desc.n_pol;
+    char* w = (char*)ws;
+    auto buf = [&](int i) { return (float2*)(w + (size_t)i * state); };
+    // layout: [0, n_ckpt-1) checkpoints 1..; [n_ckpt-1, +seg-1) segment inputs; 2 gradient buffers
+    const int b_seg = f.n_ckpt - 1, b_grad = b_seg + f.seg - 1;
+    float* part = (float*)(w + (size_t)(b_grad + 2) * state);
+    auto ckpt = [&](int c) { return c == 0 ? (const float2*)in : (const float2*)buf(c - 1); };
+
+    // forward with a checkpoint every f.seg steps (the state after the last step is not needed)
+    {
+        const float2* src = (const float2*)in;
+        int tog = 0;
+        for (int st = 0; st + 1 < ns; ++st) {
+            float2* dst = ((st + 1) % f.seg == 0) ? buf((st + 1) / f.seg - 1) : buf(b_seg + (tog ^= 1));
+            FirArgs a = fir_args(p, st, taps, fir);
+            a.x = src;
+            a.z = dst;
+            if (launch_fir_step(npol, a, s) != hipSuccess) return DBP_ERR_HIP;
+            src = dst;
+        }
+    }
+    // reverse: recompute each segment's step inputs from its checkpoint, then run its adjoint steps
+    float2* gfinal = grad_in ? (float2*)grad_in : buf(b_grad + 1);
+    const float2* gcur = (const float2*)grad_out;
+    int r = 0;
+    for (int c = f.n_ckpt - 1; c >= 0; --c) {
+        const int s0 = c * f.seg, len = std::min(f.seg, ns - s0);
+        for (int j = 1; j < len; ++j) {
+            FirArgs a = fir_args(p, s0 + j - 1, taps, fir);
+            a.x = j == 1 ? ckpt(c) : buf(b_seg + j - 2);
+            a.z = buf(b_seg + j - 1);
+            if (launch_fir_step(npol, a, s) != hipSuccess) return DBP_ERR_HIP;
+        }
+        for (int j = len - 1; j >= 0; --j, ++r) {
+            FirArgs a = fir_args(p, s0 + j, taps, fir);
+            a.x = j == 0 ? ckpt(c) : buf(b_seg + j - 1);
+            a.gz = gcur;
+            float2* gdst = ((ns - 1 - r) % 2 == 0) ? gfinal : buf(b_grad + (gfinal == buf(b_grad + 1) ? 0 : 1));
+            a.z = gdst;
+            a.part = part + (size_t)(s0 + j) * f.n_wg * f.width;
+            if (launch_fir_adjoint(npol, a, s) != hipSuccess) return DBP_ERR_HIP;
+            gcur = gdst;
+        }
+    }
+    if ((grad_taps && f.nw) || grad_fir) {
+        if (launch_reduce_partials(part, ns, f.n_wg, f.nw, p->desc.n_fir, f.nw ? grad_taps : nullptr,
+                                   (float*)grad_fir, s) != hipSuccess)
+            return DBP_ERR_HIP;
+    }
+    return DBP_OK;
 }
 
 dbp_status dbp_plan_batch(const dbp_desc* descs, int32_t n, dbp_plan_t* out) {

@@ -9,8 +9,8 @@
 // X[t + T*q] in register q: forward output and inverse input share one layout
 // (frequency bins in natural order) and the inverse output is back in the
 // load/store layout.  Only the NB/R-strided Stockham writes between passes go
-// through LDS, padded by one complex every E to keep the strided writes free
-// of bank conflicts.
+// through LDS, with an XOR swizzle of the addresses that keeps the strided
+// writes and reads free of bank conflicts.
 //
 // Forward:  X_k = sum_n x_n exp(-2 pi i k n / NB)   (unscaled)
 // Inverse:  x_n = sum_k X_k exp(+2 pi i k n / NB)   (unscaled; 1/NB lives in
@@ -159,9 +159,11 @@ template <int NB, int E> struct FftShape {
     static constexpr int tw_off(int p) { return p == 0 ? 0 : tw_off(p - 1) + n_tw(p - 1); }
     static constexpr int NTW = tw_off(P);
     static constexpr int NTW_ALLOC = NTW > 0 ? NTW : 1;
-    // padded LDS position: one complex of padding every E complex
-    static __device__ __forceinline__ int pad(int i) { return i + (i >> LOGE); }
-    static constexpr int PADDED = NB + NB / E;
+    // LDS position of element i: the low five bits XORed with the five bits
+    // above log2(E), a bijection on [0, NB) that spreads both the NB/R-strided
+    // Stockham writes and the T-strided reads over all banks
+    static __device__ __forceinline__ int pad(int i) { return i ^ ((i >> LOGE) & 31); }
+    static constexpr int PADDED = NB;
 };
 
 template <int NB, int E> using TwReg = float2[FftShape<NB, E>::NTW_ALLOC];
@@ -195,14 +197,28 @@ __device__ __forceinline__ void load_twiddles(TwReg<NB, E>& twr,
     }(std::make_integer_sequence<int, S::P>{});
 }
 
-// One Stockham pass on NPOL polarizations.  lds holds NPOL padded blocks.
-template <int NB, int E, int NPOL, bool INV, int PASS>
+// Exchange buffers: a block of NPOL padded arrays per buffer.  Multi-wave
+// blocks alternate two buffers when both fit in 64 KiB, so that one barrier
+// per exchange suffices (a buffer is rewritten only after the barrier of the
+// following exchange, which every thread reaches after its reads of the
+// buffer); larger blocks use one buffer and a second barrier after the reads.
+// Single-wave blocks execute their LDS operations in order and use one buffer.
+template <int NB, int E, int NPOL> struct Exchange {
+    using S = FftShape<NB, E>;
+    static constexpr bool MULTIWAVE = S::T > 64;
+    static constexpr int NBUF = (MULTIWAVE && 2 * NPOL * S::PADDED * 8 <= 65536) ? 2 : 1;
+    static constexpr bool WAR_BARRIER = MULTIWAVE && NBUF == 1;
+    static constexpr int FLOATS2 = NBUF * NPOL * S::PADDED;     // float2 elements of LDS
+};
+
+// One Stockham pass on NPOL polarizations; BUF selects the exchange buffer.
+template <int NB, int E, int NPOL, bool INV, int PASS, int BUF>
 __device__ __forceinline__ void fft_pass(float2 (&v)[NPOL][E], float2* __restrict__ lds,
-                                         const TwReg<NB, E>& twr,
-                                         int t) {
+                                         const TwReg<NB, E>& twr, int t) {
     using S = FftShape<NB, E>;
     constexpr int R = S::radix(PASS), LS = S::ls(PASS), M = E / R, T = S::T;
     constexpr bool LAST = PASS == S::P - 1;
+    float2* __restrict__ buf = lds + BUF * NPOL * S::PADDED;
 #pragma unroll
     for (int m = 0; m < M; ++m) {
         const int j = t + m * T;
@@ -227,7 +243,7 @@ __device__ __forceinline__ void fft_pass(float2 (&v)[NPOL][E], float2* __restric
 #pragma unroll
                 for (int s = 0; s < R; ++s) v[p][m + s * M] = a[s];
             } else {
-                float2* dst = lds + p * S::PADDED;
+                float2* dst = buf + p * S::PADDED;
                 const int base = (j - k) * R + k;
 #pragma unroll
                 for (int s = 0; s < R; ++s) dst[S::pad(base + s * LS)] = a[s];
@@ -239,21 +255,24 @@ __device__ __forceinline__ void fft_pass(float2 (&v)[NPOL][E], float2* __restric
 #pragma unroll
         for (int p = 0; p < NPOL; ++p)
 #pragma unroll
-            for (int q = 0; q < E; ++q) v[p][q] = lds[p * S::PADDED + S::pad(t + T * q)];
-        if constexpr (T > 64) __syncthreads();   // all reads done before the next pass writes
+            for (int q = 0; q < E; ++q) v[p][q] = buf[p * S::PADDED + S::pad(t + T * q)];
+        if constexpr (Exchange<NB, E, NPOL>::WAR_BARRIER) __syncthreads();
     }
 }
 
 // Full NB-point transform of every polarization; data in and out in the
-// thread-strided layout (register q <-> index t + T q).  The caller must make
-// sure no thread still reads lds when this starts (T > 64).
+// thread-strided layout (register q <-> index t + T q).  Exchange j of the
+// transform uses buffer (j + PAR0) mod NBUF.  The forward transform starts at
+// parity 0 and the inverse at parity P-1, so consecutive transforms never
+// reuse the buffer the previous exchange just read.
 template <int NB, int E, int NPOL, bool INV>
 __device__ __forceinline__ void block_fft(float2 (&v)[NPOL][E], float2* __restrict__ lds,
-                                          const TwReg<NB, E>& twr,
-                                          int t) {
+                                          const TwReg<NB, E>& twr, int t) {
     using S = FftShape<NB, E>;
+    constexpr int NBUF = Exchange<NB, E, NPOL>::NBUF;
+    constexpr int PAR0 = INV ? (S::P - 1) : 0;
     [&]<int... Ps>(std::integer_sequence<int, Ps...>) {
-        (fft_pass<NB, E, NPOL, INV, Ps>(v, lds, twr, t), ...);
+        (fft_pass<NB, E, NPOL, INV, Ps, (Ps + PAR0) % NBUF>(v, lds, twr, t), ...);
     }(std::make_integer_sequence<int, S::P>{});
 }
 

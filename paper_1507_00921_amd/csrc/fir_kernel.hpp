@@ -1,0 +1,300 @@
+// Time-domain split step and its adjoint, for the learnable-dispersion
+// variant: the linear substep of Sec. II applied as a complex FIR h (the
+// centre taps of the impulse response of Eq. (1), or learned values) instead
+// of the FFT filter, followed by the (E)SSFM nonlinear substep of Eqs. (2)-(3).
+//
+// Both kernels work on tiles of FT_TS consecutive samples of every
+// polarization, circular over the signal.  A tile loads its input with the
+// halo the step needs (h spans +-HF samples, the tap filter w +-NC), so tiled
+// results equal the whole-signal step up to rounding.
+//
+// Conventions: u[n] = sum_m h[m] x[n - (m - HF)], J[n] = sum_m w[m] I[n - (m - NC)],
+// z = u exp(-j phi J).  Gradients: g = dL/dRe + j dL/dIm.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "fft.hpp"
+#include "step_kernel.hpp"
+
+namespace dbp {
+
+constexpr int FT_THREADS = 256;
+constexpr int FT_TS = 1024;       // output samples per tile
+constexpr int FT_MAXH = 64;       // largest FIR half-width
+constexpr int FT_MAXC = 64;       // largest tap half-width
+
+struct FirArgs {
+    const float2* x;        // step input [n_sig][NPOL][L]
+    float2* z;              // step output (forward) or input gradient (adjoint)
+    const float2* gz;       // adjoint: gradient at the step output
+    long long L;
+    int n_tiles;            // tiles per signal
+    int n_wg;               // n_tiles * n_sig
+    const float2* h;        // this step's FIR taps [nfir]
+    int nfir;
+    const float* w;         // this step's intensity taps [ntaps], nullptr for SSFM
+    int ntaps;
+    float phi;
+    float* part;            // adjoint: per-tile partial gradients [n_wg][ntaps + 2 nfir]
+};
+
+__device__ __forceinline__ long long wrap(long long i, long long L) {
+    i %= L;
+    return i < 0 ? i + L : i;
+}
+
+// Load x[(base + i) mod L], i < n, of every polarization into s[p][i] (row stride n).
+template <int NPOL>
+__device__ __forceinline__ void load_tile(float2* s, const float2* __restrict__ x, long long base, int n,
+                                          long long L) {
+    for (int i = threadIdx.x; i < n; i += FT_THREADS) {
+        const long long g = wrap(base + i, L);
+#pragma unroll
+        for (int p = 0; p < NPOL; ++p) s[p * n + i] = x[p * L + g];
+    }
+}
+
+// u over n_out positions: u[i] = sum_m h[m] xs[i + 2 HF - m] (xs row stride nx),
+// and the total intensity I[i].
+template <int NPOL>
+__device__ __forceinline__ void fir_u(float2* us, float* is, const float2* xs, int nx, int n_out,
+                                      const float2* hs, int nfir) {
+    const int hf2 = nfir - 1;
+    for (int i = threadIdx.x; i < n_out; i += FT_THREADS) {
+        float in = 0.f;
+#pragma unroll
+        for (int p = 0; p < NPOL; ++p) {
+            float2 acc = make_float2(0.f, 0.f);
+            const float2* xr = xs + p * nx + i + hf2;
+            for (int m = 0; m < nfir; ++m) {
+                const float2 hv = hs[m];
+                const float2 xv = xr[-m];
+                acc.x = fmaf(hv.x, xv.x, fmaf(-hv.y, xv.y, acc.x));
+                acc.y = fmaf(hv.x, xv.y, fmaf(hv.y, xv.x, acc.y));
+            }
+            us[p * n_out + i] = acc;
+            in = fmaf(acc.x, acc.x, fmaf(acc.y, acc.y, in));
+        }
+        is[i] = in;
+    }
+}
+
+// J[i] = sum_m w[m] I[i + 2 NC - m] over n_out positions (SSFM: J = I shifted by NC).
+__device__ __forceinline__ void tap_filter(float* js, const float* is, int n_out, const float* ws, int ntaps) {
+    const int c2 = ntaps - 1;
+    for (int i = threadIdx.x; i < n_out; i += FT_THREADS) {
+        float acc = 0.f;
+        if (ws) {
+            for (int m = 0; m < ntaps; ++m) acc = fmaf(ws[m], is[i + c2 - m], acc);
+        } else {
+            acc = is[i];
+        }
+        js[i] = acc;
+    }
+}
+
+// Forward step on one tile: out[a + o] for o < FT_TS.
+template <int NPOL>
+__global__ __launch_bounds__(FT_THREADS) void fir_step_kernel(FirArgs a) {
+    extern __shared__ float4 smem4[];
+    char* smem = reinterpret_cast<char*>(smem4);
+    const int HF = (a.nfir - 1) / 2;
+    const int NC = a.w ? (a.ntaps - 1) / 2 : 0;
+    const int nx = FT_TS + 2 * (HF + NC);     // x on [a0 - HF - NC, a0 + TS + HF + NC)
+    const int nu = FT_TS + 2 * NC;            // u, I on [a0 - NC, a0 + TS + NC)
+    float2* hs = reinterpret_cast<float2*>(smem);
+    float* wsm = reinterpret_cast<float*>(hs + 2 * FT_MAXH + 1);
+    float2* xs = reinterpret_cast<float2*>(wsm + 2 * FT_MAXC + 2);
+    float2* us = xs + NPOL * nx;
+    float* is = reinterpret_cast<float*>(us + NPOL * nu);
+
+    const int wg = xcd_remap(blockIdx.x, a.n_wg);
+    const int sig = wg / a.n_tiles;
+    const int tile = wg - sig * a.n_tiles;
+    const long long L = a.L;
+    const long long a0 = (long long)tile * FT_TS;
+    const float2* __restrict__ x = a.x + (long long)sig * NPOL * L;
+    float2* __restrict__ z = a.z + (long long)sig * NPOL * L;
+
+    for (int i = threadIdx.x; i < a.nfir; i += FT_THREADS) hs[i] = a.h[i];
+    if (a.w)
+        for (int i = threadIdx.x; i < a.ntaps; i += FT_THREADS) wsm[i] = a.w[i];
+    load_tile<NPOL>(xs, x, a0 - HF - NC, nx, L);
+    __syncthreads();
+    fir_u<NPOL>(us, is, xs, nx, nu, hs, a.nfir);
+    __syncthreads();
+    for (int o = threadIdx.x; o < FT_TS; o += FT_THREADS) {
+        if (a0 + o >= L) break;
+        float j = 0.f;
+        if (a.w) {
+            for (int m = 0; m < a.ntaps; ++m) j = fmaf(wsm[m], is[o + 2 * NC - m], j);
+        } else {
+            j = is[o];
+        }
+        float sn, cs;
+        sincosf(-a.phi * j, &sn, &cs);
+#pragma unroll
+        for (int p = 0; p < NPOL; ++p) z[p * L + a0 + o] = cmul(us[p * nu + o + NC], make_float2(cs, sn));
+    }
+}
+
+// Adjoint of one step on one tile: g_x[a0 + o] for o < FT_TS, plus this tile's
+// partial sums of dL/dw (owned outputs n in [a0, a0 + TS)) and dL/dh.
+template <int NPOL>
+__global__ __launch_bounds__(FT_THREADS) void fir_adjoint_kernel(FirArgs a) {
+    extern __shared__ float4 smem4[];
+    char* smem = reinterpret_cast<char*>(smem4);
+    const int HF = (a.nfir - 1) / 2;
+    const int NC = a.w ? (a.ntaps - 1) / 2 : 0;
+    const int nx = FT_TS + 4 * HF + 4 * NC;   // x on [a0 - 2HF - 2NC, ...)
+    const int nu = FT_TS + 2 * HF + 4 * NC;   // u, I on [a0 - HF - 2NC, ...)
+    const int nz = FT_TS + 2 * HF + 2 * NC;   // J, g_z, Jbar on [a0 - HF - NC, ...)
+    const int ng = FT_TS + 2 * HF;            // g_u on [a0 - HF, ...)
+    float2* hs = reinterpret_cast<float2*>(smem);
+    float* wsm = reinterpret_cast<float*>(hs + 2 * FT_MAXH + 1);
+    float2* xs = reinterpret_cast<float2*>(wsm + 2 * FT_MAXC + 2);
+    float2* us = xs + NPOL * nx;
+    float2* gzs = us + NPOL * nu;              // g_z, then g_u in place
+    float* is = reinterpret_cast<float*>(gzs + NPOL * nz);
+    float* js = is + nu;
+    float* jb = js + nz;
+    float* red = jb + nz;                      // [4 waves][64] partial sums
+
+    const int t = threadIdx.x;
+    const int wg = xcd_remap(blockIdx.x, a.n_wg);
+    const int sig = wg / a.n_tiles;
+    const int tile = wg - sig * a.n_tiles;
+    const long long L = a.L;
+    const long long a0 = (long long)tile * FT_TS;
+    const float2* __restrict__ x = a.x + (long long)sig * NPOL * L;
+    const float2* __restrict__ gz = a.gz + (long long)sig * NPOL * L;
+    float2* __restrict__ gx = a.z + (long long)sig * NPOL * L;
+
+    for (int i = t; i < a.nfir; i += FT_THREADS) hs[i] = a.h[i];
+    if (a.w)
+        for (int i = t; i < a.ntaps; i += FT_THREADS) wsm[i] = a.w[i];
+    load_tile<NPOL>(xs, x, a0 - 2 * HF - 2 * NC, nx, L);
+    load_tile<NPOL>(gzs, gz, a0 - HF - NC, nz, L);
+    __syncthreads();
+    // recompute the step: u and I on the u range, J on the z range
+    fir_u<NPOL>(us, is, xs, nx, nu, hs, a.nfir);
+    __syncthreads();
+    tap_filter(js, is, nz, a.w ? wsm : nullptr, a.ntaps);
+    __syncthreads();
+    // Jbar = phi sum_p Im(conj(g_z) z), z = u exp(-j phi J), on the z range
+    for (int i = t; i < nz; i += FT_THREADS) {
+        float sn, cs;
+        sincosf(-a.phi * js[i], &sn, &cs);
+        float acc = 0.f;
+#pragma unroll
+        for (int p = 0; p < NPOL; ++p) {
+            const float2 zz = cmul(us[p * nu + i + NC], make_float2(cs, sn));
+            const float2 g = gzs[p * nz + i];
+            acc = fmaf(g.x, zz.y, fmaf(-g.y, zz.x, acc));
+        }
+        jb[i] = a.phi * acc;
+    }
+    __syncthreads();
+    // g_u = g_z exp(+j phi J) + 2 Ibar u on the g range, Ibar = w^T (*) Jbar
+    for (int i = t; i < ng; i += FT_THREADS) {
+        const int iz = i + NC;                 // position in the z range
+        float ib = 0.f;
+        if (a.w) {
+            for (int m = 0; m < a.ntaps; ++m) ib = fmaf(wsm[m], jb[iz + m - NC], ib);
+        } else {
+            ib = jb[iz];
+        }
+        float sn, cs;
+        sincosf(a.phi * js[iz], &sn, &cs);
+        float2 gu[NPOL];
+#pragma unroll
+        for (int p = 0; p < NPOL; ++p) {
+            const float2 uu = us[p * nu + iz + NC];
+            const float2 g = cmul(gzs[p * nz + iz], make_float2(cs, sn));
+            gu[p] = make_float2(fmaf(2.f * ib, uu.x, g.x), fmaf(2.f * ib, uu.y, g.y));
+        }
+        // in place: this iteration alone reads and writes position iz of gzs
+#pragma unroll
+        for (int p = 0; p < NPOL; ++p) gzs[p * nz + iz] = gu[p];
+    }
+    __syncthreads();
+    // input gradient: g_x[o] = sum_m conj(h[m]) g_u[o + m - HF]
+    for (int o = t; o < FT_TS; o += FT_THREADS) {
+        if (a0 + o >= L) break;
+#pragma unroll
+        for (int p = 0; p < NPOL; ++p) {
+            float2 acc = make_float2(0.f, 0.f);
+            const float2* gr = gzs + p * nz + NC + o;     // g_u at o - HF is gzs[p][NC + o]
+            for (int m = 0; m < a.nfir; ++m) {
+                const float2 hv = hs[m];
+                const float2 g = gr[m];
+                acc.x = fmaf(hv.x, g.x, fmaf(hv.y, g.y, acc.x));
+                acc.y = fmaf(hv.x, g.y, fmaf(-hv.y, g.x, acc.y));
+            }
+            gx[p * L + a0 + o] = acc;
+        }
+    }
+    // parameter partials over owned outputs n = a0 + o, o < min(TS, L - a0):
+    // parameter l (chunks of 64, one per lane) is summed by each of the 4 waves
+    // over a quarter of the outputs, then the 4 quarters are added in order:
+    //   l < nfir:            dL/dh[l] = sum g_u[n] conj(x[n - (l - HF)])
+    //   nfir <= l < nfir+nw: dL/dw[l - nfir] = sum Jbar[n] I[n - (l - nfir - NC)]
+    const int lane = t & 63, q = t >> 6;
+    const int n_own = (int)min((long long)FT_TS, L - a0);
+    const int per = (n_own + 3) / 4;
+    const int o0 = q * per, o1 = min(n_own, o0 + per);
+    const int nw = a.w ? a.ntaps : 0;
+    float* part = a.part + (long long)wg * (nw + 2 * a.nfir);
+    for (int pb = 0; pb < a.nfir + nw; pb += 64) {
+        const int l = pb + lane;
+        float2 acc = make_float2(0.f, 0.f);
+        if (l < a.nfir) {
+            for (int o = o0; o < o1; ++o) {
+#pragma unroll
+                for (int p = 0; p < NPOL; ++p) {
+                    const float2 g = gzs[p * nz + NC + HF + o];
+                    const float2 xv = xs[p * nx + o + 3 * HF + 2 * NC - l];
+                    acc.x = fmaf(g.x, xv.x, fmaf(g.y, xv.y, acc.x));
+                    acc.y = fmaf(g.y, xv.x, fmaf(-g.x, xv.y, acc.y));
+                }
+            }
+        } else if (l < a.nfir + nw) {
+            const int m = l - a.nfir;
+            for (int o = o0; o < o1; ++o) acc.x = fmaf(jb[o + HF + NC], is[o + HF + 3 * NC - m], acc.x);
+        }
+        __syncthreads();                       // previous chunk's sums have been read
+        red[(q * 64 + lane) * 2] = acc.x;
+        red[(q * 64 + lane) * 2 + 1] = acc.y;
+        __syncthreads();
+        if (q == 0) {
+            float sx = 0.f, sy = 0.f;
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                sx += red[(w * 64 + lane) * 2];
+                sy += red[(w * 64 + lane) * 2 + 1];
+            }
+            if (l < a.nfir) {
+                part[nw + 2 * l] = sx;
+                part[nw + 2 * l + 1] = sy;
+            } else if (l < a.nfir + nw) {
+                part[l - a.nfir] = sx;
+            }
+        }
+    }
+}
+
+inline size_t fir_fwd_smem(int npol, int nfir, int ntaps_or_0) {
+    const int HF = (nfir - 1) / 2, NC = ntaps_or_0 ? (ntaps_or_0 - 1) / 2 : 0;
+    const int nx = FT_TS + 2 * (HF + NC), nu = FT_TS + 2 * NC;
+    return (2 * FT_MAXH + 1) * 8 + (2 * FT_MAXC + 2) * 4 + (size_t)npol * nx * 8 + (size_t)npol * nu * 8 +
+           (size_t)nu * 4;
+}
+
+inline size_t fir_adj_smem(int npol, int nfir, int ntaps_or_0) {
+    const int HF = (nfir - 1) / 2, NC = ntaps_or_0 ? (ntaps_or_0 - 1) / 2 : 0;
+    const int nx = FT_TS + 4 * HF + 4 * NC, nu = FT_TS + 2 * HF + 4 * NC, nz = FT_TS + 2 * HF + 2 * NC;
+    return (2 * FT_MAXH + 1) * 8 + (2 * FT_MAXC + 2) * 4 + (size_t)npol * (nx + nu + nz) * 8 +
+           (size_t)(nu + 2 * nz) * 4 + 4 * 64 * 2 * 4;
+}
+
+}  // namespace dbp

@@ -1,0 +1,13 @@
+// Pass-kernel variants: DBP_K(1024, 16), DBP_K(1024, 4).
+#include "registry.hpp"
+
+namespace dbp {
+
+static const KernelEntry kTable[] = {DBP_K(1024, 16), DBP_K(1024, 4)};
+
+const KernelEntry* kernels_1024(int* n) {
+    *n = (int)(sizeof(kTable) / sizeof(kTable[0]));
+    return kTable;
+}
+
+}  // namespace dbp

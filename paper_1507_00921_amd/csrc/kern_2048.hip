@@ -1,0 +1,13 @@
+// Pass-kernel variants: DBP_K(2048, 16).
+#include "registry.hpp"
+
+namespace dbp {
+
+static const KernelEntry kTable[] = {DBP_K(2048, 16)};
+
+const KernelEntry* kernels_2048(int* n) {
+    *n = (int)(sizeof(kTable) / sizeof(kTable[0]));
+    return kTable;
+}
+
+}  // namespace dbp

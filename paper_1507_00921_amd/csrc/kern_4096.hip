@@ -1,0 +1,13 @@
+// Pass-kernel variants: DBP_K(4096, 16).
+#include "registry.hpp"
+
+namespace dbp {
+
+static const KernelEntry kTable[] = {DBP_K(4096, 16)};
+
+const KernelEntry* kernels_4096(int* n) {
+    *n = (int)(sizeof(kTable) / sizeof(kTable[0]));
+    return kTable;
+}
+
+}  // namespace dbp

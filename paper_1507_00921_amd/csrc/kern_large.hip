@@ -1,0 +1,13 @@
+// Pass-kernel variants: DBP_K(8192, 16), DBP_KP(16384, 16, 1).
+#include "registry.hpp"
+
+namespace dbp {
+
+static const KernelEntry kTable[] = {DBP_K(8192, 16), DBP_KP(16384, 16, 1)};
+
+const KernelEntry* kernels_large(int* n) {
+    *n = (int)(sizeof(kTable) / sizeof(kTable[0]));
+    return kTable;
+}
+
+}  // namespace dbp

@@ -1,0 +1,13 @@
+// Pass-kernel variants: DBP_K(256, 4), DBP_K(512, 8).
+#include "registry.hpp"
+
+namespace dbp {
+
+static const KernelEntry kTable[] = {DBP_K(256, 4), DBP_K(512, 8)};
+
+const KernelEntry* kernels_small(int* n) {
+    *n = (int)(sizeof(kTable) / sizeof(kTable[0]));
+    return kTable;
+}
+
+}  // namespace dbp

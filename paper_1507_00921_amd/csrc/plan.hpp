@@ -30,6 +30,7 @@ struct dbp_plan_s {
     float2* d_tw = nullptr;          // FFT twiddles
     dbp::StepDev* d_steps = nullptr;
     float* d_taps = nullptr;         // [N_s][n_taps]
+    float2* d_fir = nullptr;         // FIR linear step: [N_s][n_fir]
     std::vector<float> h_taps;
 
     size_t state_bytes() const {

@@ -1,0 +1,37 @@
+// Table of compiled pass-kernel variants.  Each kern_*.hip translation unit
+// instantiates the variants of some block sizes and exposes them through one
+// accessor, so the variants build in parallel.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "step_kernel.hpp"
+
+namespace dbp {
+
+using LaunchFn = hipError_t (*)(const PassArgs&, int grid, hipStream_t);
+
+struct KernelEntry {
+    int nb, e, npol;
+    bool p64;
+    int nt;          // compile-time taps: 0 SSFM, > 0 fixed, -1 run time
+    LaunchFn fn;
+};
+
+template <int NB, int E, int NPOL, bool P64, int NT>
+hipError_t launch_pass(const PassArgs& a, int grid, hipStream_t s) {
+    hipLaunchKernelGGL((dbp_pass_kernel<NB, E, NPOL, P64, NT>), dim3(grid), dim3(NB / E), 0, s, a);
+    return hipGetLastError();
+}
+
+#define DBP_KV(NB, E, NPOL, P64, NT) {NB, E, NPOL, P64, NT, launch_pass<NB, E, NPOL, P64, NT>}
+#define DBP_KT(NB, E, NPOL, P64) DBP_KV(NB, E, NPOL, P64, 0), DBP_KV(NB, E, NPOL, P64, 9), DBP_KV(NB, E, NPOL, P64, -1)
+#define DBP_KP(NB, E, NPOL) DBP_KT(NB, E, NPOL, false), DBP_KT(NB, E, NPOL, true)
+#define DBP_K(NB, E) DBP_KP(NB, E, 1), DBP_KP(NB, E, 2)
+
+const KernelEntry* kernels_small(int* n);
+const KernelEntry* kernels_1024(int* n);
+const KernelEntry* kernels_2048(int* n);
+const KernelEntry* kernels_4096(int* n);
+const KernelEntry* kernels_large(int* n);
+
+}  // namespace dbp

@@ -57,12 +57,20 @@ __device__ __forceinline__ float2 phase_factor(float j, const StepDev& st) {
     return make_float2(c, s);
 }
 
-template <int NB, int E, int NPOL, bool PHASE64>
+// NT: number of ESSFM taps known at compile time (0: SSFM, J = I; -1: taken
+// from a.ntaps at run time).
+template <int NB, int E, int NPOL, bool PHASE64, int NT>
 __global__ __launch_bounds__(NB / E) void dbp_pass_kernel(PassArgs a) {
     using S = FftShape<NB, E>;
+    using X = Exchange<NB, E, NPOL>;
     constexpr int T = S::T;
-    __shared__ float2 lds[NPOL * S::PADDED];
-    float* ilds = reinterpret_cast<float*>(lds);   // intensity, aliases the FFT exchange buffer
+    // intensity for the tap filter: its own array when two exchange buffers
+    // alternate (another wave may still read one of them), else the exchange
+    // buffer itself (single wave: in-order LDS; one buffer: fenced by barriers)
+    constexpr bool OWN_I = X::NBUF == 2 && NT != 0;
+    __shared__ float2 lds[X::FLOATS2];
+    __shared__ float ilds_own[OWN_I ? NB : 1];
+    float* ilds = OWN_I ? ilds_own : reinterpret_cast<float*>(lds);
 
     const int t = threadIdx.x;
     const int wg = xcd_remap(blockIdx.x, a.n_wg);
@@ -85,19 +93,28 @@ __global__ __launch_bounds__(NB / E) void dbp_pass_kernel(PassArgs a) {
     TwReg<NB, E> twr;
     load_twiddles<NB, E>(twr, a.tw, t);
 
-    const int c = (a.ntaps - 1) >> 1;
+    const int ntaps = NT >= 0 ? NT : a.ntaps;
+    const int c = (ntaps - 1) >> 1;
     for (int s = a.s0; s < a.s0 + a.ks; ++s) {
         const StepDev st = a.steps[s];
+        // issue this step's table and tap loads first: the forward FFT hides their latency
+        const float2* __restrict__ hs = a.H + st.h_off;
+        float2 h[E];
+#pragma unroll
+        for (int q = 0; q < E; ++q) h[q] = hs[t + T * q];
+        const float* __restrict__ w = a.taps + (long long)s * ntaps;
+        float wr[NT > 0 ? NT : 1];
+        if constexpr (NT > 0) {
+#pragma unroll
+            for (int m = 0; m < NT; ++m) wr[m] = w[m];
+        }
         // (i) forward FFT of both polarizations
         block_fft<NB, E, NPOL, false>(v, lds, twr, t);
         // (ii) dispersion, Eq. (1), with the inverse FFT's 1/Nb folded in
-        const float2* __restrict__ hs = a.H + st.h_off;
 #pragma unroll
-        for (int q = 0; q < E; ++q) {
-            const float2 h = hs[t + T * q];
+        for (int q = 0; q < E; ++q)
 #pragma unroll
-            for (int p = 0; p < NPOL; ++p) v[p][q] = cmul(v[p][q], h);
-        }
+            for (int p = 0; p < NPOL; ++p) v[p][q] = cmul(v[p][q], h[q]);
         // (iii) inverse FFT
         block_fft<NB, E, NPOL, true>(v, lds, twr, t);
         // (iv) nonlinear phase driven by the total intensity, Eqs. (2)-(3)
@@ -109,20 +126,27 @@ __global__ __launch_bounds__(NB / E) void dbp_pass_kernel(PassArgs a) {
             for (int p = 0; p < NPOL; ++p) in = fmaf(v[p][q].x, v[p][q].x, fmaf(v[p][q].y, v[p][q].y, in));
             J[q] = in;
         }
-        if (a.taps != nullptr) {
-            if constexpr (T > 64) __syncthreads();   // last FFT pass reads of lds are done
+        if constexpr (NT != 0) {
 #pragma unroll
             for (int q = 0; q < E; ++q) ilds[t + T * q] = J[q];
             __syncthreads();
-            const float* __restrict__ w = a.taps + (long long)s * a.ntaps;
 #pragma unroll
             for (int q = 0; q < E; ++q) J[q] = 0.f;
-            for (int m = 0; m < a.ntaps; ++m) {
-                const float wm = w[m];
+            if constexpr (NT > 0) {
 #pragma unroll
-                for (int q = 0; q < E; ++q) J[q] = fmaf(wm, ilds[(t + T * q - m + c) & (NB - 1)], J[q]);
+                for (int m = 0; m < NT; ++m)
+#pragma unroll
+                    for (int q = 0; q < E; ++q)
+                        J[q] = fmaf(wr[m], ilds[(t + T * q - m + c) & (NB - 1)], J[q]);
+            } else {
+                for (int m = 0; m < ntaps; ++m) {
+                    const float wm = w[m];
+#pragma unroll
+                    for (int q = 0; q < E; ++q) J[q] = fmaf(wm, ilds[(t + T * q - m + c) & (NB - 1)], J[q]);
+                }
             }
-            if constexpr (T > 64) __syncthreads();   // tap reads done before the next FFT writes lds
+            // the next exchange overwrites the aliased buffer: wait for every wave's reads
+            if constexpr (X::WAR_BARRIER) __syncthreads();
         }
 #pragma unroll
         for (int q = 0; q < E; ++q) {

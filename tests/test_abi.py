@@ -149,3 +149,16 @@ def test_geometry_rules():
     # whole-signal sizes without a kernel are refused as unsupported, not invalid
     d = _desc(n_samples=12288, whole=True)
     assert dbp.lib().dbp_choose_geometry(ctypes.byref(d), None, None, None) == 2
+
+
+@pytest.mark.parametrize("band", [0.0, 0.0154])
+def test_planner_fir_design_matches_oracle(band):
+    dbp = _lib_or_skip()
+    b2 = siggen.beta2_ps2_km()
+    d = _desc(n_spans=4, steps_per_span=2, linear=dbp.LINEAR_FIR, n_fir=33, fir_band_thz=band)
+    b = R.schedule(4, 80.0, 2, b2, 1.3, 0.2)[3].b
+    ref = R.ls_fir_taps(33, b, siggen.FS_THZ, band) if band > 0 else R.ideal_fir_taps(33, b, siggen.FS_THZ)
+    got = dbp.fir_taps(d, 3)
+    assert np.max(np.abs(got - ref)) < 1e-7 * max(1.0, np.max(np.abs(ref))) + 2e-8
+    with pytest.raises(dbp.DbpError):
+        dbp.fir_taps(d, 8)      # step out of range

@@ -168,3 +168,30 @@ def test_ideal_fir_taps_are_l2_optimal_truncation():
     h = R.ideal_fir_taps(33, b, FS)
     assert np.allclose(h, h[::-1], atol=1e-15)         # even impulse response (f^2 phase)
     assert 0.5 < np.sum(np.abs(h) ** 2) <= 1.0 + 1e-12  # all-pass: total energy 1 over all lags
+
+
+def test_ls_fir_full_band_is_truncated_impulse_response():
+    # with the whole grid in band and unit weight, the least-squares FIR on an N-point DFT grid
+    # is the centre of the N-point impulse response (orthogonality of the DFT basis)
+    b = -21.6826 * 80.0
+    for nt in [9, 33]:
+        a = R.ls_fir_taps(nt, b, FS, 1.0, n_grid=4096)
+        t = R.ideal_fir_taps(nt, b, FS, n_fft=4096)
+        assert np.max(np.abs(a - t)) < 1e-14
+
+
+def test_ls_fir_band_design_is_stable_and_close_in_band():
+    b = -21.6826 * 80.0
+    band = 0.0154
+    f = np.linspace(-FS / 2, FS / 2, 2001)
+    for h, gain_max, err_max in [(R.ls_fir_taps(33, b, FS, band), 1.01, 0.01),
+                                 (R.ideal_fir_taps(33, b, FS), 1.4, 0.1)]:
+        c = len(h) // 2
+        resp = np.exp(-2j * math.pi * np.outer(f / FS, np.arange(len(h)) - c)) @ h
+        inb = np.abs(f) <= band
+        err = np.sqrt(np.mean(np.abs(resp[inb] - np.exp(-1j * 2 * math.pi ** 2 * b * f[inb] ** 2)) ** 2))
+        assert np.abs(resp).max() < gain_max and err < err_max
+    # plain truncation of an 80 km response exceeds unit gain (a 40-step cascade would amplify)
+    h = R.ideal_fir_taps(33, b, FS)
+    resp = np.exp(-2j * math.pi * np.outer(f / FS, np.arange(33) - 16)) @ h
+    assert np.abs(resp).max() > 1.2
