@@ -194,11 +194,25 @@ dbp_status dbp_plan_batch(const dbp_desc* descs, int32_t n, dbp_plan_t* out);
  * buffer, host array of n + 1 entries (the last is the total). */
 dbp_status dbp_batch_offsets(dbp_plan_t plan, int64_t* offsets, int32_t n_plus_1);
 
+/* Geometry chosen for signal i of a batch plan (the autotuner measures the
+ * cost of each block size once per process and kernel variant, then picks
+ * for every signal the block, overlap and steps per pass of least modelled
+ * time; explicit block/overlap/steps_per_pass in a descriptor are kept). */
+dbp_status dbp_batch_geometry(dbp_plan_t plan, int32_t i, int32_t* block, int32_t* overlap,
+                              int32_t* steps_per_pass);
+
 /* Backpropagate every signal of a batch plan: in_packed -> out_packed (device
- * complex64, layout of dbp_batch_offsets; in == out allowed).  All passes of
- * all signals run in one persistent launch, replayed from a HIP graph. */
+ * complex64, layout of dbp_batch_offsets; in == out allowed).  ws_bytes >=
+ * dbp_workspace_size(plan, 0) (twice the packed size).  All passes of all
+ * signals run in one persistent launch per kernel variant, pass n+1 of a
+ * block waiting only on its neighbours' pass n, the launches captured once
+ * into a HIP graph (per in/out/ws triple) and replayed on `stream`. */
 dbp_status dbp_backprop_batch(dbp_plan_t plan, const void* in_packed, void* out_packed,
                               void* ws, size_t ws_bytes, void* stream);
+
+/* Synchronous: error flags of the last completed batch run (0: none; bit 0:
+ * a dependency wait exceeded its bound and the block was skipped). */
+dbp_status dbp_batch_status(dbp_plan_t plan, int32_t* flags);
 
 /* Short static description of a status code. */
 const char* dbp_status_string(dbp_status s);

@@ -84,6 +84,10 @@ def lib():
         L.dbp_batch_offsets.restype = c_int32
         L.dbp_backprop_batch.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]
         L.dbp_backprop_batch.restype = c_int32
+        L.dbp_batch_geometry.argtypes = [c_void_p, c_int32] + [POINTER(c_int32)] * 3
+        L.dbp_batch_geometry.restype = c_int32
+        L.dbp_batch_status.argtypes = [c_void_p, POINTER(c_int32)]
+        L.dbp_batch_status.restype = c_int32
         L.dbp_fir_taps.argtypes = [POINTER(Desc), c_int32, POINTER(c_float)]
         L.dbp_fir_taps.restype = c_int32
         L.dbp_status_string.argtypes = [c_int32]
@@ -271,6 +275,81 @@ class Plan:
                                      _stream_ptr(stream))
         _check(st, "dbp_backprop_grad")
         return gx, gt, gf
+
+
+class BatchPlan:
+    """A dbp_plan_batch: many signals (one Desc each, batch = 1) in one packed buffer."""
+
+    def __init__(self, descs):
+        self.descs = list(descs)
+        arr = (Desc * len(self.descs))(*self.descs)
+        h = c_void_p()
+        _check(lib().dbp_plan_batch(arr, len(self.descs), ctypes.byref(h)), "dbp_plan_batch")
+        self._h = h
+        n = len(self.descs)
+        offs = (c_int64 * (n + 1))()
+        _check(lib().dbp_batch_offsets(h, offs, n + 1), "dbp_batch_offsets")
+        self.offsets = np.array(offs[:], dtype=np.int64)
+        self.n_pol = self.descs[0].n_pol
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().dbp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def geometry(self, i):
+        nb, o, k = c_int32(), c_int32(), c_int32()
+        _check(lib().dbp_batch_geometry(self._h, i, ctypes.byref(nb), ctypes.byref(o), ctypes.byref(k)),
+               "dbp_batch_geometry")
+        return nb.value, o.value, k.value
+
+    def workspace_size(self) -> int:
+        return int(lib().dbp_workspace_size(self._h, 0))
+
+    def workspace(self):
+        import torch
+        return torch.empty(max(self.workspace_size(), 1), dtype=torch.uint8, device="cuda")
+
+    def pack(self, fields):
+        """Host list of [n_pol][L_i] complex arrays -> packed complex64 CUDA tensor."""
+        import torch
+        flat = np.concatenate([np.asarray(f, dtype=np.complex64).reshape(-1) for f in fields])
+        assert flat.size == self.offsets[-1]
+        return torch.from_numpy(flat).cuda()
+
+    def unpack(self, packed):
+        """Packed tensor -> list of [n_pol][L_i] complex64 host arrays."""
+        a = packed.cpu().numpy()
+        return [a[self.offsets[i]:self.offsets[i + 1]].reshape(self.n_pol, -1)
+                for i in range(len(self.descs))]
+
+    def backprop(self, packed, out=None, workspace=None, stream=None):
+        import torch
+        if packed.dtype != torch.complex64 or not packed.is_cuda or packed.numel() != self.offsets[-1]:
+            raise ValueError("packed input must be a complex64 CUDA tensor of the batch's total size")
+        if out is None:
+            out = torch.empty_like(packed)
+        if workspace is None:
+            workspace = self.workspace()
+        st = lib().dbp_backprop_batch(self._h, _ptr(packed), _ptr(out), _ptr(workspace), workspace.numel(),
+                                      _stream_ptr(stream))
+        _check(st, "dbp_backprop_batch")
+        return out
+
+    def status(self) -> int:
+        v = c_int32()
+        _check(lib().dbp_batch_status(self._h, ctypes.byref(v)), "dbp_batch_status")
+        return v.value
+
+
+def plan_batch(descs) -> BatchPlan:
+    return BatchPlan(descs)
 
 
 def _autograd_function():

@@ -1,0 +1,568 @@
+// Ragged batch: planning (autotuned geometry per signal), work queues, and the
+// graph-captured persistent launch.  Declarations in include/dbp.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <map>
+#include <mutex>
+#include <new>
+#include <tuple>
+#include <vector>
+
+#include "batch_registry.hpp"
+#include "dbp.h"
+#include "plan.hpp"
+#include "registry.hpp"
+
+namespace dbp {
+
+// ------------------------------------------------------------------ autotuner
+
+// Measured cost of one block item of a kernel variant at full occupancy:
+// c0 + k * c1 microseconds of chip time per block for a k-step pass.
+struct Cost {
+    double c0 = 0, c1 = 0;
+};
+
+static std::mutex g_cost_mu;
+static std::map<std::tuple<int, int, int, int, int>, Cost> g_costs;   // (device, npol, nt, p64, nb)
+
+static const int kBatchBlocks[] = {256, 512, 1024, 2048, 4096};
+
+static float time_launches(LaunchFn fn, PassArgs& a, int reps, hipStream_t s) {
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return -1.f;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return -1.f;
+    }
+    float ms = -1.f;
+    if (fn(a, a.n_wg, s) == hipSuccess && hipEventRecord(e0, s) == hipSuccess) {
+        bool ok = true;
+        for (int r = 0; r < reps && ok; ++r) ok = fn(a, a.n_wg, s) == hipSuccess;
+        if (ok && hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess)
+            (void)hipEventElapsedTime(&ms, e0, e1);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return ms < 0 ? -1.f : ms / reps;
+}
+
+// Time the pass kernel of a variant on a synthetic signal of 2^22 samples per
+// polarization with O = Nb/2, at k = 1 and k = 4 steps per pass.
+static dbp_status measure_cost(int npol, int nt, bool p64, int nb, Cost& out) {
+    const int e = default_e(nb, 1 << 20);
+    LaunchFn fn = find_kernel(nb, e, npol, p64, nt);
+    if (!fn) return DBP_ERR_UNSUPPORTED;
+    const int V = nb / 2;
+    const long long L = 1LL << 22;
+    const int n_blk = (int)(L / V);
+    const int ntaps = nt > 0 ? nt : (nt < 0 ? 9 : 1);
+    std::vector<float2> h(nb, make_float2(1.0f / nb, 0.f)), tw;
+    twiddle_table(nb, tw);
+    std::vector<StepDev> st(4);
+    for (auto& x : st) {
+        x.h_off = 0;
+        x.phi = 0.01f;
+        x.phi64 = 0.01;
+    }
+    std::vector<float> taps(4 * ntaps, 1.0f / ntaps);
+    float2 *d_in = nullptr, *d_out = nullptr, *d_h = nullptr, *d_tw = nullptr;
+    StepDev* d_st = nullptr;
+    float* d_taps = nullptr;
+    const size_t bytes = (size_t)npol * L * sizeof(float2);
+    dbp_status rc = DBP_ERR_HIP;
+    hipStream_t s = nullptr;
+    if (hipMalloc(&d_in, bytes) == hipSuccess && hipMalloc(&d_out, bytes) == hipSuccess &&
+        hipMalloc(&d_h, nb * sizeof(float2)) == hipSuccess && hipMalloc(&d_tw, nb * sizeof(float2)) == hipSuccess &&
+        hipMalloc(&d_st, st.size() * sizeof(StepDev)) == hipSuccess &&
+        hipMalloc(&d_taps, taps.size() * sizeof(float)) == hipSuccess &&
+        hipMemset(d_in, 0, bytes) == hipSuccess &&
+        hipMemcpy(d_h, h.data(), nb * sizeof(float2), hipMemcpyHostToDevice) == hipSuccess &&
+        hipMemcpy(d_tw, tw.data(), nb * sizeof(float2), hipMemcpyHostToDevice) == hipSuccess &&
+        hipMemcpy(d_st, st.data(), st.size() * sizeof(StepDev), hipMemcpyHostToDevice) == hipSuccess &&
+        hipMemcpy(d_taps, taps.data(), taps.size() * sizeof(float), hipMemcpyHostToDevice) == hipSuccess &&
+        hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess) {
+        PassArgs a{};
+        a.in = d_in;
+        a.out = d_out;
+        a.L = L;
+        a.V = V;
+        a.halo = (nb - V) / 2;
+        a.n_blk = n_blk;
+        a.n_wg = n_blk;
+        a.steps = d_st;
+        a.s0 = 0;
+        a.H = d_h;
+        a.tw = d_tw;
+        a.taps = nt == 0 ? nullptr : d_taps;
+        a.ntaps = ntaps;
+        a.ks = 1;
+        const float t1 = time_launches(fn, a, 3, s);
+        a.ks = 4;
+        const float t4 = time_launches(fn, a, 3, s);
+        if (t1 > 0 && t4 > 0) {
+            out.c1 = std::max(0.0, (t4 - t1) / 3.0) * 1e3 / n_blk;
+            out.c0 = std::max(1e-6, t1 * 1e3 / n_blk - out.c1);
+            rc = DBP_OK;
+        }
+    }
+    if (s) (void)hipStreamDestroy(s);
+    for (void* ptr : {(void*)d_in, (void*)d_out, (void*)d_h, (void*)d_tw, (void*)d_st, (void*)d_taps})
+        if (ptr) (void)hipFree(ptr);
+    return rc;
+}
+
+static dbp_status get_cost(int dev, int npol, int nt, bool p64, int nb, Cost& c) {
+    std::lock_guard<std::mutex> lk(g_cost_mu);
+    const auto key = std::make_tuple(dev, npol, nt, (int)p64, nb);
+    auto it = g_costs.find(key);
+    if (it != g_costs.end()) {
+        c = it->second;
+        return DBP_OK;
+    }
+    dbp_status st = measure_cost(npol, nt, p64, nb, c);
+    if (st != DBP_OK) return st;
+    g_costs[key] = c;
+    if (const char* path = std::getenv("DBP_AUTOTUNE_LOG")) {
+        if (FILE* f = std::fopen(path, "a")) {
+            std::fprintf(f, "{\"npol\": %d, \"nt\": %d, \"p64\": %d, \"nb\": %d, \"c0_us\": %.6g, \"c1_us\": %.6g}\n",
+                         npol, nt, (int)p64, nb, c.c0, c.c1);
+            std::fclose(f);
+        }
+    }
+    return DBP_OK;
+}
+
+struct SigGeo {
+    int block, overlap, k;
+};
+
+// Circular arcs [a, a + la) and [c, c + lc) on a circle of length L intersect.
+static bool arcs_meet(long long a, long long la, long long c, long long lc, long long L) {
+    const long long d1 = ((c - a) % L + L) % L, d2 = ((a - c) % L + L) % L;
+    return d1 < la || d2 < lc;
+}
+
+// Dependencies of every block of a signal: the blocks whose output region its
+// input window covers, and the blocks whose input window covers its output
+// region.  Windows reach at most O/2 <= V/2 past their region, except that of
+// the last, partial block, so candidates are b-2..b+2 and the two blocks at
+// each end of the signal.
+static bool block_deps(const BatchSig& s, int nb, std::vector<int>& deps) {
+    const long long L = s.L;
+    const int n = s.n_blk;
+    auto region = [&](int b, long long& st, long long& len) {
+        st = (long long)b * s.V;
+        len = std::min<long long>(s.V, L - st);
+    };
+    for (int b = 0; b < n; ++b) {
+        long long rs, rl;
+        region(b, rs, rl);
+        const long long ws = (((long long)b * s.V - s.halo) % L + L) % L;
+        std::vector<int> cand;
+        for (int d = -2; d <= 2; ++d) cand.push_back(((b + d) % n + n) % n);
+        for (int e : {0, 1, n - 2, n - 1}) cand.push_back(((e % n) + n) % n);
+        std::sort(cand.begin(), cand.end());
+        cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
+        int cnt = 0;
+        for (int c : cand) {
+            long long cs, cl;
+            region(c, cs, cl);
+            const long long cws = (((long long)c * s.V - s.halo) % L + L) % L;
+            const bool raw = arcs_meet(ws, std::min<long long>(nb, L), cs, cl, L);
+            const bool war = arcs_meet(cws, std::min<long long>(nb, L), rs, rl, L);
+            if (raw || war) {
+                if (cnt == DEPS_MAX) return false;
+                deps[(size_t)(s.prog_off + b) * DEPS_MAX + cnt++] = c;
+            }
+        }
+    }
+    return true;
+}
+
+// Cheapest (Nb, O, k) for one signal under the measured cost model: every pass
+// costs n_blk * (c0 + k c1); O is the smallest overlap covering k steps.
+static dbp_status tune_signal(const dbp_desc* d, const std::vector<double>& b, int dev, SigGeo& g) {
+    const int ns = (int)b.size();
+    const int nc = d->method == DBP_ESSFM ? (d->n_taps - 1) / 2 : 0;
+    const int nt = tap_variant(d->method, d->n_taps);
+    const bool p64 = d->precision != DBP_FP32;
+    if (d->block != 0) {
+        g.block = d->block;
+        g.overlap = d->overlap;
+        double smax = 0;
+        for (double v : b) smax = std::max(smax, spread_per_side(v, d->fs_thz, nc));
+        int kmax = smax > 0 ? (int)std::floor((d->overlap / 2 - kMargin) / smax) : ns;
+        kmax = std::max(1, std::min(kmax, ns));
+        g.k = d->steps_per_pass > 0 ? std::min(d->steps_per_pass, ns) : balance_k(ns, kmax);
+        return DBP_OK;
+    }
+    double smax = 0;
+    for (double v : b) smax = std::max(smax, spread_per_side(v, d->fs_thz, nc));
+    double best = 1e300;
+    for (int nb : kBatchBlocks) {
+        if (nb > d->n_samples) break;
+        Cost c;
+        dbp_status st = get_cost(dev, d->n_pol, nt, p64, nb, c);
+        if (st != DBP_OK) return st;
+        for (int k = 1; k <= ns; ++k) {
+            const int o = 2 * (int)std::ceil(k * smax + kMargin);
+            if (o > nb / 2) break;
+            const int kb = balance_k(ns, k);
+            const int passes = (ns + kb - 1) / kb;
+            const long long nblk = (d->n_samples + (nb - o) - 1) / (nb - o);
+            const double cost = (double)nblk * (passes * c.c0 + ns * c.c1);
+            if (cost < best) {
+                best = cost;
+                g.block = nb;
+                g.overlap = o;
+                g.k = kb;
+            }
+        }
+    }
+    return best < 1e300 ? DBP_OK : DBP_ERR_UNSUPPORTED;
+}
+
+// ------------------------------------------------------------------ plan state
+
+struct BatchGroup {
+    int nb, e, npol, nt;
+    bool p64;
+    BatchLaunchFn fn;
+    int grid;
+    int item0, n_items;
+    float2* d_tw = nullptr;
+};
+
+struct BatchState {
+    std::vector<BatchSig> sigs;
+    std::vector<BatchGroup> groups;
+    BatchSig* d_sigs = nullptr;
+    int4* d_items = nullptr;
+    int* d_counters = nullptr;
+    int* d_progress = nullptr;
+    int* d_deps = nullptr;
+    int* d_err = nullptr;
+    StepDev* d_steps = nullptr;
+    float2* d_h = nullptr;
+    float* d_taps = nullptr;
+    int n_progress = 0;
+    long long total = 0;                 // complex elements of the packed buffer
+    hipStream_t cap = nullptr;           // private capture stream
+    hipGraphExec_t exec = nullptr;
+    const void* g_in = nullptr;
+    void* g_out = nullptr;
+    void* g_ws = nullptr;
+};
+
+void destroy_batch(Plan* p) {
+    if (!p || !p->batch) return;
+    BatchState* b = (BatchState*)p->batch;
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    std::map<float2*, int> tws;
+    for (auto& g : b->groups) tws[g.d_tw] = 1;
+    for (auto& kv : tws)
+        if (kv.first) (void)hipFree(kv.first);
+    for (void* ptr : {(void*)b->d_sigs, (void*)b->d_items, (void*)b->d_counters, (void*)b->d_progress,
+                      (void*)b->d_deps, (void*)b->d_err, (void*)b->d_steps, (void*)b->d_h, (void*)b->d_taps})
+        if (ptr) (void)hipFree(ptr);
+    delete b;
+    p->batch = nullptr;
+}
+
+static BatchLaunchFn find_batch_kernel(int nb, int e, int npol, bool p64, int nt, BatchOccFn* occ) {
+    for (auto acc : {batch_kernels_1, batch_kernels_2}) {
+        int n = 0;
+        const BatchKernelEntry* t = acc(&n);
+        for (int i = 0; i < n; ++i)
+            if (t[i].nb == nb && t[i].e == e && t[i].npol == npol && t[i].p64 == p64 && t[i].nt == nt) {
+                *occ = t[i].occ;
+                return t[i].fn;
+            }
+    }
+    return nullptr;
+}
+
+}  // namespace dbp
+
+using namespace dbp;
+
+extern "C" {
+
+dbp_status dbp_plan_batch(const dbp_desc* descs, int32_t n, dbp_plan_t* out) {
+    if (!descs || n < 1 || !out) return DBP_ERR_INVALID_ARG;
+    *out = nullptr;
+    for (int i = 0; i < n; ++i) {
+        dbp_status st = validate(&descs[i]);
+        if (st != DBP_OK) return st;
+        if (descs[i].batch != 1 || descs[i].n_pol != descs[0].n_pol) return DBP_ERR_INVALID_ARG;
+        if (descs[i].linear != DBP_LINEAR_FFT || (descs[i].flags & DBP_FLAG_WHOLE) ||
+            descs[i].precision == DBP_BF16X3)
+            return DBP_ERR_UNSUPPORTED;
+    }
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return DBP_ERR_HIP;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return DBP_ERR_HIP;
+
+    Plan* p = new (std::nothrow) Plan();
+    BatchState* B = new (std::nothrow) BatchState();
+    if (!p || !B) {
+        delete p;
+        delete B;
+        return DBP_ERR_OOM;
+    }
+    p->is_batch = true;
+    p->batch = B;
+    p->device = dev;
+    p->desc = descs[0];
+    p->desc.taps = nullptr;
+    p->desc.fir = nullptr;
+    p->n_sig = n;
+    const int npol = descs[0].n_pol;
+
+    std::vector<StepDev> steps;
+    std::vector<float2> htab;
+    std::vector<float> taps;
+    std::map<std::tuple<int, double, bool>, int> hoff;        // (Nb, b, fp64) -> table offset
+    struct Key {
+        int nb, nt;
+        bool p64;
+        bool operator<(const Key& o) const { return std::tie(nb, nt, p64) < std::tie(o.nb, o.nt, o.p64); }
+    };
+    std::map<Key, std::vector<int>> by_group;
+    p->offsets.assign(n + 1, 0);
+    int prog = 0;
+    dbp_status st = DBP_OK;
+    for (int i = 0; i < n && st == DBP_OK; ++i) {
+        const dbp_desc* d = &descs[i];
+        std::vector<double> b, phi;
+        build_schedule(d, b, phi);
+        SigGeo g;
+        st = tune_signal(d, b, dev, g);
+        if (st != DBP_OK) break;
+        const bool fp64 = d->precision != DBP_FP32;
+        BatchSig s{};
+        s.off = p->offsets[i];
+        s.L = d->n_samples;
+        s.V = g.block - g.overlap;
+        s.halo = g.overlap / 2;
+        s.n_blk = (int)((s.L + s.V - 1) / s.V);
+        s.k = g.k;
+        s.n_steps = (int)b.size();
+        s.n_pass = (s.n_steps + g.k - 1) / g.k;
+        s.step0 = (int)steps.size();
+        s.ntaps = d->method == DBP_ESSFM ? d->n_taps : 1;
+        s.taps_off = d->method == DBP_ESSFM ? (int)taps.size() : -1;
+        s.prog_off = prog;
+        prog += s.n_blk;
+        if (s.halo > s.V) st = DBP_ERR_UNSUPPORTED;      // dependency candidates assume O/2 <= V
+        for (int k = 0; k < s.n_steps; ++k) {
+            const auto key = std::make_tuple(g.block, b[k], fp64);
+            auto it = hoff.find(key);
+            int off;
+            if (it == hoff.end()) {
+                off = (int)htab.size();
+                htab.resize(htab.size() + g.block);
+                dispersion_table(g.block, b[k], d->fs_thz, fp64, htab.data() + off);
+                hoff[key] = off;
+            } else {
+                off = it->second;
+            }
+            StepDev sd;
+            sd.h_off = off;
+            sd.phi = (float)phi[k];
+            sd.phi64 = phi[k];
+            steps.push_back(sd);
+            if (d->method == DBP_ESSFM)
+                for (int m = 0; m < d->n_taps; ++m)
+                    taps.push_back(d->taps[(d->taps_per_step ? (size_t)k * d->n_taps : 0) + m]);
+        }
+        p->offsets[i + 1] = p->offsets[i] + (long long)npol * s.L;
+        p->sig_block.push_back(g.block);
+        p->sig_overlap.push_back(g.overlap);
+        p->sig_k.push_back(g.k);
+        B->sigs.push_back(s);
+        by_group[Key{g.block, tap_variant(d->method, d->n_taps), fp64}].push_back(i);
+    }
+    if (st != DBP_OK) {
+        dbp_destroy(p);
+        return st;
+    }
+    B->total = p->offsets[n];
+    B->n_progress = prog;
+    std::vector<int> deps((size_t)std::max(1, prog) * DEPS_MAX, -1);
+    for (int i = 0; i < n; ++i)
+        if (!block_deps(B->sigs[i], p->sig_block[i], deps)) {
+            dbp_destroy(p);
+            return DBP_ERR_UNSUPPORTED;
+        }
+
+    // work queues: per group, pass level by pass level; within a level the signals with
+    // the most remaining passes first
+    std::vector<int4> items;
+    for (auto& kv : by_group) {
+        BatchGroup G{};
+        G.nb = kv.first.nb;
+        G.nt = kv.first.nt;
+        G.p64 = kv.first.p64;
+        G.npol = npol;
+        G.e = default_e(G.nb, 1 << 20);
+        BatchOccFn occ = nullptr;
+        G.fn = find_batch_kernel(G.nb, G.e, npol, G.p64, G.nt, &occ);
+        if (!G.fn) {
+            dbp_destroy(p);
+            return DBP_ERR_UNSUPPORTED;
+        }
+        std::vector<int> sig = kv.second;
+        std::sort(sig.begin(), sig.end(), [&](int a, int b) { return B->sigs[a].n_pass > B->sigs[b].n_pass; });
+        int max_pass = 0;
+        for (int i : sig) max_pass = std::max(max_pass, B->sigs[i].n_pass);
+        G.item0 = (int)items.size();
+        for (int lv = 0; lv < max_pass; ++lv)
+            for (int i : sig)
+                if (B->sigs[i].n_pass > lv)
+                    for (int blk = 0; blk < B->sigs[i].n_blk; ++blk) items.push_back(make_int4(i, lv, blk, 0));
+        G.n_items = (int)items.size() - G.item0;
+        const int per_cu = std::max(1, occ ? occ() : 1);
+        G.grid = std::max(1, std::min(G.n_items, per_cu * prop.multiProcessorCount));
+        B->groups.push_back(G);
+    }
+
+    auto upload = [&](void** dptr, const void* src, size_t bytes) -> dbp_status {
+        if (bytes == 0) return DBP_OK;
+        hipError_t e = hipMalloc(dptr, bytes);
+        if (e == hipErrorOutOfMemory) return DBP_ERR_OOM;
+        if (e != hipSuccess) return DBP_ERR_HIP;
+        if (src && hipMemcpy(*dptr, src, bytes, hipMemcpyHostToDevice) != hipSuccess) return DBP_ERR_HIP;
+        return DBP_OK;
+    };
+    std::map<int, float2*> tw_by_nb;
+    for (auto& G : B->groups) {
+        if (!tw_by_nb.count(G.nb)) {
+            std::vector<float2> tw;
+            twiddle_table(G.nb, tw);
+            float2* d = nullptr;
+            if ((st = upload((void**)&d, tw.data(), tw.size() * sizeof(float2))) != DBP_OK) break;
+            tw_by_nb[G.nb] = d;
+        }
+        G.d_tw = tw_by_nb[G.nb];
+    }
+    if (st == DBP_OK &&
+        ((st = upload((void**)&B->d_sigs, B->sigs.data(), B->sigs.size() * sizeof(BatchSig))) != DBP_OK ||
+         (st = upload((void**)&B->d_items, items.data(), items.size() * sizeof(int4))) != DBP_OK ||
+         (st = upload((void**)&B->d_counters, nullptr, B->groups.size() * sizeof(int))) != DBP_OK ||
+         (st = upload((void**)&B->d_progress, nullptr, std::max(1, prog) * sizeof(int))) != DBP_OK ||
+         (st = upload((void**)&B->d_deps, deps.data(), deps.size() * sizeof(int))) != DBP_OK ||
+         (st = upload((void**)&B->d_err, nullptr, sizeof(int))) != DBP_OK ||
+         (st = upload((void**)&B->d_steps, steps.data(), steps.size() * sizeof(StepDev))) != DBP_OK ||
+         (st = upload((void**)&B->d_h, htab.data(), htab.size() * sizeof(float2))) != DBP_OK ||
+         (st = upload((void**)&B->d_taps, taps.data(), taps.size() * sizeof(float))) != DBP_OK)) {
+    }
+    if (st == DBP_OK && hipMemset(B->d_err, 0, sizeof(int)) != hipSuccess) st = DBP_ERR_HIP;
+    if (st == DBP_OK && hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking) != hipSuccess) st = DBP_ERR_HIP;
+    if (st != DBP_OK) {
+        dbp_destroy(p);
+        return st;
+    }
+    p->geo.n_passes = 0;
+    *out = p;
+    return DBP_OK;
+}
+
+dbp_status dbp_batch_offsets(dbp_plan_t p, int64_t* offsets, int32_t n_plus_1) {
+    if (!p || !p->is_batch || !offsets || n_plus_1 != p->n_sig + 1) return DBP_ERR_INVALID_ARG;
+    for (int i = 0; i <= p->n_sig; ++i) offsets[i] = p->offsets[i];
+    return DBP_OK;
+}
+
+dbp_status dbp_batch_geometry(dbp_plan_t p, int32_t i, int32_t* block, int32_t* overlap, int32_t* k) {
+    if (!p || !p->is_batch || i < 0 || i >= p->n_sig) return DBP_ERR_INVALID_ARG;
+    if (block) *block = p->sig_block[i];
+    if (overlap) *overlap = p->sig_overlap[i];
+    if (k) *k = p->sig_k[i];
+    return DBP_OK;
+}
+
+dbp_status dbp_batch_status(dbp_plan_t p, int32_t* flags) {
+    if (!p || !p->is_batch || !flags) return DBP_ERR_INVALID_ARG;
+    BatchState* B = (BatchState*)p->batch;
+    int v = 0;
+    if (hipMemcpy(&v, B->d_err, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return DBP_ERR_HIP;
+    *flags = v;
+    return DBP_OK;
+}
+
+dbp_status dbp_backprop_batch(dbp_plan_t p, const void* in_packed, void* out_packed, void* ws, size_t ws_bytes,
+                              void* stream) {
+    if (!p || !p->is_batch || !in_packed || !out_packed) return DBP_ERR_INVALID_ARG;
+    BatchState* B = (BatchState*)p->batch;
+    const size_t state = p->state_bytes();
+    const char* ib = (const char*)in_packed;
+    const char* ob = (const char*)out_packed;
+    if (in_packed != out_packed && ib < ob + state && ob < ib + state) return DBP_ERR_INVALID_ARG;
+    if (!ws || ws_bytes < 2 * state) return DBP_ERR_WORKSPACE;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return DBP_ERR_HIP;
+    if (dev != p->device) return DBP_ERR_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+
+    if (!B->exec || B->g_in != in_packed || B->g_out != out_packed || B->g_ws != ws) {
+        if (B->exec) {
+            (void)hipGraphExecDestroy(B->exec);
+            B->exec = nullptr;
+        }
+        const bool inplace = in_packed == out_packed;
+        float2* ws0 = (float2*)ws;
+        float2* ws1 = (float2*)((char*)ws + state);
+        hipGraph_t graph = nullptr;
+        if (hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) return DBP_ERR_HIP;
+        bool ok = launch_batch_reset(B->d_counters, (int)B->groups.size(), B->d_progress, B->n_progress, B->d_err,
+                                     B->cap) == hipSuccess;
+        // in place: every pass-0 block must read the untouched input, so stage it first
+        if (ok && inplace) ok = launch_copy(ws1, (const float2*)in_packed, B->total, B->cap) == hipSuccess;
+        for (size_t gi = 0; gi < B->groups.size() && ok; ++gi) {
+            const BatchGroup& G = B->groups[gi];
+            BatchArgs a{};
+            a.in = inplace ? ws1 : (const float2*)in_packed;
+            a.out = (float2*)out_packed;
+            a.ws0 = ws0;
+            a.sigs = B->d_sigs;
+            a.items = B->d_items + G.item0;
+            a.n_items = G.n_items;
+            a.counter = B->d_counters + gi;
+            a.progress = B->d_progress;
+            a.deps = B->d_deps;
+            a.err = B->d_err;
+            a.steps = B->d_steps;
+            a.H = B->d_h;
+            a.tw = G.d_tw;
+            a.taps = B->d_taps;
+            a.spin_limit = 1LL << 18;          // about 0.25 s per wait at ~1 us per poll
+            ok = G.fn(a, G.grid, B->cap) == hipSuccess;
+        }
+        const hipError_t ec = hipStreamEndCapture(B->cap, &graph);
+        if (!ok || ec != hipSuccess || !graph) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return DBP_ERR_HIP;
+        }
+        const hipError_t ei = hipGraphInstantiate(&B->exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ei != hipSuccess) {
+            B->exec = nullptr;
+            return DBP_ERR_HIP;
+        }
+        B->g_in = in_packed;
+        B->g_out = out_packed;
+        B->g_ws = ws;
+    }
+    if (hipGraphLaunch(B->exec, s) != hipSuccess) return DBP_ERR_HIP;
+    return DBP_OK;
+}
+
+}  // extern "C"

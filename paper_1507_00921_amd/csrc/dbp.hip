@@ -21,7 +21,7 @@ namespace dbp {
 
 // ------------------------------------------------------------------ kernel registry
 
-static LaunchFn find_kernel(int nb, int e, int npol, bool p64, int nt) {
+LaunchFn find_kernel(int nb, int e, int npol, bool p64, int nt) {
     using Acc = const KernelEntry* (*)(int*);
     static const Acc tables[] = {kernels_small, kernels_1024, kernels_2048, kernels_4096, kernels_large};
     for (Acc acc : tables) {
@@ -35,7 +35,7 @@ static LaunchFn find_kernel(int nb, int e, int npol, bool p64, int nt) {
 }
 
 // Compile-time tap count of the variant serving a method and tap count.
-static int tap_variant(int method, int n_taps) {
+int tap_variant(int method, int n_taps) {
     if (method == DBP_SSFM) return 0;
     return n_taps == 9 ? 9 : -1;
 }
@@ -116,9 +116,9 @@ void build_schedule(const dbp_desc* d, std::vector<double>& b, std::vector<doubl
 
 // Samples of spread per side one step adds: half the dispersion memory
 // 2 pi |b| fs^2 (Sec. III) plus the Nc taps of the intensity filter.
-static double spread_per_side(double b, double fs, int nc) { return M_PI * std::fabs(b) * fs * fs + nc; }
+double spread_per_side(double b, double fs, int nc) { return M_PI * std::fabs(b) * fs * fs + nc; }
 
-static constexpr int kMargin = 16;
+
 
 // Largest k whose accumulated spread fits the halo, at least 1.
 static int max_k(const std::vector<double>& b, double fs, int nc, int halo) {
@@ -129,7 +129,7 @@ static int max_k(const std::vector<double>& b, double fs, int nc, int halo) {
     return (int)std::max<long long>(1, std::min<long long>(k, (long long)b.size()));
 }
 
-static int balance_k(int ns, int kmax) {
+int balance_k(int ns, int kmax) {
     const int passes = (ns + kmax - 1) / kmax;
     return (ns + passes - 1) / passes;
 }
@@ -196,7 +196,7 @@ dbp_status choose_geometry(const dbp_desc* d, const std::vector<double>& b, Geom
 
 // ------------------------------------------------------------------ tables
 
-static void twiddle_table(int nb, std::vector<float2>& tw) {
+void twiddle_table(int nb, std::vector<float2>& tw) {
     tw.resize(nb);
     for (int q = 0; q < nb; ++q) {
         const double a = -2.0 * M_PI * (double)q / nb;
@@ -205,7 +205,7 @@ static void twiddle_table(int nb, std::vector<float2>& tw) {
 }
 
 // exp(-j 2 pi^2 b f_k^2) / nb in natural bin order, f_k = fftfreq(nb, 1/fs)
-static void dispersion_table(int nb, double b, double fs, bool fp64, float2* out) {
+void dispersion_table(int nb, double b, double fs, bool fp64, float2* out) {
     for (int k = 0; k < nb; ++k) {
         const int kk = k < (nb + 1) / 2 ? k : k - nb;
         if (fp64) {
@@ -511,6 +511,7 @@ void dbp_destroy(dbp_plan_t p) {
     if (p->d_steps) (void)hipFree(p->d_steps);
     if (p->d_taps) (void)hipFree(p->d_taps);
     if (p->d_fir) (void)hipFree(p->d_fir);
+    destroy_batch(p);
     delete p;
 }
 
@@ -577,13 +578,14 @@ extern "C" {
 size_t dbp_workspace_size(dbp_plan_t p, int32_t grad) {
     if (!p) return 0;
     const size_t state = p->state_bytes();
+    if (p->is_batch) return grad ? 0 : 2 * state;
     if (grad) return p->desc.linear == DBP_LINEAR_FIR ? grad_ws_bytes(p) : 0;
     return p->geo.n_passes == 1 ? state : 2 * state;
 }
 
 dbp_status dbp_backprop(dbp_plan_t p, const void* in, void* out, const float* taps, const void* fir,
                         void* ws, size_t ws_bytes, void* stream) {
-    if (!p || !in || !out) return DBP_ERR_INVALID_ARG;
+    if (!p || !in || !out || p->is_batch) return DBP_ERR_INVALID_ARG;
     (void)fir;
     const size_t state = p->state_bytes();
     const char* ib = (const char*)in;
@@ -660,7 +662,7 @@ dbp_status dbp_backprop(dbp_plan_t p, const void* in, void* out, const float* ta
 dbp_status dbp_backprop_grad(dbp_plan_t p, const void* in, const float* taps, const void* fir,
                              const void* grad_out, void* grad_in, float* grad_taps, void* grad_fir,
                              void* ws, size_t ws_bytes, void* stream) {
-    if (!p || !in || !grad_out) return DBP_ERR_INVALID_ARG;
+    if (!p || !in || !grad_out || p->is_batch) return DBP_ERR_INVALID_ARG;
     if (p->desc.linear != DBP_LINEAR_FIR) return DBP_ERR_UNSUPPORTED;
     const size_t state = p->state_bytes();
     const char* go = (const char*)grad_out;
@@ -724,25 +726,6 @@ dbp_status dbp_backprop_grad(dbp_plan_t p, const void* in, const float* taps, co
             return DBP_ERR_HIP;
     }
     return DBP_OK;
-}
-
-dbp_status dbp_plan_batch(const dbp_desc* descs, int32_t n, dbp_plan_t* out) {
-    if (!descs || n < 1 || !out) return DBP_ERR_INVALID_ARG;
-    *out = nullptr;
-    return DBP_ERR_UNSUPPORTED;
-}
-
-dbp_status dbp_batch_offsets(dbp_plan_t p, int64_t* offsets, int32_t n_plus_1) {
-    (void)offsets; (void)n_plus_1;
-    if (!p) return DBP_ERR_INVALID_ARG;
-    return DBP_ERR_UNSUPPORTED;
-}
-
-dbp_status dbp_backprop_batch(dbp_plan_t p, const void* in_packed, void* out_packed, void* ws,
-                              size_t ws_bytes, void* stream) {
-    (void)in_packed; (void)out_packed; (void)ws; (void)ws_bytes; (void)stream;
-    if (!p) return DBP_ERR_INVALID_ARG;
-    return DBP_ERR_UNSUPPORTED;
 }
 
 }  // extern "C"

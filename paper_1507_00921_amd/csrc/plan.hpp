@@ -18,6 +18,8 @@ struct Geometry {
     int n_passes = 0;
 };
 
+struct BatchGroup;
+
 }  // namespace dbp
 
 struct dbp_plan_s {
@@ -33,9 +35,35 @@ struct dbp_plan_s {
     float2* d_fir = nullptr;         // FIR linear step: [N_s][n_fir]
     std::vector<float> h_taps;
 
+    // ragged batch (dbp_plan_batch)
+    bool is_batch = false;
+    int n_sig = 0;
+    std::vector<long long> offsets;          // element offsets, n_sig + 1
+    std::vector<int> sig_block, sig_overlap, sig_k;
+    void* batch = nullptr;                   // dbp::BatchState
+
     size_t state_bytes() const {
+        if (is_batch) return (size_t)offsets.back() * sizeof(float2);
         return (size_t)desc.batch * desc.n_pol * (size_t)desc.n_samples * sizeof(float2);
     }
 };
 
 using Plan = dbp_plan_s;
+
+namespace dbp {
+
+// planner helpers shared by the translation units of the C ABI
+using LaunchFn = hipError_t (*)(const PassArgs&, int grid, hipStream_t);
+constexpr int kMargin = 16;
+dbp_status validate(const dbp_desc* d);
+void build_schedule(const dbp_desc* d, std::vector<double>& b, std::vector<double>& phi);
+LaunchFn find_kernel(int nb, int e, int npol, bool p64, int nt);
+int tap_variant(int method, int n_taps);
+int default_e(int nb, long long n_wg);
+double spread_per_side(double b, double fs, int nc);
+int balance_k(int ns, int kmax);
+void twiddle_table(int nb, std::vector<float2>& tw);
+void dispersion_table(int nb, double b, double fs, bool fp64, float2* out);
+void destroy_batch(Plan* p);
+
+}  // namespace dbp

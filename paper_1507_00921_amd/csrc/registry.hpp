@@ -7,8 +7,11 @@
 #include "step_kernel.hpp"
 
 namespace dbp {
-
 using LaunchFn = hipError_t (*)(const PassArgs&, int grid, hipStream_t);
+}
+
+namespace dbp {
+
 
 struct KernelEntry {
     int nb, e, npol;

@@ -57,29 +57,45 @@ __device__ __forceinline__ float2 phase_factor(float j, const StepDev& st) {
     return make_float2(c, s);
 }
 
+// One overlap-and-save block through steps [s0, s0 + ks) of one signal.
+struct BlockJob {
+    const float2* src;      // signal input [NPOL][L]
+    float2* dst;            // signal output [NPOL][L]
+    long long L;
+    int V, halo, blk;
+    const StepDev* steps;
+    int s0, ks;
+    const float2* H;
+    const float* taps;      // [N_s][ntaps] of this signal, nullptr for SSFM
+    int ntaps;
+};
+
+// Shared-memory footprint of the block routine.
+template <int NB, int E, int NPOL, int NT> struct BlockSmem {
+    using X = Exchange<NB, E, NPOL>;
+    static constexpr bool OWN_I = X::NBUF == 2 && NT != 0;
+    float2 lds[X::FLOATS2];
+    float ilds_own[OWN_I ? NB : 1];
+};
+
 // NT: number of ESSFM taps known at compile time (0: SSFM, J = I; -1: taken
-// from a.ntaps at run time).
+// from the job at run time).  Every thread of the workgroup must call this.
 template <int NB, int E, int NPOL, bool PHASE64, int NT>
-__global__ __launch_bounds__(NB / E) void dbp_pass_kernel(PassArgs a) {
+__device__ __forceinline__ void process_block(const BlockJob& a, const TwReg<NB, E>& twr,
+                                              BlockSmem<NB, E, NPOL, NT>& sm) {
     using S = FftShape<NB, E>;
     using X = Exchange<NB, E, NPOL>;
     constexpr int T = S::T;
     // intensity for the tap filter: its own array when two exchange buffers
     // alternate (another wave may still read one of them), else the exchange
     // buffer itself (single wave: in-order LDS; one buffer: fenced by barriers)
-    constexpr bool OWN_I = X::NBUF == 2 && NT != 0;
-    __shared__ float2 lds[X::FLOATS2];
-    __shared__ float ilds_own[OWN_I ? NB : 1];
-    float* ilds = OWN_I ? ilds_own : reinterpret_cast<float*>(lds);
+    constexpr bool OWN_I = BlockSmem<NB, E, NPOL, NT>::OWN_I;
+    float2* lds = sm.lds;
+    float* ilds = OWN_I ? sm.ilds_own : reinterpret_cast<float*>(sm.lds);
 
     const int t = threadIdx.x;
-    const int wg = xcd_remap(blockIdx.x, a.n_wg);
-    const int sig = wg / a.n_blk;
-    const int blk = wg - sig * a.n_blk;
     const long long L = a.L;
-    const float2* __restrict__ src = a.in + (long long)sig * NPOL * L;
-    float2* __restrict__ dst = a.out + (long long)sig * NPOL * L;
-    const long long start = (long long)blk * a.V - a.halo;
+    const long long start = (long long)a.blk * a.V - a.halo;
 
     float2 v[NPOL][E];
 #pragma unroll
@@ -87,11 +103,8 @@ __global__ __launch_bounds__(NB / E) void dbp_pass_kernel(PassArgs a) {
         long long i = start + t + T * q;
         i = i < 0 ? i + L : (i >= L ? i - L : i);
 #pragma unroll
-        for (int p = 0; p < NPOL; ++p) v[p][q] = src[p * L + i];
+        for (int p = 0; p < NPOL; ++p) v[p][q] = a.src[p * L + i];
     }
-
-    TwReg<NB, E> twr;
-    load_twiddles<NB, E>(twr, a.tw, t);
 
     const int ntaps = NT >= 0 ? NT : a.ntaps;
     const int c = (ntaps - 1) >> 1;
@@ -160,12 +173,37 @@ __global__ __launch_bounds__(NB / E) void dbp_pass_kernel(PassArgs a) {
 #pragma unroll
     for (int q = 0; q < E; ++q) {
         const int pos = t + T * q;
-        const long long o = (long long)blk * a.V + pos - a.halo;
+        const long long o = (long long)a.blk * a.V + pos - a.halo;
         if (pos >= a.halo && pos < a.halo + a.V && o < L) {
 #pragma unroll
-            for (int p = 0; p < NPOL; ++p) dst[p * L + o] = v[p][q];
+            for (int p = 0; p < NPOL; ++p) a.dst[p * L + o] = v[p][q];
         }
     }
+    // before the LDS is reused by a following job, every wave is done with it
+    if constexpr (S::T > 64) __syncthreads();
+}
+
+template <int NB, int E, int NPOL, bool PHASE64, int NT>
+__global__ __launch_bounds__(NB / E) void dbp_pass_kernel(PassArgs a) {
+    __shared__ BlockSmem<NB, E, NPOL, NT> sm;
+    const int wg = xcd_remap(blockIdx.x, a.n_wg);
+    const int sig = wg / a.n_blk;
+    TwReg<NB, E> twr;
+    load_twiddles<NB, E>(twr, a.tw, threadIdx.x);
+    BlockJob j;
+    j.src = a.in + (long long)sig * NPOL * a.L;
+    j.dst = a.out + (long long)sig * NPOL * a.L;
+    j.L = a.L;
+    j.V = a.V;
+    j.halo = a.halo;
+    j.blk = wg - sig * a.n_blk;
+    j.steps = a.steps;
+    j.s0 = a.s0;
+    j.ks = a.ks;
+    j.H = a.H;
+    j.taps = a.taps;
+    j.ntaps = a.ntaps;
+    process_block<NB, E, NPOL, PHASE64, NT>(j, twr, sm);
 }
 
 }  // namespace dbp

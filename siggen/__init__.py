@@ -173,3 +173,26 @@ def symmetric_taps(gen: np.random.Generator, n_c: int) -> np.ndarray:
     half[0] = max(half[0], 1.0)
     full = np.concatenate([half[:0:-1], half])
     return full / full.sum()
+
+
+def ragged_workload(n_signals: int = 512, seed: int = 0, lo_exp: float = 12.0, hi_exp: float = 17.0,
+                    spans=(10, 40), essfm_nc=(2, 6), ssfm_steps=(4, 20)):
+    """The ragged-batch workload: per signal a dict with its length (log-uniform on
+    [2^lo, 2^hi], even), span count (uniform), and method: the even-indexed half
+    ESSFM at one step per span with Nc uniform in essfm_nc (seeded symmetric,
+    unit-sum taps), the odd-indexed half SSFM with steps per span uniform in
+    ssfm_steps."""
+    g = rng(2, seed, 0)
+    lengths = ragged_lengths(g, n_signals, lo_exp, hi_exp)
+    out = []
+    for i in range(n_signals):
+        gi = rng(2, seed, 1 + i)
+        n_spans = int(gi.integers(spans[0], spans[1] + 1))
+        if i % 2 == 0:
+            nc = int(gi.integers(essfm_nc[0], essfm_nc[1] + 1))
+            out.append(dict(n=int(lengths[i]), n_spans=n_spans, steps_per_span=1,
+                            taps=symmetric_taps(gi, nc)))
+        else:
+            out.append(dict(n=int(lengths[i]), n_spans=n_spans,
+                            steps_per_span=int(gi.integers(ssfm_steps[0], ssfm_steps[1] + 1)), taps=None))
+    return out

@@ -1,0 +1,122 @@
+"""GPU parity of the ragged batch (persistent, graph-replayed) against the FP64 oracle.
+
+Each signal is compared with the oracle's overlap-and-save cascade in the
+geometry the autotuner chose for it (read back per signal); tolerances as for
+single plans: relative L2 <= 1e-5 up to 40 steps, <= 2e-4 beyond.
+"""
+import numpy as np
+import pytest
+
+import siggen
+from oracle import dbp_ref as R
+
+from gpu_inputs import B2, FS, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def dbp():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1507_00921_amd as m
+    m.lib()
+    return m
+
+
+def descs_for(dbp, work, **kw):
+    return [dbp.make_desc(w["n"], w["n_spans"], w["steps_per_span"], taps=w["taps"], beta2_ps2_km=B2, **kw)
+            for w in work]
+
+
+def fields_for(work, seed):
+    return [siggen.transmitted_field(2, seed * 1000 + i, 2, w["n"], 2.0)[0].astype(np.complex64)
+            for i, w in enumerate(work)]
+
+
+def oracle_one(x, w, geo):
+    nb, o, k = geo
+    taps = None if w["taps"] is None else w["taps"].astype(np.float32).astype(np.float64)
+    steps = R.schedule(w["n_spans"], 80.0, w["steps_per_span"], B2, 1.3, 0.2, taps=taps)
+    return R.run_blocked(x.astype(np.complex128), steps, FS, nb, o, k), len(steps)
+
+
+def small_work(seed, n):
+    work = siggen.ragged_workload(n, seed=seed, lo_exp=11.5, hi_exp=14.0, spans=(2, 5), essfm_nc=(2, 6),
+                                  ssfm_steps=(2, 8))
+    work[0]["n"] = 2050            # short signal: partial last block shorter than the halo
+    return work
+
+
+def test_small_ragged_batch_parity(dbp):
+    work = small_work(1, 14)
+    bp = dbp.plan_batch(descs_for(dbp, work))
+    xs = fields_for(work, 1)
+    y = bp.unpack(bp.backprop(bp.pack(xs)))
+    torch.cuda.synchronize()
+    assert bp.status() == 0
+    for i, w in enumerate(work):
+        ref, ns = oracle_one(xs[i], w, bp.geometry(i))
+        err = rel_l2(y[i].astype(np.complex128), ref)
+        print(f"signal {i}: L={w['n']} steps={ns} geo={bp.geometry(i)} rel L2 {err:.3e}")
+        assert err <= (1e-5 if ns <= 40 else 2e-4)
+
+
+def test_graph_replays_and_in_place(dbp):
+    work = small_work(2, 10)
+    bp = dbp.plan_batch(descs_for(dbp, work))
+    xs = fields_for(work, 2)
+    x = bp.pack(xs)
+    ws = bp.workspace()
+    out = torch.empty_like(x)
+    first = bp.backprop(x, out=out, workspace=ws).clone()
+    for r in range(3):
+        # eager work between replays (a torch reduction over many blocks)
+        _ = torch.sum(torch.abs(x)).item()
+        again = bp.backprop(x, out=out, workspace=ws)
+        torch.cuda.synchronize()
+        assert torch.equal(again, first), r
+    y = x.clone()
+    bp.backprop(y, out=y, workspace=ws)
+    torch.cuda.synchronize()
+    assert torch.equal(y, first)
+    assert bp.status() == 0
+
+
+def test_explicit_geometry_is_kept(dbp):
+    work = small_work(3, 6)
+    ds = descs_for(dbp, work, block=512, overlap=128, steps_per_pass=2)
+    bp = dbp.plan_batch(ds)
+    xs = fields_for(work, 3)
+    y = bp.unpack(bp.backprop(bp.pack(xs)))
+    for i, w in enumerate(work):
+        assert bp.geometry(i) == (512, 128, 2)
+        ref, ns = oracle_one(xs[i], w, (512, 128, 2))
+        assert rel_l2(y[i].astype(np.complex128), ref) <= (1e-5 if ns <= 40 else 2e-4)
+
+
+def test_full_ragged_workload_sampled(dbp):
+    # 512 signals (lengths 2^12..2^17, 10-40 spans, half ESSFM 5-13 taps, half SSFM 4-20 steps/span):
+    # the shortest, the longest and six more signals against the oracle
+    work = siggen.ragged_workload(512, seed=0)
+    bp = dbp.plan_batch(descs_for(dbp, work))
+    lengths = np.array([w["n"] for w in work])
+    steps = np.array([w["n_spans"] * w["steps_per_span"] for w in work])
+    cost = lengths * steps
+    pick = [int(np.argmin(lengths)), int(np.argmax(lengths))]
+    order = np.argsort(cost)
+    pick += [int(i) for i in order[[10, 60, 120, 200, 300, 400]] if int(i) not in pick]
+    xs = [None] * 512
+    for i in range(512):
+        xs[i] = siggen.transmitted_field(2, i, 2, work[i]["n"], 0.0)[0].astype(np.complex64) \
+            if i in pick else np.zeros((2, work[i]["n"]), np.complex64)
+    y = bp.unpack(bp.backprop(bp.pack(xs)))
+    torch.cuda.synchronize()
+    assert bp.status() == 0
+    for i in pick:
+        ref, ns = oracle_one(xs[i], work[i], bp.geometry(i))
+        err = rel_l2(y[i].astype(np.complex128), ref)
+        print(f"cfg2 signal {i}: L={work[i]['n']} steps={ns} geo={bp.geometry(i)} rel L2 {err:.3e}")
+        assert err <= (1e-5 if ns <= 40 else 2e-4)
