@@ -200,7 +200,74 @@ def grad_workload(dbp, torch, reps=5):
     return {"workload": f"{batch}x2x{n}, 3200 km, ESSFM 40 steps, 9 taps + 33-tap FIR per step, "
                         "checkpoint every 8 steps, symbol-MSE loss",
             "fwd_bwd_ms": round(ms_step, 3), "dbp_forward_ms": round(ms_f, 3),
-            "dbp_backward_ms": round(ms_b, 3), "loss": round(float(loss), 5)}
+            "dbp_backward_ms": round(ms_b, 3), "loss": round(float(loss.detach()), 5)}
+
+
+def batch_workload(dbp, torch, reps=5):
+    """Ragged batch: 512 PM-QPSK signals (lengths log-uniform 2^12..2^17, 10-40 spans, half
+    ESSFM 1 step/span 5-13 taps, half SSFM 4-20 steps/span) in one graph-replayed persistent
+    launch per kernel variant, geometry from the autotuner.  Algorithmic bytes: per signal,
+    pass and block Nb*16 B read + V*16 B written (valid part of the last block only)."""
+    b2 = siggen.beta2_ps2_km()
+    work = siggen.ragged_workload(512, seed=0)
+    descs = [dbp.make_desc(w["n"], w["n_spans"], w["steps_per_span"], taps=w["taps"], beta2_ps2_km=b2)
+             for w in work]
+    t0 = time.perf_counter()
+    bp = dbp.plan_batch(descs)
+    t_plan = time.perf_counter() - t0
+    xs = [siggen.transmitted_field(2, i, 2, w["n"], 0.0)[0] for i, w in enumerate(work)]
+    x = bp.pack(xs)
+    out = torch.empty_like(x)
+    ws = bp.workspace()
+    for _ in range(2):
+        bp.backprop(x, out=out, workspace=ws)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        bp.backprop(x, out=out, workspace=ws)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    assert bp.status() == 0
+    total_samples = sum(w["n"] for w in work)
+    byts = 0
+    sample_steps = 0
+    geos = {}
+    for i, w in enumerate(work):
+        nb, o, k = bp.geometry(i)
+        v = nb - o
+        ns = w["n_spans"] * w["steps_per_span"]
+        passes = -(-ns // k)
+        nblk = -(-w["n"] // v)
+        byts += passes * (nblk * nb * 16 + w["n"] * 16)
+        sample_steps += w["n"] * ns
+        geos[f"{nb}/{o}/{k}"] = geos.get(f"{nb}/{o}/{k}", 0) + 1
+    top = sorted(geos.items(), key=lambda kv: -kv[1])[:6]
+    return {"workload": f"512 ragged PM signals, {total_samples} samples/pol "
+                        f"({total_samples * 16 / 2**20:.0f} MiB per state), 10-800 steps",
+            "ms": round(ms, 3), "msamples_per_s": round(total_samples / ms / 1e3, 1),
+            "gsample_steps_per_s": round(sample_steps / ms / 1e6, 2),
+            "algorithmic_gbs": round(byts / ms / 1e6, 1), "hbm_frac": round(byts / ms / 1e6 / HBM_PEAK_GBS, 4),
+            "plan_s": round(t_plan, 2), "common_geometries": dict(top)}
+
+
+def precision_workload(dbp, torch, reps=3):
+    """Precision variants on 2 x 4194304 samples at 3200 km, SSFM 20 steps/span (800 steps):
+    samples/s for FP32 tables and phase vs FP64-generated tables and phase argument."""
+    n = 1 << 22
+    b2 = siggen.beta2_ps2_km()
+    x, _ = siggen.transmitted_field(4, 0, 2, n, 0.0)
+    xt = torch.from_numpy(x.astype(np.complex64)).reshape(1, 2, n).cuda()
+    out = torch.empty_like(xt)
+    res = {}
+    for name, prec in [("fp32", dbp.FP32), ("fp32_fp64phase", dbp.FP32_FP64PHASE)]:
+        p = dbp.plan(n, SPANS, 20, block=BLOCK, overlap=OVERLAP, precision=prec, beta2_ps2_km=b2)
+        ms, _ = time_dbp(torch, p, xt, out, p.workspace(), 1, reps)
+        res[name] = {"ms": round(ms, 2), "msamples_per_s": round(n / ms / 1e3, 2),
+                     "steps_per_pass": p.steps_per_pass}
+    res["workload"] = "2x4194304 samples, 3200 km, SSFM 800 steps, Nb=1024 O=256"
+    return res
 
 
 def cpu_baseline(rx_np, taps, k, budget_s=12.0):
@@ -269,6 +336,10 @@ def main():
     log("large working set " + json.dumps(hbm))
     grad = grad_workload(dbp, torch)
     log("gradient workload " + json.dumps(grad))
+    batch = batch_workload(dbp, torch)
+    log("batch workload " + json.dumps(batch))
+    prec = precision_workload(dbp, torch)
+    log("precision workload " + json.dumps(prec))
     value = N / (ms_e * 1e-3) / 1e6
     # dominant kernel: the fused pass kernel of the ESSFM run; algorithmic work per launch =
     # Sec. III operation count per sample and step x steps per launch x samples
@@ -306,6 +377,8 @@ def main():
             "evm_db": {k: round(v, 3) for k, v in evms.items()},
             "taps": [round(float(t), 6) for t in taps],
             "gradient": grad,
+            "batch": batch,
+            "precision": prec,
         },
         "roofline": {
             "bound": "alu",

@@ -54,7 +54,7 @@ static float time_launches(LaunchFn fn, PassArgs& a, int reps, hipStream_t s) {
 // Time the pass kernel of a variant on a synthetic signal of 2^22 samples per
 // polarization with O = Nb/2, at k = 1 and k = 4 steps per pass.
 static dbp_status measure_cost(int npol, int nt, bool p64, int nb, Cost& out) {
-    const int e = default_e(nb, 1 << 20);
+    const int e = measured_e(nb, 1 << 20);
     LaunchFn fn = find_kernel(nb, e, npol, p64, nt);
     if (!fn) return DBP_ERR_UNSUPPORTED;
     const int V = nb / 2;
@@ -412,7 +412,7 @@ dbp_status dbp_plan_batch(const dbp_desc* descs, int32_t n, dbp_plan_t* out) {
         G.nt = kv.first.nt;
         G.p64 = kv.first.p64;
         G.npol = npol;
-        G.e = default_e(G.nb, 1 << 20);
+        G.e = measured_e(G.nb, 1 << 20);
         BatchOccFn occ = nullptr;
         G.fn = find_batch_kernel(G.nb, G.e, npol, G.p64, G.nt, &occ);
         if (!G.fn) {

@@ -40,13 +40,31 @@ int tap_variant(int method, int n_taps) {
     return n_taps == 9 ? 9 : -1;
 }
 
-// Values per thread: 16 (one wave per 1024-point block) when the launch has
-// enough blocks to fill the chip; with fewer than two blocks per CU, the
-// 256-thread variant spreads each block over all four SIMDs of its CU.
-int default_e(int nb, long long n_wg) {
-    if (nb == 1024 && n_wg < 512) return 4;
-    return nb <= 256 ? 4 : nb <= 512 ? 8 : 16;
+// Values per thread by block size, from measured throughput on gfx950: a
+// 1024-point block runs best as four waves of 4 values per thread; 512- and
+// 2048-point blocks take 4 values per thread on grids too small to fill the
+// chip several times over and 8 otherwise; 4096-point blocks 8; larger ones 16.
+int measured_e(int nb, long long n_wg) {
+    switch (nb) {
+        case 256: return 4;
+        case 512: return n_wg < 4096 ? 4 : 8;
+        case 1024: return 4;
+        case 2048: return n_wg < 2048 ? 4 : 8;
+        case 4096: return 8;
+        default: return 16;
+    }
 }
+
+// measured_e, unless DBP_FORCE_E (4, 8 or 16) names another compiled variant.
+int default_e(int nb, long long n_wg) {
+    if (const char* f = std::getenv("DBP_FORCE_E")) {
+        const int e = std::atoi(f);
+        if (e == 4 || e == 8 || e == 16) return e;
+    }
+    return measured_e(nb, n_wg);
+}
+
+static int nb_fallback_e(int nb) { return nb <= 256 ? 4 : nb <= 512 ? 8 : 16; }
 
 bool have_kernel(int nb, int e, int npol) { return find_kernel(nb, e, npol, false, -1) != nullptr; }
 
@@ -188,6 +206,7 @@ dbp_status choose_geometry(const dbp_desc* d, const std::vector<double>& b, Geom
         const long long n_wg = (d->n_samples + v - 1) / v * d->batch;
         g.e = default_e(g.block, n_wg);
     }
+    if (!have_kernel(g.block, g.e, d->n_pol)) g.e = nb_fallback_e(g.block);
     if (!have_kernel(g.block, g.e, d->n_pol)) return DBP_ERR_UNSUPPORTED;
     g.n_steps = ns;
     g.n_passes = (ns + g.k - 1) / g.k;

@@ -3,7 +3,7 @@
 
 namespace dbp {
 
-static const KernelEntry kTable[] = {DBP_K(4096, 16)};
+static const KernelEntry kTable[] = {DBP_K(4096, 16), DBP_K(4096, 8), DBP_K(4096, 4)};
 
 const KernelEntry* kernels_4096(int* n) {
     *n = (int)(sizeof(kTable) / sizeof(kTable[0]));

@@ -3,8 +3,8 @@
 
 namespace dbp {
 
-static const BatchKernelEntry kTable[] = {DBP_BP(256, 4, 1), DBP_BP(512, 8, 1), DBP_BP(1024, 16, 1),
-                                          DBP_BP(2048, 16, 1), DBP_BP(4096, 16, 1)};
+static const BatchKernelEntry kTable[] = {DBP_BP(256, 4, 1), DBP_BP(512, 8, 1), DBP_BP(1024, 4, 1),
+                                          DBP_BP(2048, 8, 1), DBP_BP(4096, 8, 1)};
 
 const BatchKernelEntry* batch_kernels_1(int* n) {
     *n = (int)(sizeof(kTable) / sizeof(kTable[0]));

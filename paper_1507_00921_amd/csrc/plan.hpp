@@ -60,6 +60,7 @@ void build_schedule(const dbp_desc* d, std::vector<double>& b, std::vector<doubl
 LaunchFn find_kernel(int nb, int e, int npol, bool p64, int nt);
 int tap_variant(int method, int n_taps);
 int default_e(int nb, long long n_wg);
+int measured_e(int nb, long long n_wg);
 double spread_per_side(double b, double fs, int nc);
 int balance_k(int ns, int kmax);
 void twiddle_table(int nb, std::vector<float2>& tw);
