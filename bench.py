@@ -17,6 +17,7 @@ both EVMs and the oracle's CPU rate are reported beside it.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -50,14 +51,14 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def gpu_field(dbp, torch):
-    """Launch, forward-propagate (library, physical direction) and add noise."""
-    x, sym = siggen.transmitted_field(1, 0, 2, N, P_DBM)
+def gpu_field(dbp, torch, p_dbm=P_DBM):
+    """Launch at p_dbm, forward-propagate (library, physical direction, 100 steps per span)
+    and add ASE whose power is fixed at the 0 dBm, 20 dB OSNR value (ASE-limited link)."""
+    x, sym = siggen.transmitted_field(1, 0, 2, N, p_dbm)
     fwd = dbp.plan(N, SPANS, 100, forward=True, beta2_ps2_km=siggen.beta2_ps2_km())
     xt = torch.from_numpy(x.astype(np.complex64)).reshape(1, 2, N).cuda()
     rx = fwd.backprop(xt)
     torch.cuda.synchronize()
-    log(f"forward channel: 4000 steps, Nb={fwd.block} O={fwd.overlap} k={fwd.steps_per_pass}")
     r = rx.cpu().numpy().reshape(2, N).astype(np.complex128)
     r = siggen.add_awgn(siggen.rng(1, 0, 2), r, siggen.awgn_sigma2(siggen.dbm_to_w(0.0), OSNR_DB))
     return torch.from_numpy(r.astype(np.complex64)).reshape(1, 2, N).cuda(), sym
@@ -270,6 +271,17 @@ def precision_workload(dbp, torch, reps=3):
     return res
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "host"
+
+
 def cpu_baseline(rx_np, taps, k, budget_s=12.0):
     """The FP64 oracle on the host: ESSFM 40 steps, blocked like the GPU, on the full field."""
     from oracle import dbp_ref as R
@@ -288,24 +300,112 @@ def cpu_baseline(rx_np, taps, k, budget_s=12.0):
                       f"(single-threaded pocketfft), {el:.1f} s"}
 
 
+KERNEL_SOURCES = ["fft.hpp", "step_kernel.hpp", "registry.hpp", "kern_1024.hip"]
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "dbp_pass_kernel_1024_essfm_2x262144_traffic.md")
+
+
+def kernel_source_hash():
+    """sha256 over the sources of the dominant kernel (to tell whether stored counters are current)."""
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1507_00921_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def stored_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE, each scaled by the factor a plain 1 GiB copy gives), or
+    None when there is none or the kernel's sources changed since it was taken."""
+    try:
+        with open(TRAFFIC_PROFILE) as f:
+            text = f.read()
+        blob = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
+    except (OSError, IndexError, ValueError):
+        return None, "no stored counters"
+    if blob.get("source_sha256") != kernel_source_hash():
+        return None, "stored counters predate the current kernel sources"
+    return float(blob["traffic_bytes_per_launch"]), "FETCH_SIZE x %.3g + WRITE_SIZE x %.3g (copy-calibrated)" % (
+        blob["fetch_factor"], blob["write_factor"])
+
+
+def calibrate_copy():
+    """A plain device copy of 1 GiB, three times: the reference for the counters' scale."""
+    import torch
+    a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    log("copied 3 x 1 GiB")
+
+
+def evm_sweep_power(dbp, torch, powers):
+    """Launch-power sweep: per power the field is regenerated and forward-propagated, the
+    ESSFM taps are refitted and the EVM of each receiver is computed."""
+    b2 = siggen.beta2_ps2_km()
+    out = {}
+    for pw in powers:
+        rx, sym = gpu_field(dbp, torch, pw)
+        ssfm = dbp.plan(N, SPANS, 20, block=BLOCK, overlap=OVERLAP, beta2_ps2_km=b2)
+        target = ssfm.backprop(rx)
+        taps = fit_taps(dbp, torch, rx, target)
+        essfm = dbp.plan(N, SPANS, 1, taps=taps, block=BLOCK, overlap=OVERLAP, beta2_ps2_km=b2)
+        ssfm1 = dbp.plan(N, SPANS, 1, block=BLOCK, overlap=OVERLAP, beta2_ps2_km=b2)
+        cd = dbp.plan(N, 1, 1, span_km=80.0 * SPANS, gamma_w_km=0.0, block=8192, overlap=2048,
+                      beta2_ps2_km=b2)
+        out[pw] = {"essfm_1_per_span": evm_db(essfm.backprop(rx), sym),
+                   "ssfm_20_per_span": evm_db(target, sym),
+                   "ssfm_1_per_span": evm_db(ssfm1.backprop(rx), sym),
+                   "cd_only": evm_db(cd.backprop(rx), sym)}
+        log(f"{pw:+.0f} dBm EVM " + json.dumps({k: round(v, 3) for k, v in out[pw].items()}))
+    return out
+
+
+def ssfm_steps_sweep(dbp, torch, rx, sym, counts, reps=5):
+    """SSFM at several steps per span on the same field: EVM and time per DBP."""
+    b2 = siggen.beta2_ps2_km()
+    out = torch.empty_like(rx)
+    res = {}
+    for n in counts:
+        p = dbp.plan(N, SPANS, n, block=BLOCK, overlap=OVERLAP, beta2_ps2_km=b2)
+        e = evm_db(p.backprop(rx), sym)
+        ms, _ = time_dbp(torch, p, rx, out, p.workspace(), 2, reps)
+        res[n] = {"evm_db": round(e, 3), "ms": round(ms, 4), "msamples_per_s": round(N / ms / 1e3, 2)}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle's CPU baseline")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the 0 dBm ESSFM/SSFM headline (for profiler runs)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run a plain 1 GiB device copy three times and exit (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the backpropagation path is built and measured on a "
               "single MI355X (multi-GPU sharding is described, not built)", file=sys.stderr)
         sys.exit(2)
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
 
     import torch
     import paper_1507_00921_amd as dbp
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     b2 = siggen.beta2_ps2_km()
-    rx, sym = gpu_field(dbp, torch)
+
+    sweep = None
+    p_best = P_DBM
+    if not args.headline_only:
+        sweep = evm_sweep_power(dbp, torch, [-2.0, -1.0, 0.0, 1.0, 2.0, 3.0, 4.0])
+        p_best = min(sweep, key=lambda pw: sweep[pw]["ssfm_20_per_span"])
+    rx, sym = gpu_field(dbp, torch, p_best)
 
     ssfm = dbp.plan(N, SPANS, 20, block=BLOCK, overlap=OVERLAP, beta2_ps2_km=b2)
     target = ssfm.backprop(rx)
@@ -313,15 +413,8 @@ def main():
     taps = fit_taps(dbp, torch, rx, target)
     log(f"fitted taps {np.round(taps, 5).tolist()}")
     essfm = dbp.plan(N, SPANS, 1, taps=taps, block=BLOCK, overlap=OVERLAP, beta2_ps2_km=b2)
-    ssfm1 = dbp.plan(N, SPANS, 1, block=BLOCK, overlap=OVERLAP, beta2_ps2_km=b2)
-    cdonly = dbp.plan(N, 1, 1, span_km=80.0 * SPANS, gamma_w_km=0.0, block=8192, overlap=2048,
-                      beta2_ps2_km=b2)
-
-    evms = {"essfm_1_per_span": evm_db(essfm.backprop(rx), sym),
-            "ssfm_20_per_span": evm_db(target, sym),
-            "ssfm_1_per_span": evm_db(ssfm1.backprop(rx), sym),
-            "cd_only": evm_db(cdonly.backprop(rx), sym)}
-    log("EVM dB " + json.dumps({k: round(v, 3) for k, v in evms.items()}))
+    evm_e = evm_db(essfm.backprop(rx), sym)
+    evm_s = evm_db(target, sym)
 
     out = torch.empty_like(rx)
     ws = essfm.workspace()
@@ -330,17 +423,35 @@ def main():
     k_s = max(3, args.steps // 10)
     ms_s, _ = time_dbp(torch, ssfm, rx, out, ws_s, 2, k_s)
     log(f"ESSFM {ms_e:.4f} ms/DBP ({essfm.n_passes} launches), SSFM {ms_s:.3f} ms/DBP "
-        f"({ssfm.n_passes} launches)")
-
-    hbm = hbm_working_set(dbp, torch, rx, taps)
-    log("large working set " + json.dumps(hbm))
-    grad = grad_workload(dbp, torch)
-    log("gradient workload " + json.dumps(grad))
-    batch = batch_workload(dbp, torch)
-    log("batch workload " + json.dumps(batch))
-    prec = precision_workload(dbp, torch)
-    log("precision workload " + json.dumps(prec))
+        f"({ssfm.n_passes} launches), EVM {evm_e:.3f} / {evm_s:.3f} dB at {p_best:+.0f} dBm")
     value = N / (ms_e * 1e-3) / 1e6
+
+    extras = {}
+    if not args.headline_only:
+        steps = ssfm_steps_sweep(dbp, torch, rx, sym, [1, 2, 3, 4, 5, 6, 8, 10, 20])
+        log("SSFM steps/span sweep " + json.dumps(steps))
+        match = [n for n in sorted(steps) if steps[n]["evm_db"] <= evm_e]
+        n_eq = match[0] if match else None
+        extras["equal_evm"] = {
+            "launch_dbm": p_best,
+            "essfm_minus_ssfm20_db": round(evm_e - evm_s, 3),
+            "within_0p1_db": abs(evm_e - evm_s) <= 0.1,
+            "ssfm_steps_per_span_matching_essfm": n_eq,
+            "ssfm_matching": steps[n_eq] if n_eq else None,
+            "essfm_vs_matching_ssfm_speedup": round(steps[n_eq]["ms"] / ms_e, 2) if n_eq else None,
+            "ssfm_sweep": steps,
+        }
+        extras["evm_vs_launch_power_db"] = {f"{pw:+.0f}": {k: round(v, 3) for k, v in e.items()}
+                                            for pw, e in sweep.items()}
+        hbm = hbm_working_set(dbp, torch, rx, taps)
+        log("large working set " + json.dumps(hbm))
+        extras["gradient"] = grad_workload(dbp, torch)
+        log("gradient workload " + json.dumps(extras["gradient"]))
+        extras["batch"] = batch_workload(dbp, torch)
+        log("batch workload " + json.dumps(extras["batch"]))
+        extras["precision"] = precision_workload(dbp, torch)
+        log("precision workload " + json.dumps(extras["precision"]))
+
     # dominant kernel: the fused pass kernel of the ESSFM run; algorithmic work per launch =
     # Sec. III operation count per sample and step x steps per launch x samples
     launches = essfm.n_passes
@@ -349,6 +460,7 @@ def main():
     achieved_tflops = flops_launch / (avg_launch_ms * 1e-3) / 1e12
     bytes_launch = N * 2 * 8 * (BLOCK / (BLOCK - OVERLAP)) + N * 2 * 8
     achieved_gbs = bytes_launch / (avg_launch_ms * 1e-3) / 1e9
+    traffic, traffic_note = stored_traffic()
 
     res = {
         "metric": "DBP Msamples/s (both pols) at 3200 km, ESSFM vs SSFM at equal EVM; fwd+bwd ms",
@@ -362,23 +474,19 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
-        "data": "synthetic PM-QPSK, forward-propagated on the GPU, ASE at 20 dB OSNR",
+        "data": "synthetic PM-QPSK, forward-propagated on the GPU, ASE fixed at 20 dB OSNR for 0 dBm",
         "config": {
-            "workload": "PM-QPSK 28 GBd, 2x262144 samples, 40x80 km SMF (3200 km), 0 dBm; "
+            "workload": f"PM-QPSK 28 GBd, 2x262144 samples, 40x80 km SMF (3200 km), {p_best:+.0f} dBm; "
                         "ESSFM 1 step/span 9 taps vs SSFM 20 steps/span; overlap-save Nb=1024 O=256",
             "essfm": {"steps": essfm.n_steps, "steps_per_pass": essfm.steps_per_pass,
                       "launches": essfm.n_passes, "ms": round(ms_e, 5),
-                      "msamples_per_s": round(value, 2), "evm_db": round(evms["essfm_1_per_span"], 3)},
+                      "msamples_per_s": round(value, 2), "evm_db": round(evm_e, 3)},
             "ssfm": {"steps": ssfm.n_steps, "steps_per_pass": ssfm.steps_per_pass,
                      "launches": ssfm.n_passes, "ms": round(ms_s, 4),
-                     "msamples_per_s": round(N / (ms_s * 1e-3) / 1e6, 2),
-                     "evm_db": round(evms["ssfm_20_per_span"], 3)},
+                     "msamples_per_s": round(N / (ms_s * 1e-3) / 1e6, 2), "evm_db": round(evm_s, 3)},
             "essfm_vs_ssfm_speedup": round(ms_s / ms_e, 2),
-            "evm_db": {k: round(v, 3) for k, v in evms.items()},
             "taps": [round(float(t), 6) for t in taps],
-            "gradient": grad,
-            "batch": batch,
-            "precision": prec,
+            **extras,
         },
         "roofline": {
             "bound": "alu",
@@ -386,20 +494,23 @@ def main():
             "peak": FP32_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": round(achieved_tflops / FP32_PEAK_TFLOPS, 4),
-            "traffic": None,
+            "traffic": traffic,
+            "traffic_source": traffic_note,
             "kernel": "dbp_pass_kernel<1024,4,2,true,9>",
             "avg_launch_us": round(avg_launch_ms * 1e3, 3),
             "algorithmic_flops_per_launch": flops_launch,
             "algorithmic_bytes_per_launch": bytes_launch,
             "achieved_hbm_gbs": round(achieved_gbs, 1),
             "hbm_frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
-            "large_working_set": hbm,
+            "frac_of_nonpacked_fp32": round(achieved_tflops / (FP32_PEAK_TFLOPS / 2), 4),
         },
     }
-    if not args.no_cpu:
+    if not args.headline_only:
+        res["roofline"]["large_working_set"] = hbm
+    if not args.no_cpu and not args.headline_only:
         res["cpu_baseline"] = cpu_baseline(rx.cpu().numpy().reshape(2, N).astype(np.complex128), taps,
                                            essfm.steps_per_pass)
-        res["cpu_baseline"]["cpu"] = platform.processor() or "host"
+        res["cpu_baseline"]["cpu"] = cpu_model()
     print(json.dumps(res), flush=True)
 
 

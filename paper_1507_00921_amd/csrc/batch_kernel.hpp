@@ -97,8 +97,10 @@ __global__ __launch_bounds__(NB / E) void dbp_batch_kernel(BatchArgs a) {
                     const int* pr = a.progress + sg.prog_off + nb;
                     long long spins = 0;
                     for (;;) {
+                        // relaxed: an acquiring load would invalidate this XCD's L2 on
+                        // every poll; one acquire fence follows the whole wait
                         const int pv = __builtin_amdgcn_readfirstlane(
-                            __hip_atomic_load(pr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT));
+                            __hip_atomic_load(pr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
                         if (pv >= pass) break;
                         if (++spins > a.spin_limit) {
                             ok = 0;
@@ -116,8 +118,10 @@ __global__ __launch_bounds__(NB / E) void dbp_batch_kernel(BatchArgs a) {
                 __syncthreads();              // ok_s read by all before it is rewritten
             }
             if (!ok && t == 0) atomicOr(a.err, 1);
+            // pass 0 reads only the caller's input; later passes acquire what the awaited
+            // blocks released (one L2 invalidation per wave and item)
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         if (ok) {
             BlockJob j;
             j.src = pass == 0 ? a.in + sg.off : pass_dst(a, sg, pass - 1);
@@ -134,10 +138,11 @@ __global__ __launch_bounds__(NB / E) void dbp_batch_kernel(BatchArgs a) {
             j.ntaps = sg.ntaps;
             process_block<NB, E, NPOL, PHASE64, NT>(j, twr, sm);
         }
-        // every thread's stores are released at agent scope before any lane publishes
+        // every thread's stores are released at agent scope (one L2 writeback) before
+        // the progress counter is published with a plain atomic store
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         if constexpr (MULTI) __syncthreads();
-        __hip_atomic_store(a.progress + sg.prog_off + blk, pass + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(a.progress + sg.prog_off + blk, pass + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
