@@ -14,7 +14,7 @@ LIB = os.path.join(LIBDIR, "libdbp.so")
 INCLUDE = os.path.join(ROOT, "include")
 
 SOURCES = ["dbp.hip", "kern_small.hip", "kern_1024.hip", "kern_2048.hip", "kern_4096.hip",
-           "kern_large.hip", "kern_fir.hip",
+           "kern_large.hip", "kern_fir.hip", "kern_mfma.hip",
            "kern_batch1.hip", "kern_batch2.hip", "batch.hip"]
 
 HIPCC_FLAGS = [

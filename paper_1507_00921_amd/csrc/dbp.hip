@@ -16,6 +16,7 @@
 #include "plan.hpp"
 #include "registry.hpp"
 #include "fir_launch.hpp"
+#include "mfma_kernel.hpp"
 
 namespace dbp {
 
@@ -23,7 +24,8 @@ namespace dbp {
 
 LaunchFn find_kernel(int nb, int e, int npol, bool p64, int nt) {
     using Acc = const KernelEntry* (*)(int*);
-    static const Acc tables[] = {kernels_small, kernels_1024, kernels_2048, kernels_4096, kernels_large};
+    static const Acc tables[] = {kernels_small, kernels_1024, kernels_2048, kernels_4096, kernels_large,
+                                 kernels_mfma};
     for (Acc acc : tables) {
         int n = 0;
         const KernelEntry* t = acc(&n);
@@ -167,13 +169,16 @@ dbp_status choose_geometry(const dbp_desc* d, const std::vector<double>& b, Geom
         g.n_passes = ns;
         return DBP_OK;
     }
+    const bool split = d->precision == DBP_BF16X3;   // matrix-core DFT: Nb = 1024 only
     if (d->flags & DBP_FLAG_WHOLE) {
         if (!pow2(d->n_samples) || d->n_samples > max_block(d->n_pol) || d->n_samples < 256)
             return DBP_ERR_UNSUPPORTED;
+        if (split && d->n_samples != MF_NB) return DBP_ERR_UNSUPPORTED;
         g.block = (int)d->n_samples;
         g.overlap = 0;
         g.k = ns;
     } else if (d->block != 0) {
+        if (split && d->block != MF_NB) return DBP_ERR_UNSUPPORTED;
         g.block = d->block;
         g.overlap = d->overlap;
         g.k = d->steps_per_pass > 0 ? std::min(d->steps_per_pass, ns)
@@ -185,6 +190,7 @@ dbp_status choose_geometry(const dbp_desc* d, const std::vector<double>& b, Geom
         double smax = 0;
         for (double v : b) smax = std::max(smax, spread_per_side(v, d->fs_thz, nc));
         for (int nb = 256; nb <= std::min<long long>(max_block(d->n_pol), d->n_samples); nb *= 2) {
+            if (split && nb != MF_NB) continue;
             for (int k = 1; k <= ns; ++k) {
                 int o = 2 * (int)std::ceil(k * smax + kMargin);
                 if (o > nb / 2) break;
@@ -201,19 +207,77 @@ dbp_status choose_geometry(const dbp_desc* d, const std::vector<double>& b, Geom
         if (best == 1e300) return DBP_ERR_UNSUPPORTED;
         if (d->steps_per_pass > 0) g.k = std::min(d->steps_per_pass, ns);
     }
-    {
+    if (split) {
+        g.e = 0;
+        if (!find_kernel(MF_NB, 0, d->n_pol, true, -1)) return DBP_ERR_UNSUPPORTED;
+    } else {
         const long long v = g.block - g.overlap;
         const long long n_wg = (d->n_samples + v - 1) / v * d->batch;
         g.e = default_e(g.block, n_wg);
+        if (!have_kernel(g.block, g.e, d->n_pol)) g.e = nb_fallback_e(g.block);
+        if (!have_kernel(g.block, g.e, d->n_pol)) return DBP_ERR_UNSUPPORTED;
     }
-    if (!have_kernel(g.block, g.e, d->n_pol)) g.e = nb_fallback_e(g.block);
-    if (!have_kernel(g.block, g.e, d->n_pol)) return DBP_ERR_UNSUPPORTED;
     g.n_steps = ns;
     g.n_passes = (ns + g.k - 1) / g.k;
     return DBP_OK;
 }
 
 // ------------------------------------------------------------------ tables
+
+static uint16_t bf16_rne(float f) {
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return 0x7fc0;
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+static double bf16_value(uint16_t h) {
+    const uint32_t u = (uint32_t)h << 16;
+    float f;
+    std::memcpy(&f, &u, 4);
+    return f;
+}
+
+// Constant operand fragments of the split-precision DFT (mfma_kernel.hpp): for
+// each fragment and lane 8 BF16 slots (two per 32-bit word, low half first),
+// the hi part, and at a fixed offset the lo part v - hi.  Slots 0-3 multiply
+// real parts and 4-7 imaginary parts of the contracted index; entries of
+// W^{nk} are formed in FP64 from (nk mod N).
+void mfma_fragments(std::vector<uint32_t>& out) {
+    out.assign((size_t)MF_FRAGS * 4, 0u);
+    auto put = [&](size_t frag, int j, double v) {
+        const uint16_t hi = bf16_rne((float)v);
+        const uint16_t lo = bf16_rne((float)(v - bf16_value(hi)));
+        const size_t lo_frag = frag < (size_t)2 * MF_CF1 ? frag + MF_CF1 : frag + MF_CF2;
+        out[frag * 4 + j / 2] |= (uint32_t)hi << (16 * (j & 1));
+        out[lo_frag * 4 + j / 2] |= (uint32_t)lo << (16 * (j & 1));
+    };
+    // entry of the real 2x2 block of w = exp(-i th) acting on (re, im) of the input,
+    // giving the real (out_im = 0) or imaginary part of the product
+    auto coef = [](double th, int in_im, int out_im) {
+        if (in_im == out_im) return std::cos(th);
+        return in_im ? std::sin(th) : -std::sin(th);
+    };
+    for (int lane = 0; lane < 64; ++lane) {
+        const int g = lane >> 4, r = lane & 15;
+        for (int j = 0; j < 8; ++j) {
+            // 64-point product, B operand [kc][nt]: K = b = 16 kc + 4 g + (j & 3), N = c
+            for (int kc = 0; kc < 4; ++kc)
+                for (int nt = 0; nt < 8; ++nt) {
+                    const int b = 16 * kc + 4 * g + (j & 3), c = 16 * (nt & 3) + r;
+                    const double th = 2.0 * M_PI * ((b * c) % 64) / 64.0;
+                    put((size_t)(kc * 8 + nt) * 64 + lane, j, coef(th, j >> 2, nt >> 2));
+                }
+            // 16-point product, A operand [mt]: M = d = r, K = a = 4 g + (j & 3)
+            for (int mt = 0; mt < 2; ++mt) {
+                const int d = r, a = 4 * g + (j & 3);
+                const double th = 2.0 * M_PI * ((a * d) % 16) / 16.0;
+                put((size_t)2 * MF_CF1 + mt * 64 + lane, j, coef(th, j >> 2, mt));
+            }
+        }
+    }
+}
 
 void twiddle_table(int nb, std::vector<float2>& tw) {
     tw.resize(nb);
@@ -425,7 +489,7 @@ dbp_status dbp_plan(const dbp_desc* desc, dbp_plan_t* out) {
     *out = nullptr;
     dbp_status st = validate(desc);
     if (st != DBP_OK) return st;
-    if (desc->precision == DBP_BF16X3) return DBP_ERR_UNSUPPORTED;
+    if (desc->precision == DBP_BF16X3 && desc->linear == DBP_LINEAR_FIR) return DBP_ERR_UNSUPPORTED;
     Plan* p = new (std::nothrow) Plan();
     if (!p) return DBP_ERR_OOM;
     p->desc = *desc;
@@ -510,7 +574,18 @@ dbp_status dbp_plan(const dbp_desc* desc, dbp_plan_t* out) {
         if (hipMemcpy(*dptr, src, bytes, hipMemcpyHostToDevice) != hipSuccess) return DBP_ERR_HIP;
         return DBP_OK;
     };
-    if ((st = upload((void**)&p->d_h, htab.data(), htab.size() * sizeof(float2))) != DBP_OK ||
+    std::vector<uint32_t> frag;
+    if (desc->precision == DBP_BF16X3) {
+        mfma_fragments(frag);
+        int cu = 0;
+        if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess || cu < 1) {
+            delete p;
+            return DBP_ERR_HIP;
+        }
+        p->grid_cap = cu;   // one 8-wave workgroup per CU (the constants fill most of the LDS)
+    }
+    if ((st = upload((void**)&p->d_frag, frag.data(), frag.size() * sizeof(uint32_t))) != DBP_OK ||
+        (st = upload((void**)&p->d_h, htab.data(), htab.size() * sizeof(float2))) != DBP_OK ||
         (st = upload((void**)&p->d_tw, tw.data(), tw.size() * sizeof(float2))) != DBP_OK ||
         (st = upload((void**)&p->d_steps, steps.data(), steps.size() * sizeof(StepDev))) != DBP_OK ||
         (st = upload((void**)&p->d_taps, taps.data(), taps.size() * sizeof(float))) != DBP_OK ||
@@ -530,6 +605,7 @@ void dbp_destroy(dbp_plan_t p) {
     if (p->d_steps) (void)hipFree(p->d_steps);
     if (p->d_taps) (void)hipFree(p->d_taps);
     if (p->d_fir) (void)hipFree(p->d_fir);
+    if (p->d_frag) (void)hipFree(p->d_frag);
     destroy_batch(p);
     delete p;
 }
@@ -653,6 +729,8 @@ dbp_status dbp_backprop(dbp_plan_t p, const void* in, void* out, const float* ta
     a.tw = p->d_tw;
     a.taps = p->desc.method == DBP_ESSFM ? (taps ? taps : p->d_taps) : nullptr;
     a.ntaps = p->desc.method == DBP_ESSFM ? p->desc.n_taps : 1;
+    a.frag = p->d_frag;
+    const int grid = p->grid_cap > 0 ? std::min(p->grid_cap, a.n_wg) : a.n_wg;
 
     const int P = g.n_passes;
     const float2* src = (const float2*)in;
@@ -669,7 +747,7 @@ dbp_status dbp_backprop(dbp_plan_t p, const void* in, void* out, const float* ta
         a.out = dst;
         a.s0 = pass * g.k;
         a.ks = std::min(g.k, g.n_steps - a.s0);
-        if (fn(a, a.n_wg, s) != hipSuccess) return DBP_ERR_HIP;
+        if (fn(a, grid, s) != hipSuccess) return DBP_ERR_HIP;
         src = dst;
     }
     if (P == 1 && inplace) {

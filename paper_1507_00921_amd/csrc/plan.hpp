@@ -33,6 +33,8 @@ struct dbp_plan_s {
     dbp::StepDev* d_steps = nullptr;
     float* d_taps = nullptr;         // [N_s][n_taps]
     float2* d_fir = nullptr;         // FIR linear step: [N_s][n_fir]
+    void* d_frag = nullptr;          // split-precision DFT constant fragments
+    int grid_cap = 0;                // persistent launch width (split-precision kernel), 0: one workgroup per block
     std::vector<float> h_taps;
 
     // ragged batch (dbp_plan_batch)
@@ -65,6 +67,7 @@ double spread_per_side(double b, double fs, int nc);
 int balance_k(int ns, int kmax);
 void twiddle_table(int nb, std::vector<float2>& tw);
 void dispersion_table(int nb, double b, double fs, bool fp64, float2* out);
+void mfma_fragments(std::vector<uint32_t>& out);
 void destroy_batch(Plan* p);
 
 }  // namespace dbp

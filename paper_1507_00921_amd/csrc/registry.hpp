@@ -36,5 +36,6 @@ const KernelEntry* kernels_1024(int* n);
 const KernelEntry* kernels_2048(int* n);
 const KernelEntry* kernels_4096(int* n);
 const KernelEntry* kernels_large(int* n);
+const KernelEntry* kernels_mfma(int* n);   // BF16x3 matrix-core DFT, Nb = 1024 (e = 0)
 
 }  // namespace dbp

@@ -31,6 +31,7 @@ struct PassArgs {
     const float2* tw;       // exp(-2 pi i q / Nb), q < Nb
     const float* taps;      // [N_s][ntaps] or nullptr (SSFM: J = I)
     int ntaps;              // odd
+    const void* frag;       // split-precision variant: BF16 DFT constant fragments
 };
 
 // Workgroups are dealt round-robin to the 8 XCDs; give each XCD a contiguous

@@ -162,3 +162,22 @@ def test_planner_fir_design_matches_oracle(band):
     assert np.max(np.abs(got - ref)) < 1e-7 * max(1.0, np.max(np.abs(ref))) + 2e-8
     with pytest.raises(dbp.DbpError):
         dbp.fir_taps(d, 8)      # step out of range
+
+def test_split_precision_geometry_rules():
+    """The matrix-core (BF16x3) variant exists for 1024-point blocks with FFT linear steps
+    only; everything else is refused as unsupported before any device call."""
+    dbp = _lib_or_skip()
+    lib = dbp.lib()
+    assert dbp.choose_geometry(_desc(precision=dbp.BF16X3))[0] == 1024
+    assert dbp.choose_geometry(_desc(precision=dbp.BF16X3, block=1024, overlap=256)) == \
+        dbp.choose_geometry(_desc(block=1024, overlap=256))
+    for d in (_desc(precision=dbp.BF16X3, block=2048, overlap=512),
+              _desc(precision=dbp.BF16X3, n_samples=2048, whole=True)):
+        assert lib.dbp_choose_geometry(ctypes.byref(d), None, None, None) == 2
+    d = _desc(precision=dbp.BF16X3, linear=dbp.LINEAR_FIR, n_fir=33)
+    h = ctypes.c_void_p(123)
+    assert lib.dbp_plan(ctypes.byref(d), ctypes.byref(h)) == 2
+    assert h.value is None
+    arr = (dbp.Desc * 2)(_desc(n_samples=4096, precision=dbp.BF16X3), _desc(n_samples=4096))
+    assert lib.dbp_plan_batch(arr, 2, ctypes.byref(h)) == 2
+
