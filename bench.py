@@ -64,29 +64,32 @@ def gpu_field(dbp, torch, p_dbm=P_DBM):
     return torch.from_numpy(r.astype(np.complex64)).reshape(1, 2, N).cuda(), sym
 
 
-def fit_taps(dbp, torch, rx, target, n_fit=100000, iters=8):
+def fit_taps(dbp, torch, rx, target, n_fit=100000, iters=8, nc=NC, plan_kw=None):
     """ESSFM coefficient fit of Sec. IV: least squares against the multi-step SSFM output
     on the first n_fit samples; Nc+1 symmetric coefficients shared by every step,
-    Gauss-Newton with a forward-difference Jacobian, every evaluation on the GPU."""
+    Gauss-Newton with a forward-difference Jacobian, every evaluation on the GPU.
+    plan_kw: the ESSFM plan's link and geometry (default 1 step per span, Nb=1024 O=256)."""
     b2 = siggen.beta2_ps2_km()
+    kw = plan_kw or dict(n_spans=SPANS, steps_per_span=1, block=BLOCK, overlap=OVERLAP)
     sl = slice(BLOCK, n_fit)            # away from the circular wrap of the first block
 
     def full(c):
         return np.concatenate([c[:0:-1], c]).astype(np.float32)
 
     def resid(c):
-        p = dbp.plan(N, SPANS, 1, taps=full(c), block=BLOCK, overlap=OVERLAP, beta2_ps2_km=b2)
+        k = dict(kw)
+        p = dbp.plan(N, k.pop("n_spans"), k.pop("steps_per_span"), taps=full(c), beta2_ps2_km=b2, **k)
         y = p.backprop(rx)
         r = (y[0, :, sl] - target[0, :, sl]).reshape(-1)
         return torch.view_as_real(r).reshape(-1).double()
 
-    c = np.zeros(NC + 1)
+    c = np.zeros(nc + 1)
     c[0] = 1.0
     r0 = resid(c)
     for _ in range(iters):
         h = 1e-3
         cols = []
-        for i in range(NC + 1):
+        for i in range(nc + 1):
             cc = c.copy()
             cc[i] += h
             cols.append((resid(cc) - r0) / h)
@@ -99,6 +102,29 @@ def fit_taps(dbp, torch, rx, target, n_fit=100000, iters=8):
             break
         r0 = r1
     return full(c)
+
+
+def paper_arrangement(dbp, torch, rx, sym, target, sweep, reps=20):
+    """The experiment's own arrangement (Sec. IV): ESSFM with one step for the whole 40-span
+    link and Nc = 32 (65 taps, fitted like the 9-tap case) against SSFM with steps over two
+    spans (20 steps for the link) and over one span; geometry from the planner.  Times on
+    the headline field; EVMs per launch power from the sweep."""
+    b2 = siggen.beta2_ps2_km()
+    out = torch.empty_like(rx)
+    taps = fit_taps(dbp, torch, rx, target, nc=32, plan_kw=dict(n_spans=SPANS, steps_per_span=1,
+                                                                 spans_per_step=SPANS))
+    res = {}
+    for name, kw in [("essfm_1_step_link_nc32", dict(spans_per_step=SPANS, taps=taps)),
+                     ("ssfm_1_per_2_spans", dict(spans_per_step=2)),
+                     ("ssfm_1_per_span", dict())]:
+        p = dbp.plan(N, SPANS, 1, beta2_ps2_km=b2, **kw)
+        ms, _ = time_dbp(torch, p, rx, out, p.workspace(), 3, reps)
+        res[name] = {"ms": round(ms, 4), "msamples_per_s": round(N / ms / 1e3, 2),
+                     "geometry": [p.block, p.overlap, p.steps_per_pass], "steps": p.n_steps,
+                     "evm_db_by_launch_dbm": {f"{pw:+.0f}": round(e[name], 3) for pw, e in sweep.items()}}
+    best = {k: max(sweep, key=lambda pw: -sweep[pw][k]) for k in ("essfm_1_step_link_nc32", "ssfm_1_per_2_spans")}
+    res["best_launch_dbm"] = {k: v for k, v in best.items()}
+    return res
 
 
 def evm_db(y, sym):
@@ -254,20 +280,35 @@ def batch_workload(dbp, torch, reps=5):
 
 
 def precision_workload(dbp, torch, reps=3):
-    """Precision variants on 2 x 4194304 samples at 3200 km, SSFM 20 steps/span (800 steps):
-    samples/s for FP32 tables and phase vs FP64-generated tables and phase argument."""
+    """Precision variants on 2 x 4194304 samples at 3200 km, SSFM 20 steps/span (800 steps),
+    Nb=1024 O=256: FP32 tables and phase, FP64-generated tables and phase argument, and the
+    BF16x3 matrix-core DFT.  The field is launched at 0 dBm, forward-propagated by the library
+    and noise-loaded (20 dB OSNR); per variant the time per DBP, the EVM, and the relative L2
+    distance to the FP64-phase variant (the oracle comparison runs in the tests)."""
     n = 1 << 22
     b2 = siggen.beta2_ps2_km()
-    x, _ = siggen.transmitted_field(4, 0, 2, n, 0.0)
-    xt = torch.from_numpy(x.astype(np.complex64)).reshape(1, 2, n).cuda()
-    out = torch.empty_like(xt)
+    x, sym = siggen.transmitted_field(4, 0, 2, n, 0.0)
+    fwd = dbp.plan(n, SPANS, 100, forward=True, beta2_ps2_km=b2)
+    rx = fwd.backprop(torch.from_numpy(x.astype(np.complex64)).reshape(1, 2, n).cuda())
+    torch.cuda.synchronize()
+    r = rx.cpu().numpy().reshape(2, n).astype(np.complex128)
+    r = siggen.add_awgn(siggen.rng(4, 0, 2), r, siggen.awgn_sigma2(siggen.dbm_to_w(0.0), OSNR_DB))
+    xt = torch.from_numpy(r.astype(np.complex64)).reshape(1, 2, n).cuda()
+    del rx, r
     res = {}
-    for name, prec in [("fp32", dbp.FP32), ("fp32_fp64phase", dbp.FP32_FP64PHASE)]:
+    outs = {}
+    for name, prec in [("fp32", dbp.FP32), ("fp32_fp64phase", dbp.FP32_FP64PHASE), ("bf16x3", dbp.BF16X3)]:
         p = dbp.plan(n, SPANS, 20, block=BLOCK, overlap=OVERLAP, precision=prec, beta2_ps2_km=b2)
+        out = torch.empty_like(xt)
         ms, _ = time_dbp(torch, p, xt, out, p.workspace(), 1, reps)
+        outs[name] = out
         res[name] = {"ms": round(ms, 2), "msamples_per_s": round(n / ms / 1e3, 2),
-                     "steps_per_pass": p.steps_per_pass}
-    res["workload"] = "2x4194304 samples, 3200 km, SSFM 800 steps, Nb=1024 O=256"
+                     "steps_per_pass": p.steps_per_pass,
+                     "evm_db": round(siggen.evm_db(out.cpu().numpy().reshape(2, n).astype(np.complex128), sym), 4)}
+    ref = outs["fp32_fp64phase"]
+    for name in ("fp32", "bf16x3"):
+        res[name]["rel_l2_vs_fp32_fp64phase"] = float(f"{float((outs[name] - ref).norm() / ref.norm()):.3e}")
+    res["workload"] = "2x4194304 samples, 3200 km, SSFM 800 steps, Nb=1024 O=256, 0 dBm, 20 dB OSNR"
     return res
 
 
@@ -354,10 +395,17 @@ def evm_sweep_power(dbp, torch, powers):
         ssfm1 = dbp.plan(N, SPANS, 1, block=BLOCK, overlap=OVERLAP, beta2_ps2_km=b2)
         cd = dbp.plan(N, 1, 1, span_km=80.0 * SPANS, gamma_w_km=0.0, block=8192, overlap=2048,
                       beta2_ps2_km=b2)
+        # the experiment's arrangement: one ESSFM step for the link (Nc = 32), SSFM over 2 spans
+        taps_link = fit_taps(dbp, torch, rx, target, nc=32,
+                             plan_kw=dict(n_spans=SPANS, steps_per_span=1, spans_per_step=SPANS))
+        essfm_link = dbp.plan(N, SPANS, 1, spans_per_step=SPANS, taps=taps_link, beta2_ps2_km=b2)
+        ssfm_2span = dbp.plan(N, SPANS, 1, spans_per_step=2, beta2_ps2_km=b2)
         out[pw] = {"essfm_1_per_span": evm_db(essfm.backprop(rx), sym),
                    "ssfm_20_per_span": evm_db(target, sym),
                    "ssfm_1_per_span": evm_db(ssfm1.backprop(rx), sym),
-                   "cd_only": evm_db(cd.backprop(rx), sym)}
+                   "cd_only": evm_db(cd.backprop(rx), sym),
+                   "essfm_1_step_link_nc32": evm_db(essfm_link.backprop(rx), sym),
+                   "ssfm_1_per_2_spans": evm_db(ssfm_2span.backprop(rx), sym)}
         log(f"{pw:+.0f} dBm EVM " + json.dumps({k: round(v, 3) for k, v in out[pw].items()}))
     return out
 
@@ -441,6 +489,8 @@ def main():
             "essfm_vs_matching_ssfm_speedup": round(steps[n_eq]["ms"] / ms_e, 2) if n_eq else None,
             "ssfm_sweep": steps,
         }
+        extras["paper_arrangement"] = paper_arrangement(dbp, torch, rx, sym, target, sweep)
+        log("paper arrangement " + json.dumps(extras["paper_arrangement"]))
         extras["evm_vs_launch_power_db"] = {f"{pw:+.0f}": {k: round(v, 3) for k, v in e.items()}
                                             for pw, e in sweep.items()}
         hbm = hbm_working_set(dbp, torch, rx, taps)

@@ -108,6 +108,12 @@ typedef struct dbp_desc {
     int32_t steps_per_pass;   /* k >= 1; 0: chosen by the planner */
     int32_t precision;        /* dbp_precision */
     uint32_t flags;           /* DBP_FLAG_* */
+    int32_t spans_per_step;   /* 1 (or 0): steps_per_span steps in every span.  m > 1: each
+                                 step covers m whole spans (steps_per_span must be 1 and m
+                                 must divide n_spans; N_s = n_spans / m), as in the
+                                 experiment of Sec. IV; such a step applies the dispersion of
+                                 its m spans and one nonlinear phase weighted by the sum of
+                                 their effective lengths, m (1 - e^{-alpha L}) / alpha */
 } dbp_desc;
 
 #define DBP_MAX_TAPS 129
@@ -142,8 +148,9 @@ dbp_status dbp_choose_geometry(const dbp_desc* desc, int32_t* block, int32_t* ov
                                int32_t* steps_per_pass);
 
 /* Host-only: the FP64 step schedule for desc: b[s] = +-beta2 dz and
- * phi[s] = +-gamma exp(-alpha z_a) dz_eff for s < N_s (arrays of n entries;
- * returns DBP_ERR_INVALID_ARG if n < N_s). */
+ * phi[s] = +-gamma exp(-alpha z_a) dz_eff for s < N_s (steps covering m whole
+ * spans: +-beta2 m L and +-gamma m L_eff(L)); arrays of n entries, returns
+ * DBP_ERR_INVALID_ARG if n < N_s. */
 dbp_status dbp_schedule(const dbp_desc* desc, double* b, double* phi, int32_t n);
 
 /* Host-only: the designed FIR taps (desc->fir == NULL, linear == DBP_LINEAR_FIR)

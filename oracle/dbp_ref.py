@@ -118,35 +118,48 @@ def effective_length(dz: float, alpha: float) -> float:
 
 def schedule(n_spans: int, span_km: float, steps_per_span: int, beta2_ps2_km: float,
              gamma_w_km: float, alpha_db_km: float, backward: bool = True,
-             taps: Optional[Sequence] = None) -> list[Step]:
+             taps: Optional[Sequence] = None, spans_per_step: int = 1) -> list[Step]:
     """Step list for a homogeneous link (Sec. II step parameters; backward = DBP).
 
     taps: None (SSFM), one tap vector for every step, or one per step.
+    spans_per_step > 1 (with steps_per_span = 1): each step covers that many whole
+    spans, as in the experiment of Sec. IV (one step per two spans, one step for the
+    whole link).  Such a step applies the dispersion of all its spans at once and one
+    nonlinear phase whose weight is the sum of the spans' effective lengths (each
+    span's power restarts at its amplifier, so each contributes its full Delta z_eff).
     """
-    dz = span_km / steps_per_span
     a = alpha_lin(alpha_db_km)
-    leff = effective_length(dz, a)
-    n_steps = n_spans * steps_per_span
+    m = int(spans_per_step)
+    if m < 1 or (m > 1 and (steps_per_span != 1 or n_spans % m != 0)):
+        raise ValueError("spans_per_step needs one step per span and must divide n_spans")
+    if m > 1:
+        n_steps = n_spans // m
+        sign = -1.0 if backward else 1.0
+        leff = effective_length(span_km, a)
+        steps_b = [sign * beta2_ps2_km * span_km * m] * n_steps
+        steps_phi = [sign * gamma_w_km * leff * m] * n_steps
+    else:
+        dz = span_km / steps_per_span
+        leff = effective_length(dz, a)
+        n_steps = n_spans * steps_per_span
+        steps_b, steps_phi = [], []
+        for _span in range(n_spans):
+            for i in range(steps_per_span):
+                if backward:
+                    z_a = span_km - (i + 1) * dz     # transmitter-side end of segment i
+                    sign = -1.0
+                else:
+                    z_a = i * dz
+                    sign = 1.0
+                steps_b.append(sign * beta2_ps2_km * dz)
+                steps_phi.append(sign * gamma_w_km * math.exp(-a * z_a) * leff)
     per_step_taps = None
     if taps is not None:
         t = np.asarray(taps, dtype=np.float64)
         per_step_taps = [t] * n_steps if t.ndim == 1 else [np.asarray(v) for v in t]
         assert len(per_step_taps) == n_steps
-    out = []
-    s = 0
-    for _span in range(n_spans):
-        for i in range(steps_per_span):
-            if backward:
-                z_a = span_km - (i + 1) * dz     # transmitter-side end of segment i
-                sign = -1.0
-            else:
-                z_a = i * dz
-                sign = 1.0
-            w = None if per_step_taps is None else per_step_taps[s]
-            out.append(Step(b=sign * beta2_ps2_km * dz,
-                            phi=sign * gamma_w_km * math.exp(-a * z_a) * leff, w=w))
-            s += 1
-    return out
+    return [Step(b=steps_b[s], phi=steps_phi[s], w=None if per_step_taps is None else per_step_taps[s])
+            for s in range(n_steps)]
 
 
 # --------------------------------------------------------------------------- cascades

@@ -43,7 +43,7 @@ class Desc(ctypes.Structure):
         ("method", c_int32), ("n_taps", c_int32), ("taps", POINTER(c_float)), ("taps_per_step", c_int32),
         ("linear", c_int32), ("n_fir", c_int32), ("fir", POINTER(c_float)), ("fir_per_step", c_int32),
         ("fir_band_thz", c_double), ("block", c_int32), ("overlap", c_int32), ("steps_per_pass", c_int32),
-        ("precision", c_int32), ("flags", c_uint32),
+        ("precision", c_int32), ("flags", c_uint32), ("spans_per_step", c_int32),
     ]
 
 
@@ -110,7 +110,7 @@ def make_desc(n_samples: int, n_spans: int, steps_per_span: int = 1, *, n_pol: i
               n_fir: int = 0, fir_band_thz: float = 0.0, linear: int = LINEAR_FFT, block: int = 0,
               overlap: int = 0,
               steps_per_pass: int = 0, precision: int = FP32_FP64PHASE, forward: bool = False,
-              whole: bool = False):
+              whole: bool = False, spans_per_step: int = 1):
     """Build a Desc.  taps (ESSFM) and fir are host arrays kept alive on the returned object."""
     d = Desc()
     lib().dbp_desc_init(ctypes.byref(d))
@@ -142,13 +142,15 @@ def make_desc(n_samples: int, n_spans: int, steps_per_span: int = 1, *, n_pol: i
     d.block, d.overlap, d.steps_per_pass = block, overlap, steps_per_pass
     d.precision = precision
     d.flags = (FLAG_FORWARD if forward else 0) | (FLAG_WHOLE if whole else 0)
+    d.spans_per_step = spans_per_step
     d._keep = keep
     return d
 
 
 def schedule(desc: Desc):
     """Host-only FP64 step schedule (b, phi) the planner builds for desc."""
-    ns = desc.n_spans * desc.steps_per_span
+    m = desc.spans_per_step
+    ns = desc.n_spans // m if m > 1 else desc.n_spans * desc.steps_per_span
     b = (c_double * ns)()
     p = (c_double * ns)()
     _check(lib().dbp_schedule(ctypes.byref(desc), b, p, ns), "dbp_schedule")

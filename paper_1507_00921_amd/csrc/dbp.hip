@@ -102,6 +102,9 @@ dbp_status validate(const dbp_desc* d) {
     if (d->precision < DBP_FP32 || d->precision > DBP_BF16X3) return DBP_ERR_INVALID_ARG;
     if (d->flags & ~(DBP_FLAG_FORWARD | DBP_FLAG_WHOLE)) return DBP_ERR_INVALID_ARG;
     if (d->steps_per_pass < 0) return DBP_ERR_INVALID_ARG;
+    if (d->spans_per_step < 0) return DBP_ERR_INVALID_ARG;
+    if (d->spans_per_step > 1 && (d->steps_per_span != 1 || d->n_spans % d->spans_per_step != 0))
+        return DBP_ERR_INVALID_ARG;
     if (d->block != 0 && !(d->flags & DBP_FLAG_WHOLE)) {
         if (!pow2(d->block)) return DBP_ERR_INVALID_ARG;
         if (d->overlap < 0 || (d->overlap % 2) != 0 || d->overlap >= d->block) return DBP_ERR_INVALID_ARG;
@@ -113,6 +116,18 @@ dbp_status validate(const dbp_desc* d) {
 // ------------------------------------------------------------------ schedule
 
 void build_schedule(const dbp_desc* d, std::vector<double>& b, std::vector<double>& phi) {
+    const bool fwd_dir = (d->flags & DBP_FLAG_FORWARD) != 0;
+    if (d->spans_per_step > 1) {
+        // steps over m whole spans: the m spans' dispersion at once, one nonlinear phase
+        // weighted by the sum of their effective lengths (each span restarts at full power)
+        const int m = d->spans_per_step;
+        const double alpha = d->alpha_db_km * std::log(10.0) / 10.0;
+        const double leff = alpha == 0.0 ? d->span_km : -std::expm1(-alpha * d->span_km) / alpha;
+        const double sign = fwd_dir ? 1.0 : -1.0;
+        b.assign(d->n_spans / m, sign * d->beta2_ps2_km * d->span_km * m);
+        phi.assign(d->n_spans / m, sign * d->gamma_w_km * leff * m);
+        return;
+    }
     const int n = d->steps_per_span;
     const int ns = d->n_spans * n;
     const double dz = d->span_km / n;
@@ -424,6 +439,7 @@ void dbp_desc_init(dbp_desc* d) {
     d->linear = DBP_LINEAR_FFT;
     d->n_fir = 1;
     d->precision = DBP_FP32_FP64PHASE;
+    d->spans_per_step = 1;
 }
 
 const char* dbp_status_string(dbp_status s) {

@@ -99,6 +99,9 @@ def _desc(**kw):
     lambda d: (setattr(d, "block", 1024), setattr(d, "overlap", 1024)),    # overlap >= block
     lambda d: (setattr(d, "block", 1024), setattr(d, "overlap", 256), setattr(d, "n_samples", 512)),
     lambda d: setattr(d, "steps_per_pass", -1),
+    lambda d: setattr(d, "spans_per_step", -2),
+    lambda d: setattr(d, "spans_per_step", 3),                            # does not divide 40 spans
+    lambda d: (setattr(d, "spans_per_step", 2), setattr(d, "steps_per_span", 2)),
 ])
 def test_invalid_descriptors_rejected_without_device(mutate):
     dbp = _lib_or_skip()
@@ -120,12 +123,15 @@ def test_null_arguments():
     lib.dbp_destroy(None)
 
 
-@pytest.mark.parametrize("steps_per_span,forward", [(1, False), (20, False), (7, True)])
-def test_planner_schedule_matches_oracle(steps_per_span, forward):
+@pytest.mark.parametrize("steps_per_span,forward,m", [(1, False, 1), (20, False, 1), (7, True, 1),
+                                                      (1, False, 2), (1, True, 8), (1, False, 40)])
+def test_planner_schedule_matches_oracle(steps_per_span, forward, m):
     dbp = _lib_or_skip()
-    d = _desc(steps_per_span=steps_per_span, forward=forward)
+    d = _desc(steps_per_span=steps_per_span, forward=forward, spans_per_step=m)
     b, phi = dbp.schedule(d)
-    ref = R.schedule(40, 80.0, steps_per_span, siggen.beta2_ps2_km(), 1.3, 0.2, backward=not forward)
+    ref = R.schedule(40, 80.0, steps_per_span, siggen.beta2_ps2_km(), 1.3, 0.2, backward=not forward,
+                     spans_per_step=m)
+    assert len(b) == len(ref)
     assert np.allclose(b, [s.b for s in ref], rtol=1e-15, atol=0)
     assert np.allclose(phi, [s.phi for s in ref], rtol=1e-14, atol=0)
 

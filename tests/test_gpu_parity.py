@@ -198,3 +198,20 @@ def test_gamma_zero_round_trip_on_gpu(dbp):
     b = dbp.plan(n, 5, 2, whole=True, gamma_w_km=0.0, beta2_ps2_km=B2)
     y = _from_gpu(b.backprop(f.backprop(_to_gpu(x))), (2, n))
     assert rel_l2(y, x) <= 1e-5
+
+
+@pytest.mark.parametrize("m,taps_nc,n", [(8, 32, 20000), (4, 4, 12288), (2, None, 9000)])
+def test_multi_span_steps_parity(dbp, m, taps_nc, n):
+    """Steps covering m whole spans (Sec. IV's arrangement: one step for several spans),
+    including one ESSFM step over 8 spans with 65 taps on 8192-point blocks."""
+    taps = None if taps_nc is None else siggen.symmetric_taps(siggen.rng(1, m, 9), taps_nc)
+    x, _ = received(1, 40 + m, 2, n, 2.0, 8, 20)
+    p = dbp.plan(n, 8, 1, spans_per_step=m, taps=taps, beta2_ps2_km=B2)
+    y = _from_gpu(p.backprop(_to_gpu(x)), x.shape)
+    t = None if taps is None else np.asarray(taps, np.float32).astype(np.float64)
+    steps = R.schedule(8, 80.0, 1, B2, siggen.GAMMA_W_KM, siggen.ALPHA_DB_KM, taps=t, spans_per_step=m)
+    ref = R.run_blocked(x, steps, FS, p.block, p.overlap, p.steps_per_pass)
+    err = rel_l2(y, ref)
+    print(f"multi-span m={m} steps={len(steps)} Nb={p.block} O={p.overlap} k={p.steps_per_pass}: rel L2 {err:.3e}")
+    assert len(steps) == p.n_steps == 8 // m
+    assert err <= 1e-5
