@@ -342,7 +342,7 @@ def cpu_baseline(rx_np, taps, k, budget_s=12.0):
 
 
 KERNEL_SOURCES = ["fft.hpp", "step_kernel.hpp", "registry.hpp", "kern_1024.hip"]
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "dbp_pass_kernel_1024_essfm_2x262144_traffic.md")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "pass_kernel_1024_essfm_2x262144_traffic.md")
 
 
 def kernel_source_hash():
@@ -354,7 +354,7 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def stored_traffic():
+def stored_traffic(kernel):
     """HBM bytes per launch of the dominant kernel from the committed counter summary
     (FETCH_SIZE and WRITE_SIZE, each scaled by the factor a plain 1 GiB copy gives), or
     None when there is none or the kernel's sources changed since it was taken."""
@@ -364,8 +364,8 @@ def stored_traffic():
         blob = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
     except (OSError, IndexError, ValueError):
         return None, "no stored counters"
-    if blob.get("source_sha256") != kernel_source_hash():
-        return None, "stored counters predate the current kernel sources"
+    if blob.get("source_sha256") != kernel_source_hash() or blob.get("kernel") != kernel:
+        return None, "stored counters predate the current kernel sources or name another kernel"
     return float(blob["traffic_bytes_per_launch"]), "FETCH_SIZE x %.3g + WRITE_SIZE x %.3g (copy-calibrated)" % (
         blob["fetch_factor"], blob["write_factor"])
 
@@ -510,7 +510,7 @@ def main():
     achieved_tflops = flops_launch / (avg_launch_ms * 1e-3) / 1e12
     bytes_launch = N * 2 * 8 * (BLOCK / (BLOCK - OVERLAP)) + N * 2 * 8
     achieved_gbs = bytes_launch / (avg_launch_ms * 1e-3) / 1e9
-    traffic, traffic_note = stored_traffic()
+    traffic, traffic_note = stored_traffic(essfm.kernel)
 
     res = {
         "metric": "DBP Msamples/s (both pols) at 3200 km, ESSFM vs SSFM at equal EVM; fwd+bwd ms",
@@ -546,7 +546,7 @@ def main():
             "frac": round(achieved_tflops / FP32_PEAK_TFLOPS, 4),
             "traffic": traffic,
             "traffic_source": traffic_note,
-            "kernel": "dbp_pass_kernel<1024,4,2,true,9>",
+            "kernel": essfm.kernel,
             "avg_launch_us": round(avg_launch_ms * 1e3, 3),
             "algorithmic_flops_per_launch": flops_launch,
             "algorithmic_bytes_per_launch": bytes_launch,

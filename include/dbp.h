@@ -137,6 +137,11 @@ dbp_status dbp_plan(const dbp_desc* desc, dbp_plan_t* out);
  * ensure no call using the plan is still running on any stream. */
 void dbp_destroy(dbp_plan_t plan);
 
+/* Name of the kernel variant the plan launches for its steps, in the form the
+ * profiler reports template kernels (e.g. "dbp_pass_kernel<1024, 4, 2, true, 9>");
+ * owned by the plan, valid until dbp_destroy; "" for NULL. */
+const char* dbp_plan_kernel(dbp_plan_t plan);
+
 /* Geometry the plan uses: block Nb, overlap O, steps per pass k, total steps
  * N_s, number of passes.  Any pointer may be NULL. */
 dbp_status dbp_plan_geometry(dbp_plan_t plan, int32_t* block, int32_t* overlap,

@@ -66,6 +66,8 @@ def lib():
         L.dbp_destroy.restype = None
         L.dbp_plan_geometry.argtypes = [c_void_p] + [POINTER(c_int32)] * 5
         L.dbp_plan_geometry.restype = c_int32
+        L.dbp_plan_kernel.argtypes = [c_void_p]
+        L.dbp_plan_kernel.restype = ctypes.c_char_p
         L.dbp_choose_geometry.argtypes = [POINTER(Desc)] + [POINTER(c_int32)] * 3
         L.dbp_choose_geometry.restype = c_int32
         L.dbp_schedule.argtypes = [POINTER(Desc), POINTER(c_double), POINTER(c_double), c_int32]
@@ -197,6 +199,7 @@ class Plan:
                                        ctypes.byref(ns), ctypes.byref(npass)), "dbp_plan_geometry")
         self.block, self.overlap, self.steps_per_pass = nb.value, o.value, k.value
         self.n_steps, self.n_passes = ns.value, npass.value
+        self.kernel = lib().dbp_plan_kernel(h).decode()
         self.shape = (desc.batch, desc.n_pol, desc.n_samples)
 
     def close(self):

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstdlib>
+#include <cstdio>
 #include <cstring>
 #include <map>
 #include <new>
@@ -22,7 +23,7 @@ namespace dbp {
 
 // ------------------------------------------------------------------ kernel registry
 
-LaunchFn find_kernel(int nb, int e, int npol, bool p64, int nt) {
+LaunchFn find_kernel(int nb, int e, int npol, bool p64, int nt, bool split) {
     using Acc = const KernelEntry* (*)(int*);
     static const Acc tables[] = {kernels_small, kernels_1024, kernels_2048, kernels_4096, kernels_large,
                                  kernels_mfma};
@@ -30,7 +31,8 @@ LaunchFn find_kernel(int nb, int e, int npol, bool p64, int nt) {
         int n = 0;
         const KernelEntry* t = acc(&n);
         for (int i = 0; i < n; ++i)
-            if (t[i].nb == nb && t[i].e == e && t[i].npol == npol && t[i].p64 == p64 && t[i].nt == nt)
+            if (t[i].nb == nb && t[i].e == e && t[i].npol == npol && t[i].p64 == p64 && t[i].nt == nt &&
+                t[i].split == split)
                 return t[i].fn;
     }
     return nullptr;
@@ -64,6 +66,17 @@ int default_e(int nb, long long n_wg) {
         if (e == 4 || e == 8 || e == 16) return e;
     }
     return measured_e(nb, n_wg);
+}
+
+// Polarization-split blocks: measured on the 2x262144 workload at Nb = 1024
+// (342 blocks), SSFM runs 3% faster split and ESSFM 50% slower (the tap filter
+// then reads both groups' intensities), so only SSFM launches with fewer blocks
+// than two per CU are split.  DBP_FORCE_SPLIT=0/1 overrides where a split
+// variant exists.
+static bool default_split(int nb, int e, int npol, int nt, long long n_wg) {
+    if (npol != 2 || !find_kernel(nb, e, 2, false, -1, true)) return false;
+    if (const char* f = std::getenv("DBP_FORCE_SPLIT")) return std::atoi(f) != 0;
+    return nt == 0 && n_wg < 512;
 }
 
 static int nb_fallback_e(int nb) { return nb <= 256 ? 4 : nb <= 512 ? 8 : 16; }
@@ -231,6 +244,7 @@ dbp_status choose_geometry(const dbp_desc* d, const std::vector<double>& b, Geom
         g.e = default_e(g.block, n_wg);
         if (!have_kernel(g.block, g.e, d->n_pol)) g.e = nb_fallback_e(g.block);
         if (!have_kernel(g.block, g.e, d->n_pol)) return DBP_ERR_UNSUPPORTED;
+        g.split = default_split(g.block, g.e, d->n_pol, tap_variant(d->method, d->n_taps), n_wg);
     }
     g.n_steps = ns;
     g.n_passes = (ns + g.k - 1) / g.k;
@@ -521,8 +535,22 @@ dbp_status dbp_plan(const dbp_desc* desc, dbp_plan_t* out) {
     const int nb = p->geo.block;
     const bool fp64 = desc->precision != DBP_FP32;
     const bool fir_mode = desc->linear == DBP_LINEAR_FIR;
-    if (!fir_mode)
-        p->launch = (void*)find_kernel(nb, p->geo.e, desc->n_pol, fp64, tap_variant(desc->method, desc->n_taps));
+    if (!fir_mode) {
+        const int nt = tap_variant(desc->method, desc->n_taps);
+        p->launch = (void*)find_kernel(nb, p->geo.e, desc->n_pol, fp64, nt, p->geo.split);
+        const char* b = fp64 ? "true" : "false";
+        if (desc->precision == DBP_BF16X3)
+            std::snprintf(p->kernel_name, sizeof(p->kernel_name), "dbp_mfma_pass_kernel<%d, true, %d>",
+                          desc->n_pol, nt);
+        else if (p->geo.split)
+            std::snprintf(p->kernel_name, sizeof(p->kernel_name), "dbp_pass_kernel_split<%d, %d, %s, %d>", nb,
+                          p->geo.e, b, nt);
+        else
+            std::snprintf(p->kernel_name, sizeof(p->kernel_name), "dbp_pass_kernel<%d, %d, %d, %s, %d>", nb,
+                          p->geo.e, desc->n_pol, b, nt);
+    } else {
+        std::snprintf(p->kernel_name, sizeof(p->kernel_name), "fir_step_kernel<%d>", desc->n_pol);
+    }
 
     std::vector<float2> fir;
     if (fir_mode) {
@@ -625,6 +653,8 @@ void dbp_destroy(dbp_plan_t p) {
     destroy_batch(p);
     delete p;
 }
+
+const char* dbp_plan_kernel(dbp_plan_t p) { return p ? p->kernel_name : ""; }
 
 dbp_status dbp_plan_geometry(dbp_plan_t p, int32_t* block, int32_t* overlap, int32_t* k,
                              int32_t* n_steps, int32_t* n_passes) {

@@ -3,7 +3,7 @@
 
 namespace dbp {
 
-static const KernelEntry kTable[] = {DBP_K(1024, 16), DBP_K(1024, 8), DBP_K(1024, 4)};
+static const KernelEntry kTable[] = {DBP_K(1024, 16), DBP_K(1024, 8), DBP_K(1024, 4), DBP_S(1024, 4)};
 
 const KernelEntry* kernels_1024(int* n) {
     *n = (int)(sizeof(kTable) / sizeof(kTable[0]));

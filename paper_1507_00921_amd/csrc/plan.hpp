@@ -14,6 +14,7 @@ struct Geometry {
     int overlap = 0;    // O
     int k = 1;          // steps per pass
     int e = 16;         // complex values per thread per polarization in the step kernel
+    bool split = false; // polarization-split blocks
     int n_steps = 0;    // N_s
     int n_passes = 0;
 };
@@ -35,6 +36,7 @@ struct dbp_plan_s {
     float2* d_fir = nullptr;         // FIR linear step: [N_s][n_fir]
     void* d_frag = nullptr;          // split-precision DFT constant fragments
     int grid_cap = 0;                // persistent launch width (split-precision kernel), 0: one workgroup per block
+    char kernel_name[96] = {0};      // the pass-kernel variant, as the profiler names it
     std::vector<float> h_taps;
 
     // ragged batch (dbp_plan_batch)
@@ -59,7 +61,7 @@ using LaunchFn = hipError_t (*)(const PassArgs&, int grid, hipStream_t);
 constexpr int kMargin = 16;
 dbp_status validate(const dbp_desc* d);
 void build_schedule(const dbp_desc* d, std::vector<double>& b, std::vector<double>& phi);
-LaunchFn find_kernel(int nb, int e, int npol, bool p64, int nt);
+LaunchFn find_kernel(int nb, int e, int npol, bool p64, int nt, bool split = false);
 int tap_variant(int method, int n_taps);
 int default_e(int nb, long long n_wg);
 int measured_e(int nb, long long n_wg);

@@ -18,6 +18,7 @@ struct KernelEntry {
     bool p64;
     int nt;          // compile-time taps: 0 SSFM, > 0 fixed, -1 run time
     LaunchFn fn;
+    bool split;      // polarization-split blocks (two thread groups, one per polarization)
 };
 
 template <int NB, int E, int NPOL, bool P64, int NT>
@@ -26,7 +27,18 @@ hipError_t launch_pass(const PassArgs& a, int grid, hipStream_t s) {
     return hipGetLastError();
 }
 
-#define DBP_KV(NB, E, NPOL, P64, NT) {NB, E, NPOL, P64, NT, launch_pass<NB, E, NPOL, P64, NT>}
+#define DBP_KV(NB, E, NPOL, P64, NT) {NB, E, NPOL, P64, NT, launch_pass<NB, E, NPOL, P64, NT>, false}
+
+template <int NB, int E, bool P64, int NT>
+hipError_t launch_split(const PassArgs& a, int grid, hipStream_t s) {
+    hipLaunchKernelGGL((dbp_pass_kernel_split<NB, E, P64, NT>), dim3(grid), dim3(2 * NB / E), 0, s, a);
+    return hipGetLastError();
+}
+
+#define DBP_SV(NB, E, P64, NT) {NB, E, 2, P64, NT, launch_split<NB, E, P64, NT>, true}
+#define DBP_S(NB, E)                                                                              \
+    DBP_SV(NB, E, false, 0), DBP_SV(NB, E, false, 9), DBP_SV(NB, E, false, -1), DBP_SV(NB, E, true, 0), \
+        DBP_SV(NB, E, true, 9), DBP_SV(NB, E, true, -1)
 #define DBP_KT(NB, E, NPOL, P64) DBP_KV(NB, E, NPOL, P64, 0), DBP_KV(NB, E, NPOL, P64, 9), DBP_KV(NB, E, NPOL, P64, -1)
 #define DBP_KP(NB, E, NPOL) DBP_KT(NB, E, NPOL, false), DBP_KT(NB, E, NPOL, true)
 #define DBP_K(NB, E) DBP_KP(NB, E, 1), DBP_KP(NB, E, 2)

@@ -184,6 +184,123 @@ __device__ __forceinline__ void process_block(const BlockJob& a, const TwReg<NB,
     if constexpr (S::T > 64) __syncthreads();
 }
 
+// Polarization-split block routine: two groups of NB/E threads, group g
+// transforms polarization g (its own exchange buffers, shared barriers), and
+// the groups meet once per step in LDS for the total intensity.  Twice the
+// waves per block with half the registers per thread: for launches with too
+// few blocks to fill the chip.
+template <int NB, int E> struct SplitSmem {
+    using X = Exchange<NB, E, 1>;
+    float2 lds[2 * X::FLOATS2];
+    float ipol[2][NB];
+};
+
+template <int NB, int E, bool PHASE64, int NT>
+__device__ __forceinline__ void process_block_split(const BlockJob& a, const TwReg<NB, E>& twr,
+                                                    SplitSmem<NB, E>& sm) {
+    using S = FftShape<NB, E>;
+    using X = Exchange<NB, E, 1>;
+    constexpr int T = S::T;
+    static_assert(T > 64 && X::NBUF == 2, "split blocks exchange through two buffers per group");
+    const int grp = threadIdx.x >= T ? 1 : 0;
+    const int t = threadIdx.x - grp * T;
+    float2* lds = sm.lds + grp * X::FLOATS2;
+    const long long L = a.L;
+    const long long start = (long long)a.blk * a.V - a.halo;
+
+    float2 v[1][E];
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+        long long i = start + t + T * q;
+        i = i < 0 ? i + L : (i >= L ? i - L : i);
+        v[0][q] = a.src[grp * L + i];
+    }
+
+    const int ntaps = NT >= 0 ? NT : a.ntaps;
+    const int c = (ntaps - 1) >> 1;
+    for (int s = a.s0; s < a.s0 + a.ks; ++s) {
+        const StepDev st = a.steps[s];
+        const float2* __restrict__ hs = a.H + st.h_off;
+        float2 h[E];
+#pragma unroll
+        for (int q = 0; q < E; ++q) h[q] = hs[t + T * q];
+        const float* __restrict__ w = a.taps + (long long)s * ntaps;
+        float wr[NT > 0 ? NT : 1];
+        if constexpr (NT > 0) {
+#pragma unroll
+            for (int m = 0; m < NT; ++m) wr[m] = w[m];
+        }
+        // (i)-(iii): this group's polarization through Eq. (1)
+        block_fft<NB, E, 1, false>(v, lds, twr, t);
+#pragma unroll
+        for (int q = 0; q < E; ++q) v[0][q] = cmul(v[0][q], h[q]);
+        block_fft<NB, E, 1, true>(v, lds, twr, t);
+        // (iv): |y_g|^2 of each group, summed over both when read back
+#pragma unroll
+        for (int q = 0; q < E; ++q) sm.ipol[grp][t + T * q] = fmaf(v[0][q].x, v[0][q].x, v[0][q].y * v[0][q].y);
+        __syncthreads();
+        float J[E];
+        if constexpr (NT == 0) {
+#pragma unroll
+            for (int q = 0; q < E; ++q) J[q] = sm.ipol[0][t + T * q] + sm.ipol[1][t + T * q];
+        } else {
+#pragma unroll
+            for (int q = 0; q < E; ++q) J[q] = 0.f;
+            if constexpr (NT > 0) {
+#pragma unroll
+                for (int m = 0; m < NT; ++m)
+#pragma unroll
+                    for (int q = 0; q < E; ++q) {
+                        const int i = (t + T * q - m + c) & (NB - 1);
+                        J[q] = fmaf(wr[m], sm.ipol[0][i] + sm.ipol[1][i], J[q]);
+                    }
+            } else {
+                for (int m = 0; m < ntaps; ++m) {
+                    const float wm = w[m];
+#pragma unroll
+                    for (int q = 0; q < E; ++q) {
+                        const int i = (t + T * q - m + c) & (NB - 1);
+                        J[q] = fmaf(wm, sm.ipol[0][i] + sm.ipol[1][i], J[q]);
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < E; ++q) v[0][q] = cmul(v[0][q], phase_factor<PHASE64>(J[q], st));
+        // ipol is rewritten after the next step's exchanges, each behind a barrier
+    }
+
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+        const int pos = t + T * q;
+        const long long o = (long long)a.blk * a.V + pos - a.halo;
+        if (pos >= a.halo && pos < a.halo + a.V && o < L) a.dst[grp * L + o] = v[0][q];
+    }
+}
+
+template <int NB, int E, bool PHASE64, int NT>
+__global__ __launch_bounds__(2 * NB / E) void dbp_pass_kernel_split(PassArgs a) {
+    __shared__ SplitSmem<NB, E> sm;
+    const int wg = xcd_remap(blockIdx.x, a.n_wg);
+    const int sig = wg / a.n_blk;
+    TwReg<NB, E> twr;
+    load_twiddles<NB, E>(twr, a.tw, threadIdx.x >= NB / E ? threadIdx.x - NB / E : threadIdx.x);
+    BlockJob j;
+    j.src = a.in + (long long)sig * 2 * a.L;
+    j.dst = a.out + (long long)sig * 2 * a.L;
+    j.L = a.L;
+    j.V = a.V;
+    j.halo = a.halo;
+    j.blk = wg - sig * a.n_blk;
+    j.steps = a.steps;
+    j.s0 = a.s0;
+    j.ks = a.ks;
+    j.H = a.H;
+    j.taps = a.taps;
+    j.ntaps = a.ntaps;
+    process_block_split<NB, E, PHASE64, NT>(j, twr, sm);
+}
+
 template <int NB, int E, int NPOL, bool PHASE64, int NT>
 __global__ __launch_bounds__(NB / E) void dbp_pass_kernel(PassArgs a) {
     __shared__ BlockSmem<NB, E, NPOL, NT> sm;

@@ -215,3 +215,20 @@ def test_multi_span_steps_parity(dbp, m, taps_nc, n):
     print(f"multi-span m={m} steps={len(steps)} Nb={p.block} O={p.overlap} k={p.steps_per_pass}: rel L2 {err:.3e}")
     assert len(steps) == p.n_steps == 8 // m
     assert err <= 1e-5
+
+
+@pytest.mark.parametrize("force", ["0", "1"])
+@pytest.mark.parametrize("nb,taps", [(1024, TAPS9), (512, None), (2048, siggen.symmetric_taps(siggen.rng(1, 5, 9), 3))])
+def test_polarization_split_blocks(dbp, monkeypatch, force, nb, taps):
+    """The polarization-split variant (two thread groups per block, one per polarization)
+    and the joint variant, forced in turn, both against the oracle."""
+    monkeypatch.setenv("DBP_FORCE_SPLIT", force)
+    n = 30000
+    x, _ = received(1, 60 + nb // 512, 2, n, 2.0, 6, 20)
+    p = dbp.plan(n, 6, 1, taps=taps, block=nb, overlap=nb // 4, beta2_ps2_km=B2)
+    assert ("split" in p.kernel) == (force == "1"), p.kernel
+    y = _from_gpu(p.backprop(_to_gpu(x)), x.shape)
+    ref = _oracle(x, p, 6, 1, taps=taps)
+    err = rel_l2(y, ref)
+    print(f"{p.kernel}: rel L2 {err:.3e}")
+    assert err <= 1e-5
