@@ -131,10 +131,9 @@ __global__ __launch_bounds__(FT_THREADS) void fir_step_kernel(FirArgs a) {
         } else {
             j = is[o];
         }
-        float sn, cs;
-        sincosf(-a.phi * j, &sn, &cs);
+        const float2 rot = expj(-a.phi * j);
 #pragma unroll
-        for (int p = 0; p < NPOL; ++p) z[p * L + a0 + o] = cmul(us[p * nu + o + NC], make_float2(cs, sn));
+        for (int p = 0; p < NPOL; ++p) z[p * L + a0 + o] = cmul(us[p * nu + o + NC], rot);
     }
 }
 
@@ -183,8 +182,8 @@ __global__ __launch_bounds__(FT_THREADS) void fir_adjoint_kernel(FirArgs a) {
     __syncthreads();
     // Jbar = phi sum_p Im(conj(g_z) z), z = u exp(-j phi J), on the z range
     for (int i = t; i < nz; i += FT_THREADS) {
-        float sn, cs;
-        sincosf(-a.phi * js[i], &sn, &cs);
+        const float2 rot = expj(-a.phi * js[i]);
+        const float cs = rot.x, sn = rot.y;
         float acc = 0.f;
 #pragma unroll
         for (int p = 0; p < NPOL; ++p) {
@@ -204,8 +203,8 @@ __global__ __launch_bounds__(FT_THREADS) void fir_adjoint_kernel(FirArgs a) {
         } else {
             ib = jb[iz];
         }
-        float sn, cs;
-        sincosf(a.phi * js[iz], &sn, &cs);
+        const float2 rot = expj(a.phi * js[iz]);
+        const float cs = rot.x, sn = rot.y;
         float2 gu[NPOL];
 #pragma unroll
         for (int p = 0; p < NPOL; ++p) {

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include "fft.hpp"
+#include "phase.hpp"
 
 namespace dbp {
 
@@ -43,19 +44,26 @@ __device__ __forceinline__ int xcd_remap(int i, int n) {
     return xcd < r ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
 }
 
+// exp(-j phi J) for the nonlinear substep.  PHASE64: the argument is formed and
+// reduced in FP64 (k = nearest integer of th 2/pi, r = th - k pi/2); otherwise
+// in FP32 with pi/2 split in two FP32 parts (Cody-Waite), exact to well below
+// an FP32 ulp of r for |th| < 1e3 rad (the nonlinear phase of a step is far
+// below a radian at any practical launch power).
 template <bool PHASE64>
 __device__ __forceinline__ float2 phase_factor(float j, const StepDev& st) {
-    float s, c;
+    float r;
+    int q;
     if constexpr (PHASE64) {
-        // argument -phi J formed and reduced to [-pi, pi] in FP64, rotated in FP32
         const double th = -st.phi64 * (double)j;
-        const double k = rint(th * 0.15915494309189533577);
-        const float r = (float)fma(-k, 6.28318530717958647693, th);
-        sincosf(r, &s, &c);
+        const double k = rint(th * 0.63661977236758134308);
+        r = (float)fma(-k, 1.57079632679489661923, th);
+        q = (int)k;
     } else {
-        sincosf(-st.phi * j, &s, &c);
+        return expj(-st.phi * j);
     }
-    return make_float2(c, s);
+    float s, c;
+    sincos_reduced(r, s, c);
+    return rotate_quadrant(q, s, c);
 }
 
 // One overlap-and-save block through steps [s0, s0 + ks) of one signal.
