@@ -35,7 +35,7 @@ struct FirArgs {
     const float* w;         // this step's intensity taps [ntaps], nullptr for SSFM
     int ntaps;
     float phi;
-    float* part;            // adjoint: per-tile partial gradients [n_wg][ntaps + 2 nfir]
+    float* part;            // adjoint: per-tile partial gradients [ntaps + 2 nfir][n_wg]
 };
 
 __device__ __forceinline__ long long wrap(long long i, long long L) {
@@ -55,10 +55,11 @@ __device__ __forceinline__ void load_tile(float2* s, const float2* __restrict__ 
 }
 
 // u over n_out positions: u[i] = sum_m h[m] xs[i + 2 HF - m] (xs row stride nx),
-// and the total intensity I[i].
-template <int NPOL>
+// and the total intensity I[i].  NF: tap count known at compile time (0: nfir).
+template <int NPOL, int NF>
 __device__ __forceinline__ void fir_u(float2* us, float* is, const float2* xs, int nx, int n_out,
-                                      const float2* hs, int nfir) {
+                                      const float2* hs, int nfir_rt) {
+    const int nfir = NF > 0 ? NF : nfir_rt;
     const int hf2 = nfir - 1;
     for (int i = threadIdx.x; i < n_out; i += FT_THREADS) {
         float in = 0.f;
@@ -66,7 +67,8 @@ __device__ __forceinline__ void fir_u(float2* us, float* is, const float2* xs, i
         for (int p = 0; p < NPOL; ++p) {
             float2 acc = make_float2(0.f, 0.f);
             const float2* xr = xs + p * nx + i + hf2;
-            for (int m = 0; m < nfir; ++m) {
+#pragma unroll
+            for (int m = 0; m < (NF > 0 ? NF : nfir); ++m) {
                 const float2 hv = hs[m];
                 const float2 xv = xr[-m];
                 acc.x = fmaf(hv.x, xv.x, fmaf(-hv.y, xv.y, acc.x));
@@ -79,13 +81,17 @@ __device__ __forceinline__ void fir_u(float2* us, float* is, const float2* xs, i
     }
 }
 
-// J[i] = sum_m w[m] I[i + 2 NC - m] over n_out positions (SSFM: J = I shifted by NC).
-__device__ __forceinline__ void tap_filter(float* js, const float* is, int n_out, const float* ws, int ntaps) {
+// J[i] = sum_m w[m] I[i + 2 NC - m] over n_out positions (SSFM, NW = 0: J = I).
+// NW: tap count known at compile time (-1: ntaps).
+template <int NW>
+__device__ __forceinline__ void tap_filter(float* js, const float* is, int n_out, const float* ws, int ntaps_rt) {
+    const int ntaps = NW > 0 ? NW : ntaps_rt;
     const int c2 = ntaps - 1;
     for (int i = threadIdx.x; i < n_out; i += FT_THREADS) {
         float acc = 0.f;
-        if (ws) {
-            for (int m = 0; m < ntaps; ++m) acc = fmaf(ws[m], is[i + c2 - m], acc);
+        if constexpr (NW != 0) {
+#pragma unroll
+            for (int m = 0; m < (NW > 0 ? NW : ntaps); ++m) acc = fmaf(ws[m], is[i + c2 - m], acc);
         } else {
             acc = is[i];
         }
@@ -93,13 +99,16 @@ __device__ __forceinline__ void tap_filter(float* js, const float* is, int n_out
     }
 }
 
-// Forward step on one tile: out[a + o] for o < FT_TS.
-template <int NPOL>
+// Forward step on one tile: out[a + o] for o < FT_TS.  NF, NW: compile-time
+// FIR and intensity tap counts (0 / -1: taken from the arguments; NW = 0: SSFM).
+template <int NPOL, int NF, int NW>
 __global__ __launch_bounds__(FT_THREADS) void fir_step_kernel(FirArgs a) {
     extern __shared__ float4 smem4[];
     char* smem = reinterpret_cast<char*>(smem4);
-    const int HF = (a.nfir - 1) / 2;
-    const int NC = a.w ? (a.ntaps - 1) / 2 : 0;
+    const int nfir = NF > 0 ? NF : a.nfir;
+    const int ntaps = NW > 0 ? NW : (NW == 0 ? 1 : a.ntaps);
+    const int HF = (nfir - 1) / 2;
+    const int NC = (ntaps - 1) / 2;
     const int nx = FT_TS + 2 * (HF + NC);     // x on [a0 - HF - NC, a0 + TS + HF + NC)
     const int nu = FT_TS + 2 * NC;            // u, I on [a0 - NC, a0 + TS + NC)
     float2* hs = reinterpret_cast<float2*>(smem);
@@ -116,18 +125,19 @@ __global__ __launch_bounds__(FT_THREADS) void fir_step_kernel(FirArgs a) {
     const float2* __restrict__ x = a.x + (long long)sig * NPOL * L;
     float2* __restrict__ z = a.z + (long long)sig * NPOL * L;
 
-    for (int i = threadIdx.x; i < a.nfir; i += FT_THREADS) hs[i] = a.h[i];
-    if (a.w)
-        for (int i = threadIdx.x; i < a.ntaps; i += FT_THREADS) wsm[i] = a.w[i];
+    for (int i = threadIdx.x; i < nfir; i += FT_THREADS) hs[i] = a.h[i];
+    if constexpr (NW != 0)
+        for (int i = threadIdx.x; i < ntaps; i += FT_THREADS) wsm[i] = a.w[i];
     load_tile<NPOL>(xs, x, a0 - HF - NC, nx, L);
     __syncthreads();
-    fir_u<NPOL>(us, is, xs, nx, nu, hs, a.nfir);
+    fir_u<NPOL, NF>(us, is, xs, nx, nu, hs, nfir);
     __syncthreads();
     for (int o = threadIdx.x; o < FT_TS; o += FT_THREADS) {
         if (a0 + o >= L) break;
         float j = 0.f;
-        if (a.w) {
-            for (int m = 0; m < a.ntaps; ++m) j = fmaf(wsm[m], is[o + 2 * NC - m], j);
+        if constexpr (NW != 0) {
+#pragma unroll
+            for (int m = 0; m < (NW > 0 ? NW : ntaps); ++m) j = fmaf(wsm[m], is[o + 2 * NC - m], j);
         } else {
             j = is[o];
         }
@@ -139,12 +149,14 @@ __global__ __launch_bounds__(FT_THREADS) void fir_step_kernel(FirArgs a) {
 
 // Adjoint of one step on one tile: g_x[a0 + o] for o < FT_TS, plus this tile's
 // partial sums of dL/dw (owned outputs n in [a0, a0 + TS)) and dL/dh.
-template <int NPOL>
+template <int NPOL, int NF, int NW>
 __global__ __launch_bounds__(FT_THREADS) void fir_adjoint_kernel(FirArgs a) {
     extern __shared__ float4 smem4[];
     char* smem = reinterpret_cast<char*>(smem4);
-    const int HF = (a.nfir - 1) / 2;
-    const int NC = a.w ? (a.ntaps - 1) / 2 : 0;
+    const int nfir = NF > 0 ? NF : a.nfir;
+    const int ntaps = NW > 0 ? NW : (NW == 0 ? 1 : a.ntaps);
+    const int HF = (nfir - 1) / 2;
+    const int NC = (ntaps - 1) / 2;
     const int nx = FT_TS + 4 * HF + 4 * NC;   // x on [a0 - 2HF - 2NC, ...)
     const int nu = FT_TS + 2 * HF + 4 * NC;   // u, I on [a0 - HF - 2NC, ...)
     const int nz = FT_TS + 2 * HF + 2 * NC;   // J, g_z, Jbar on [a0 - HF - NC, ...)
@@ -169,16 +181,16 @@ __global__ __launch_bounds__(FT_THREADS) void fir_adjoint_kernel(FirArgs a) {
     const float2* __restrict__ gz = a.gz + (long long)sig * NPOL * L;
     float2* __restrict__ gx = a.z + (long long)sig * NPOL * L;
 
-    for (int i = t; i < a.nfir; i += FT_THREADS) hs[i] = a.h[i];
-    if (a.w)
-        for (int i = t; i < a.ntaps; i += FT_THREADS) wsm[i] = a.w[i];
+    for (int i = t; i < nfir; i += FT_THREADS) hs[i] = a.h[i];
+    if constexpr (NW != 0)
+        for (int i = t; i < ntaps; i += FT_THREADS) wsm[i] = a.w[i];
     load_tile<NPOL>(xs, x, a0 - 2 * HF - 2 * NC, nx, L);
     load_tile<NPOL>(gzs, gz, a0 - HF - NC, nz, L);
     __syncthreads();
     // recompute the step: u and I on the u range, J on the z range
-    fir_u<NPOL>(us, is, xs, nx, nu, hs, a.nfir);
+    fir_u<NPOL, NF>(us, is, xs, nx, nu, hs, nfir);
     __syncthreads();
-    tap_filter(js, is, nz, a.w ? wsm : nullptr, a.ntaps);
+    tap_filter<NW>(js, is, nz, wsm, ntaps);
     __syncthreads();
     // Jbar = phi sum_p Im(conj(g_z) z), z = u exp(-j phi J), on the z range
     for (int i = t; i < nz; i += FT_THREADS) {
@@ -198,8 +210,9 @@ __global__ __launch_bounds__(FT_THREADS) void fir_adjoint_kernel(FirArgs a) {
     for (int i = t; i < ng; i += FT_THREADS) {
         const int iz = i + NC;                 // position in the z range
         float ib = 0.f;
-        if (a.w) {
-            for (int m = 0; m < a.ntaps; ++m) ib = fmaf(wsm[m], jb[iz + m - NC], ib);
+        if constexpr (NW != 0) {
+#pragma unroll
+            for (int m = 0; m < (NW > 0 ? NW : ntaps); ++m) ib = fmaf(wsm[m], jb[iz + m - NC], ib);
         } else {
             ib = jb[iz];
         }
@@ -224,7 +237,8 @@ __global__ __launch_bounds__(FT_THREADS) void fir_adjoint_kernel(FirArgs a) {
         for (int p = 0; p < NPOL; ++p) {
             float2 acc = make_float2(0.f, 0.f);
             const float2* gr = gzs + p * nz + NC + o;     // g_u at o - HF is gzs[p][NC + o]
-            for (int m = 0; m < a.nfir; ++m) {
+#pragma unroll
+            for (int m = 0; m < (NF > 0 ? NF : nfir); ++m) {
                 const float2 hv = hs[m];
                 const float2 g = gr[m];
                 acc.x = fmaf(hv.x, g.x, fmaf(hv.y, g.y, acc.x));
@@ -233,50 +247,105 @@ __global__ __launch_bounds__(FT_THREADS) void fir_adjoint_kernel(FirArgs a) {
             gx[p * L + a0 + o] = acc;
         }
     }
-    // parameter partials over owned outputs n = a0 + o, o < min(TS, L - a0):
-    // parameter l (chunks of 64, one per lane) is summed by each of the 4 waves
-    // over a quarter of the outputs, then the 4 quarters are added in order:
-    //   l < nfir:            dL/dh[l] = sum g_u[n] conj(x[n - (l - HF)])
-    //   nfir <= l < nfir+nw: dL/dw[l - nfir] = sum Jbar[n] I[n - (l - nfir - NC)]
-    const int lane = t & 63, q = t >> 6;
     const int n_own = (int)min((long long)FT_TS, L - a0);
-    const int per = (n_own + 3) / 4;
-    const int o0 = q * per, o1 = min(n_own, o0 + per);
-    const int nw = a.w ? a.ntaps : 0;
-    float* part = a.part + (long long)wg * (nw + 2 * a.nfir);
-    for (int pb = 0; pb < a.nfir + nw; pb += 64) {
-        const int l = pb + lane;
-        float2 acc = make_float2(0.f, 0.f);
-        if (l < a.nfir) {
-            for (int o = o0; o < o1; ++o) {
+    const int nw = NW != 0 ? ntaps : 0;
+    // partials parameter-major ([parameter][tile]) so that the reduction reads them contiguously
+    float* part = a.part + wg;
+    const long long pstride = a.n_wg;
+    if constexpr (NF > 0 && NW >= 0) {
+        // Parameter partials over the owned outputs n = a0 + o, o < n_own:
+        //   dL/dh[l] = sum g_u[n] conj(x[n - (l - HF)]),  dL/dw[m] = sum Jbar[n] I[n - (m - NC)].
+        // Every thread accumulates all parameters over its outputs o = t + 256 q, then
+        // the 256 sums of each parameter are added through LDS in a fixed order.
+        constexpr int NWC = NW;
+        constexpr int W = NWC + 2 * NF;
+        float acc[W];
 #pragma unroll
-                for (int p = 0; p < NPOL; ++p) {
-                    const float2 g = gzs[p * nz + NC + HF + o];
-                    const float2 xv = xs[p * nx + o + 3 * HF + 2 * NC - l];
-                    acc.x = fmaf(g.x, xv.x, fmaf(g.y, xv.y, acc.x));
-                    acc.y = fmaf(g.y, xv.x, fmaf(-g.x, xv.y, acc.y));
+        for (int j = 0; j < W; ++j) acc[j] = 0.f;
+        for (int o = t; o < n_own; o += FT_THREADS) {
+#pragma unroll
+            for (int p = 0; p < NPOL; ++p) {
+                const float2 g = gzs[p * nz + NC + HF + o];
+                const float2* xr = xs + p * nx + o + 3 * HF + 2 * NC;
+#pragma unroll
+                for (int l = 0; l < NF; ++l) {
+                    const float2 xv = xr[-l];
+                    acc[NWC + 2 * l] = fmaf(g.x, xv.x, fmaf(g.y, xv.y, acc[NWC + 2 * l]));
+                    acc[NWC + 2 * l + 1] = fmaf(g.y, xv.x, fmaf(-g.x, xv.y, acc[NWC + 2 * l + 1]));
                 }
             }
-        } else if (l < a.nfir + nw) {
-            const int m = l - a.nfir;
-            for (int o = o0; o < o1; ++o) acc.x = fmaf(jb[o + HF + NC], is[o + HF + 3 * NC - m], acc.x);
-        }
-        __syncthreads();                       // previous chunk's sums have been read
-        red[(q * 64 + lane) * 2] = acc.x;
-        red[(q * 64 + lane) * 2 + 1] = acc.y;
-        __syncthreads();
-        if (q == 0) {
-            float sx = 0.f, sy = 0.f;
+            if constexpr (NWC > 0) {
+                const float jv = jb[o + HF + NC];
 #pragma unroll
-            for (int w = 0; w < 4; ++w) {
-                sx += red[(w * 64 + lane) * 2];
-                sy += red[(w * 64 + lane) * 2 + 1];
+                for (int m = 0; m < NWC; ++m) acc[m] = fmaf(jv, is[o + HF + 3 * NC - m], acc[m]);
             }
-            if (l < a.nfir) {
-                part[nw + 2 * l] = sx;
-                part[nw + 2 * l + 1] = sy;
-            } else if (l < a.nfir + nw) {
-                part[l - a.nfir] = sx;
+        }
+        // x, u and g_z are no longer read: their LDS holds the reduction, 16 parameters
+        // at a time ([16][256] per-thread sums, then [16][16] partial sums)
+        float* rb = reinterpret_cast<float*>(xs);
+        float* rb2 = rb + 16 * FT_THREADS;
+#pragma unroll
+        for (int c0 = 0; c0 < W; c0 += 16) {
+            __syncthreads();                   // previous readers of this LDS are done
+#pragma unroll
+            for (int k = 0; k < 16; ++k)
+                if (c0 + k < W) rb[k * FT_THREADS + t] = acc[c0 + k];
+            __syncthreads();
+            {
+                const int k = t >> 4, seg = t & 15;
+                float sum = 0.f;
+#pragma unroll
+                for (int i = 0; i < 16; ++i) sum += rb[k * FT_THREADS + seg * 16 + i];
+                rb2[k * 16 + seg] = sum;
+            }
+            __syncthreads();
+            if (t < 16 && c0 + t < W) {
+                float sum = 0.f;
+#pragma unroll
+                for (int i = 0; i < 16; ++i) sum += rb2[t * 16 + i];
+                part[(c0 + t) * pstride] = sum;
+            }
+        }
+    } else {
+        // run-time tap counts: parameter l (chunks of 64, one per lane) summed by each of
+        // the 4 waves over a quarter of the outputs, the 4 quarters added in order
+        const int lane = t & 63, q = t >> 6;
+        const int per = (n_own + 3) / 4;
+        const int o0 = q * per, o1 = min(n_own, o0 + per);
+        for (int pb = 0; pb < nfir + nw; pb += 64) {
+            const int l = pb + lane;
+            float2 acc = make_float2(0.f, 0.f);
+            if (l < nfir) {
+                for (int o = o0; o < o1; ++o) {
+#pragma unroll
+                    for (int p = 0; p < NPOL; ++p) {
+                        const float2 g = gzs[p * nz + NC + HF + o];
+                        const float2 xv = xs[p * nx + o + 3 * HF + 2 * NC - l];
+                        acc.x = fmaf(g.x, xv.x, fmaf(g.y, xv.y, acc.x));
+                        acc.y = fmaf(g.y, xv.x, fmaf(-g.x, xv.y, acc.y));
+                    }
+                }
+            } else if (l < nfir + nw) {
+                const int m = l - nfir;
+                for (int o = o0; o < o1; ++o) acc.x = fmaf(jb[o + HF + NC], is[o + HF + 3 * NC - m], acc.x);
+            }
+            __syncthreads();                   // previous chunk's sums have been read
+            red[(q * 64 + lane) * 2] = acc.x;
+            red[(q * 64 + lane) * 2 + 1] = acc.y;
+            __syncthreads();
+            if (q == 0) {
+                float sx = 0.f, sy = 0.f;
+#pragma unroll
+                for (int w = 0; w < 4; ++w) {
+                    sx += red[(w * 64 + lane) * 2];
+                    sy += red[(w * 64 + lane) * 2 + 1];
+                }
+                if (l < nfir) {
+                    part[(nw + 2 * l) * pstride] = sx;
+                    part[(nw + 2 * l + 1) * pstride] = sy;
+                } else if (l < nfir + nw) {
+                    part[(l - nfir) * pstride] = sx;
+                }
             }
         }
     }
