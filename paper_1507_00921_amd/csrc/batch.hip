@@ -147,11 +147,12 @@ static bool arcs_meet(long long a, long long la, long long c, long long lc, long
     return d1 < la || d2 < lc;
 }
 
-// Dependencies of every block of a signal: the blocks whose output region its
-// input window covers, and the blocks whose input window covers its output
-// region.  Windows reach at most O/2 <= V/2 past their region, except that of
-// the last, partial block, so candidates are b-2..b+2 and the two blocks at
-// each end of the signal.
+// Dependencies of every block group (work item) of a signal: the groups holding the blocks
+// whose output region one of its blocks' input windows covers, and those
+// holding the blocks whose input window covers one of its output regions.
+// Windows reach at most O/2 <= V/2 past their region, except that of the last,
+// partial block, so the candidate blocks of block b are b-2..b+2 and the two
+// blocks at each end of the signal.
 static bool block_deps(const BatchSig& s, int nb, std::vector<int>& deps) {
     const long long L = s.L;
     const int n = s.n_blk;
@@ -159,29 +160,40 @@ static bool block_deps(const BatchSig& s, int nb, std::vector<int>& deps) {
         st = (long long)b * s.V;
         len = std::min<long long>(s.V, L - st);
     };
-    for (int b = 0; b < n; ++b) {
-        long long rs, rl;
-        region(b, rs, rl);
-        const long long ws = (((long long)b * s.V - s.halo) % L + L) % L;
-        std::vector<int> cand;
-        for (int d = -2; d <= 2; ++d) cand.push_back(((b + d) % n + n) % n);
-        for (int e : {0, 1, n - 2, n - 1}) cand.push_back(((e % n) + n) % n);
-        std::sort(cand.begin(), cand.end());
-        cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
-        int cnt = 0;
-        for (int c : cand) {
-            long long cs, cl;
-            region(c, cs, cl);
-            const long long cws = (((long long)c * s.V - s.halo) % L + L) % L;
-            const bool raw = arcs_meet(ws, std::min<long long>(nb, L), cs, cl, L);
-            const bool war = arcs_meet(cws, std::min<long long>(nb, L), rs, rl, L);
-            if (raw || war) {
-                if (cnt == DEPS_MAX) return false;
-                deps[(size_t)(s.prog_off + b) * DEPS_MAX + cnt++] = c;
+    for (int gi = 0; gi < s.n_grp; ++gi) {
+        std::vector<int> groups;
+        for (int b = gi * s.grp; b < std::min(n, (gi + 1) * s.grp); ++b) {
+            long long rs, rl;
+            region(b, rs, rl);
+            const long long ws = (((long long)b * s.V - s.halo) % L + L) % L;
+            std::vector<int> cand;
+            for (int d = -2; d <= 2; ++d) cand.push_back(((b + d) % n + n) % n);
+            for (int e : {0, 1, n - 2, n - 1}) cand.push_back(((e % n) + n) % n);
+            for (int c : cand) {
+                long long cs, cl;
+                region(c, cs, cl);
+                const long long cws = (((long long)c * s.V - s.halo) % L + L) % L;
+                const bool raw = arcs_meet(ws, std::min<long long>(nb, L), cs, cl, L);
+                const bool war = arcs_meet(cws, std::min<long long>(nb, L), rs, rl, L);
+                if (raw || war) groups.push_back(c / s.grp);
             }
         }
+        std::sort(groups.begin(), groups.end());
+        groups.erase(std::unique(groups.begin(), groups.end()), groups.end());
+        if ((int)groups.size() > DEPS_MAX) return false;
+        for (size_t k = 0; k < groups.size(); ++k) deps[(size_t)(s.prog_off + gi) * DEPS_MAX + k] = groups[k];
     }
     return true;
+}
+
+// Blocks per work item: long signals take groups of up to gmax blocks (fewer
+// synchronisations per block); signals with few blocks keep one block per item
+// so that each pass still spreads over many workgroups.  DBP_BATCH_GROUP sets
+// gmax (default 4).
+static int blocks_per_item(int n_blk) {
+    int gmax = 4;
+    if (const char* f = std::getenv("DBP_BATCH_GROUP")) gmax = std::max(1, std::min(64, std::atoi(f)));
+    return std::max(1, std::min(gmax, n_blk / 32));
 }
 
 // Cheapest (Nb, O, k) for one signal under the measured cost model: every pass
@@ -359,8 +371,10 @@ dbp_status dbp_plan_batch(const dbp_desc* descs, int32_t n, dbp_plan_t* out) {
         s.step0 = (int)steps.size();
         s.ntaps = d->method == DBP_ESSFM ? d->n_taps : 1;
         s.taps_off = d->method == DBP_ESSFM ? (int)taps.size() : -1;
+        s.grp = blocks_per_item(s.n_blk);
+        s.n_grp = (s.n_blk + s.grp - 1) / s.grp;
         s.prog_off = prog;
-        prog += s.n_blk;
+        prog += s.n_grp;
         if (s.halo > s.V) st = DBP_ERR_UNSUPPORTED;      // dependency candidates assume O/2 <= V
         for (int k = 0; k < s.n_steps; ++k) {
             const auto key = std::make_tuple(g.block, b[k], fp64);
@@ -427,7 +441,7 @@ dbp_status dbp_plan_batch(const dbp_desc* descs, int32_t n, dbp_plan_t* out) {
         for (int lv = 0; lv < max_pass; ++lv)
             for (int i : sig)
                 if (B->sigs[i].n_pass > lv)
-                    for (int blk = 0; blk < B->sigs[i].n_blk; ++blk) items.push_back(make_int4(i, lv, blk, 0));
+                    for (int gi = 0; gi < B->sigs[i].n_grp; ++gi) items.push_back(make_int4(i, lv, gi, 0));
         G.n_items = (int)items.size() - G.item0;
         const int per_cu = std::max(1, occ ? occ() : 1);
         G.grid = std::max(1, std::min(G.n_items, per_cu * prop.multiProcessorCount));

@@ -1,17 +1,21 @@
 // Persistent ragged-batch kernel: many signals of any length, link and step
 // count backpropagated in one launch per kernel variant.
 //
-// Work items are (signal, pass, block) triples, queued pass level by pass
-// level.  A resident workgroup pops the next item from an atomic counter,
-// waits until every block it depends on has finished the previous pass,
-// runs the block and publishes its progress.  Block b depends on the blocks
-// whose output region its input window reads (read after write) and on the
-// blocks whose input window reads its output region (write after read: pass
-// p+1 overwrites the buffer pass p read); the planner lists them, at most
-// DEPS_MAX, circular at the signal ends.  Every item an item waits on was
-// queued earlier and is held by a running workgroup, so the queue always
-// drains; a wait that exceeds its bound raises an error flag and the item
-// is skipped instead of spinning forever.
+// Work items are (signal, pass, group) triples, a group being grp consecutive
+// blocks of the signal (the last group may be shorter), queued pass level by
+// pass level.  A resident workgroup pops the next item from an atomic
+// counter, waits until every group it depends on has finished the previous
+// pass, runs the group's blocks one after the other and publishes its
+// progress.  A group depends on the groups holding the blocks whose output
+// region one of its blocks' input windows reads (read after write) and on
+// those holding the blocks whose input window reads one of its output regions
+// (write after read: pass p+1 overwrites the buffer pass p read); the planner
+// lists them, at most DEPS_MAX, circular at the signal ends.  Every item an
+// item waits on was queued earlier and is held by a running workgroup, so the
+// queue always drains; a wait that exceeds its bound raises an error flag and
+// the item is skipped instead of spinning forever.  Grouping blocks divides
+// the per-item synchronisation (one L2 writeback and one invalidation) among
+// them.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -25,10 +29,11 @@ struct BatchSig {
     long long off;      // element offset of the signal's [NPOL][L] in the packed buffers
     long long L;
     int V, halo, n_blk, k, n_steps, n_pass;
+    int grp, n_grp;     // blocks per work item, items per pass
     int step0;          // first entry of the signal's steps in the batch step array
     int taps_off;       // first entry of its taps ([N_s][ntaps]) in the batch tap array, -1: SSFM
     int ntaps;
-    int prog_off;       // first entry of its per-block progress counters (and DEPS_MAX x
+    int prog_off;       // first entry of its per-group progress counters (and DEPS_MAX x
                         // that many dependency entries, -1 padded)
 };
 
@@ -37,11 +42,11 @@ struct BatchArgs {
     float2* out;            // packed output
     float2* ws0;            // packed scratch (intermediate passes)
     const BatchSig* sigs;
-    const int4* items;      // (signal, pass, block, 0) in queue order
+    const int4* items;      // (signal, pass, group, 0) in queue order
     int n_items;
     int* counter;           // this group's queue head
-    int* progress;          // passes completed, per (signal, block)
-    const int* deps;        // per (signal, block): DEPS_MAX blocks of the signal, -1 padded
+    int* progress;          // passes completed, per (signal, group)
+    const int* deps;        // per (signal, group): DEPS_MAX groups of the signal, -1 padded
     int* err;               // bit 0: a dependency wait exceeded its bound
     const StepDev* steps;
     const float2* H;
@@ -85,12 +90,12 @@ __global__ __launch_bounds__(NB / E) void dbp_batch_kernel(BatchArgs a) {
         const int4 w = a.items[it];
         const int si = __builtin_amdgcn_readfirstlane(w.x);
         const int pass = __builtin_amdgcn_readfirstlane(w.y);
-        const int blk = __builtin_amdgcn_readfirstlane(w.z);
+        const int grp = __builtin_amdgcn_readfirstlane(w.z);
         const BatchSig sg = a.sigs[si];
         int ok = 1;
         if (pass > 0) {
             if (t < 64) {                     // wave 0 waits (a whole wave: uniform branch)
-                const int* dl = a.deps + (long long)(sg.prog_off + blk) * DEPS_MAX;
+                const int* dl = a.deps + (long long)(sg.prog_off + grp) * DEPS_MAX;
                 for (int d = 0; d < DEPS_MAX; ++d) {
                     const int nb = __builtin_amdgcn_readfirstlane(dl[d]);
                     if (nb < 0) break;
@@ -129,20 +134,23 @@ __global__ __launch_bounds__(NB / E) void dbp_batch_kernel(BatchArgs a) {
             j.L = sg.L;
             j.V = sg.V;
             j.halo = sg.halo;
-            j.blk = blk;
             j.steps = a.steps + sg.step0;
             j.s0 = pass * sg.k;
             j.ks = min(sg.k, sg.n_steps - j.s0);
             j.H = a.H;
             j.taps = sg.taps_off >= 0 ? a.taps + sg.taps_off : nullptr;
             j.ntaps = sg.ntaps;
-            process_block<NB, E, NPOL, PHASE64, NT>(j, twr, sm);
+            const int b1 = min(sg.n_blk, (grp + 1) * sg.grp);
+            for (int b = grp * sg.grp; b < b1; ++b) {
+                j.blk = b;
+                process_block<NB, E, NPOL, PHASE64, NT>(j, twr, sm);
+            }
         }
         // every thread's stores are released at agent scope (one L2 writeback) before
         // the progress counter is published with a plain atomic store
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         if constexpr (MULTI) __syncthreads();
-        __hip_atomic_store(a.progress + sg.prog_off + blk, pass + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(a.progress + sg.prog_off + grp, pass + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 

@@ -120,3 +120,23 @@ def test_full_ragged_workload_sampled(dbp):
         err = rel_l2(y[i].astype(np.complex128), ref)
         print(f"cfg2 signal {i}: L={work[i]['n']} steps={ns} geo={bp.geometry(i)} rel L2 {err:.3e}")
         assert err <= (1e-5 if ns <= 40 else 2e-4)
+
+
+def test_grouped_blocks_long_signals(dbp):
+    # long signals on small blocks: 50..160 blocks each, so work items carry 1..4 blocks
+    lengths = [19500, 25000, 40000, 52000, 61440, 33334]
+    work = []
+    for i, n in enumerate(lengths):
+        taps = siggen.symmetric_taps(siggen.rng(2, 900 + i, 0), 2 + i % 3) if i % 2 == 0 else None
+        work.append(dict(n=n, n_spans=6, steps_per_span=1 if taps is not None else 3, taps=taps))
+    ds = descs_for(dbp, work, block=512, overlap=128, steps_per_pass=2)
+    bp = dbp.plan_batch(ds)
+    xs = fields_for(work, 9)
+    y = bp.unpack(bp.backprop(bp.pack(xs)))
+    torch.cuda.synchronize()
+    assert bp.status() == 0
+    for i, w in enumerate(work):
+        ref, ns = oracle_one(xs[i], w, bp.geometry(i))
+        err = rel_l2(y[i].astype(np.complex128), ref)
+        print(f"grouped signal {i}: L={w['n']} blocks={-(-w['n'] // 384)} steps={ns} rel L2 {err:.3e}")
+        assert err <= 1e-5
