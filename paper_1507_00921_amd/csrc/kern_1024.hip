@@ -1,4 +1,5 @@
-// Pass-kernel variants: DBP_K(1024, 16), DBP_K(1024, 4).
+// Pass-kernel variants for 1024-point blocks (values per thread E, polarizations, phase
+// precision, tap variant; polarization-split variants where listed).
 #include "registry.hpp"
 
 namespace dbp {

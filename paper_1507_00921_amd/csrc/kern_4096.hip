@@ -1,4 +1,5 @@
-// Pass-kernel variants: DBP_K(4096, 16).
+// Pass-kernel variants for 4096-point blocks (values per thread E, polarizations, phase
+// precision, tap variant; polarization-split variants where listed).
 #include "registry.hpp"
 
 namespace dbp {

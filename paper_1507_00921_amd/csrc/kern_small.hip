@@ -1,4 +1,5 @@
-// Pass-kernel variants: DBP_K(256, 4), DBP_K(512, 8).
+// Pass-kernel variants for 256- and 512-point blocks (values per thread E, polarizations, phase
+// precision, tap variant; polarization-split variants where listed).
 #include "registry.hpp"
 
 namespace dbp {
