@@ -23,7 +23,7 @@ namespace dbp {
 
 // ------------------------------------------------------------------ kernel registry
 
-LaunchFn find_kernel(int nb, int e, int npol, bool p64, int nt, bool split) {
+const KernelEntry* find_entry(int nb, int e, int npol, bool p64, int nt, bool split) {
     using Acc = const KernelEntry* (*)(int*);
     static const Acc tables[] = {kernels_small, kernels_1024, kernels_2048, kernels_4096, kernels_large,
                                  kernels_mfma};
@@ -33,9 +33,14 @@ LaunchFn find_kernel(int nb, int e, int npol, bool p64, int nt, bool split) {
         for (int i = 0; i < n; ++i)
             if (t[i].nb == nb && t[i].e == e && t[i].npol == npol && t[i].p64 == p64 && t[i].nt == nt &&
                 t[i].split == split)
-                return t[i].fn;
+                return &t[i];
     }
     return nullptr;
+}
+
+LaunchFn find_kernel(int nb, int e, int npol, bool p64, int nt, bool split) {
+    const KernelEntry* k = find_entry(nb, e, npol, p64, nt, split);
+    return k ? k->fn : nullptr;
 }
 
 // Compile-time tap count of the variant serving a method and tap count.
@@ -437,6 +442,42 @@ using namespace dbp;
 
 // ------------------------------------------------------------------ C ABI
 
+namespace dbp {
+
+// Streaming twin of the plan's pass kernel: used when the launch has at least
+// two blocks per resident workgroup slot (so that prefetching the next block
+// has something to overlap), every step uses one dispersion table and a
+// signal fits one buffer resource.
+// DBP_STREAM=0 disables it, DBP_STREAM=1 uses it whenever a twin exists;
+// DBP_STREAM_GRID=n (a multiple of 8) sets its grid.
+static dbp_status choose_stream(Plan* p, const KernelEntry* ke, int n_tables) {
+    if (!ke || !ke->sfn || !ke->socc || n_tables != 1) return DBP_OK;
+    if ((long long)p->desc.n_pol * p->desc.n_samples * (long long)sizeof(float2) >= (1LL << 31)) return DBP_OK;
+    const char* on = std::getenv("DBP_STREAM");
+    if (on && std::atoi(on) == 0) return DBP_OK;
+    int cu = 0;
+    if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess || cu < 1)
+        return DBP_ERR_HIP;
+    const int occ = ke->socc();
+    if (occ < 1) return DBP_ERR_HIP;
+    int grid = (occ * cu) & ~7;
+    if (const char* g = std::getenv("DBP_STREAM_GRID")) {
+        const int n = std::atoi(g);
+        if (n >= 8 && n % 8 == 0) grid = n;
+    }
+    if (grid < 8) return DBP_OK;
+    const long long v = p->geo.block - p->geo.overlap;
+    const long long n_wg = (p->desc.n_samples + v - 1) / v * p->desc.batch;
+    if (!(on && std::atoi(on) == 1) && n_wg < 2LL * grid) return DBP_OK;
+    p->launch_stream = (void*)ke->sfn;
+    p->stream_grid = grid;
+    std::snprintf(p->kernel_name, sizeof(p->kernel_name), "dbp_stream_kernel<%d, %d, %d, %s, %d>", ke->nb, ke->e,
+                  ke->npol, ke->p64 ? "true" : "false", ke->nt);
+    return DBP_OK;
+}
+
+}  // namespace dbp
+
 extern "C" {
 
 void dbp_desc_init(dbp_desc* d) {
@@ -610,6 +651,14 @@ dbp_status dbp_plan(const dbp_desc* desc, dbp_plan_t* out) {
         delete p;
         return DBP_ERR_HIP;
     }
+    if (!fir_mode && desc->precision != DBP_BF16X3 &&
+        (st = choose_stream(p,
+                            find_entry(nb, p->geo.e, desc->n_pol, fp64, tap_variant(desc->method, desc->n_taps),
+                                       p->geo.split),
+                            (int)seen.size())) != DBP_OK) {
+        delete p;
+        return st;
+    }
     auto upload = [&](void** dptr, const void* src, size_t bytes) -> dbp_status {
         if (bytes == 0) return DBP_OK;
         hipError_t e = hipMalloc(dptr, bytes);
@@ -761,7 +810,7 @@ dbp_status dbp_backprop(dbp_plan_t p, const void* in, void* out, const float* ta
             return DBP_ERR_HIP;
         return DBP_OK;
     }
-    LaunchFn fn = (LaunchFn)p->launch;
+    LaunchFn fn = (LaunchFn)(p->launch_stream ? p->launch_stream : p->launch);
     if (!fn) return DBP_ERR_UNSUPPORTED;
 
     PassArgs a{};
@@ -776,7 +825,9 @@ dbp_status dbp_backprop(dbp_plan_t p, const void* in, void* out, const float* ta
     a.taps = p->desc.method == DBP_ESSFM ? (taps ? taps : p->d_taps) : nullptr;
     a.ntaps = p->desc.method == DBP_ESSFM ? p->desc.n_taps : 1;
     a.frag = p->d_frag;
-    const int grid = p->grid_cap > 0 ? std::min(p->grid_cap, a.n_wg) : a.n_wg;
+    const int grid = p->launch_stream ? p->stream_grid
+                   : p->grid_cap > 0  ? std::min(p->grid_cap, a.n_wg)
+                                      : a.n_wg;
 
     const int P = g.n_passes;
     const float2* src = (const float2*)in;

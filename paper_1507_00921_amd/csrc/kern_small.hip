@@ -4,7 +4,7 @@
 
 namespace dbp {
 
-static const KernelEntry kTable[] = {DBP_K(256, 4), DBP_K(512, 8), DBP_K(512, 4), DBP_S(512, 4)};
+static const KernelEntry kTable[] = {DBP_KS(256, 4), DBP_KS(512, 8), DBP_K(512, 4), DBP_S(512, 4)};
 
 const KernelEntry* kernels_small(int* n) {
     *n = (int)(sizeof(kTable) / sizeof(kTable[0]));

@@ -29,6 +29,8 @@ struct dbp_plan_s {
     dbp::Geometry geo;
     int device = -1;
     void* launch = nullptr;          // pass-kernel launcher
+    void* launch_stream = nullptr;   // streaming pass-kernel launcher (resident grid), used when set
+    int stream_grid = 0;             // its grid: resident workgroups, a multiple of 8
     float2* d_h = nullptr;           // dispersion tables
     float2* d_tw = nullptr;          // FFT twiddles
     dbp::StepDev* d_steps = nullptr;

@@ -44,6 +44,23 @@ __device__ __forceinline__ int xcd_remap(int i, int n) {
     return xcd < r ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
 }
 
+// Read-only plan tables (step constants, taps) through the constant address
+// space: uniform loads from it become scalar loads even in kernels that also
+// store (the compiler cannot otherwise rule out that a store aliases them).
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(4))) T* as_const(const T* p) {
+    return (const __attribute__((address_space(4))) T*)p;
+}
+
+__device__ __forceinline__ StepDev load_step(const StepDev* p) {
+    const auto q = as_const(p);
+    StepDev st;
+    st.h_off = q->h_off;
+    st.phi = q->phi;
+    st.phi64 = q->phi64;
+    return st;
+}
+
 // exp(-j phi J) for the nonlinear substep.  PHASE64: the argument is formed and
 // reduced in FP64 (k = nearest integer of th 2/pi, r = th - k pi/2); otherwise
 // in FP32 with pi/2 split in two FP32 parts (Cody-Waite), exact to well below
@@ -87,11 +104,29 @@ template <int NB, int E, int NPOL, int NT> struct BlockSmem {
     float ilds_own[OWN_I ? NB : 1];
 };
 
-// NT: number of ESSFM taps known at compile time (0: SSFM, J = I; -1: taken
-// from the job at run time).  Every thread of the workgroup must call this.
-template <int NB, int E, int NPOL, bool PHASE64, int NT>
-__device__ __forceinline__ void process_block(const BlockJob& a, const TwReg<NB, E>& twr,
-                                              BlockSmem<NB, E, NPOL, NT>& sm) {
+// Load a block's NB samples of every polarization, starting at sample `start`
+// (circular at the signal ends), into the thread-strided register layout.
+template <int NB, int E, int NPOL>
+__device__ __forceinline__ void load_block(float2 (&v)[NPOL][E], const float2* __restrict__ src, long long L,
+                                           long long start, int t) {
+    constexpr int T = NB / E;
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+        long long i = start + t + T * q;
+        i = i < 0 ? i + L : (i >= L ? i - L : i);
+#pragma unroll
+        for (int p = 0; p < NPOL; ++p) v[p][q] = src[p * L + i];
+    }
+}
+
+// Steps [s0, s0 + ks) on a block held in registers (NT: number of ESSFM taps
+// known at compile time; 0: SSFM, J = I; -1: taken from the job at run time).
+// HLDS: every step of the pass uses one dispersion table, copied to hl in
+// LDS with each thread holding the entries of its own bins (so no barrier
+// orders the copy).  Every thread of the workgroup must call this.
+template <int NB, int E, int NPOL, bool PHASE64, int NT, bool HLDS = false>
+__device__ __forceinline__ void run_steps(float2 (&v)[NPOL][E], const BlockJob& a, const TwReg<NB, E>& twr,
+                                          BlockSmem<NB, E, NPOL, NT>& sm, const float2* __restrict__ hl) {
     using S = FftShape<NB, E>;
     using X = Exchange<NB, E, NPOL>;
     constexpr int T = S::T;
@@ -101,30 +136,23 @@ __device__ __forceinline__ void process_block(const BlockJob& a, const TwReg<NB,
     constexpr bool OWN_I = BlockSmem<NB, E, NPOL, NT>::OWN_I;
     float2* lds = sm.lds;
     float* ilds = OWN_I ? sm.ilds_own : reinterpret_cast<float*>(sm.lds);
-
     const int t = threadIdx.x;
-    const long long L = a.L;
-    const long long start = (long long)a.blk * a.V - a.halo;
-
-    float2 v[NPOL][E];
-#pragma unroll
-    for (int q = 0; q < E; ++q) {
-        long long i = start + t + T * q;
-        i = i < 0 ? i + L : (i >= L ? i - L : i);
-#pragma unroll
-        for (int p = 0; p < NPOL; ++p) v[p][q] = a.src[p * L + i];
-    }
 
     const int ntaps = NT >= 0 ? NT : a.ntaps;
     const int c = (ntaps - 1) >> 1;
     for (int s = a.s0; s < a.s0 + a.ks; ++s) {
-        const StepDev st = a.steps[s];
+        const StepDev st = load_step(a.steps + s);
         // issue this step's table and tap loads first: the forward FFT hides their latency
-        const float2* __restrict__ hs = a.H + st.h_off;
         float2 h[E];
+        if constexpr (HLDS) {
 #pragma unroll
-        for (int q = 0; q < E; ++q) h[q] = hs[t + T * q];
-        const float* __restrict__ w = a.taps + (long long)s * ntaps;
+            for (int q = 0; q < E; ++q) h[q] = hl[t + T * q];
+        } else {
+            const float2* __restrict__ hs = a.H + st.h_off;
+#pragma unroll
+            for (int q = 0; q < E; ++q) h[q] = hs[t + T * q];
+        }
+        const auto w = as_const(a.taps) + (long long)s * ntaps;
         float wr[NT > 0 ? NT : 1];
         if constexpr (NT > 0) {
 #pragma unroll
@@ -177,8 +205,13 @@ __device__ __forceinline__ void process_block(const BlockJob& a, const TwReg<NB,
             for (int p = 0; p < NPOL; ++p) v[p][q] = cmul(v[p][q], r);
         }
     }
+}
 
-    // keep the centre V samples of the block
+// Keep the centre V samples of the block.
+template <int NB, int E, int NPOL>
+__device__ __forceinline__ void store_block(const float2 (&v)[NPOL][E], const BlockJob& a, int t) {
+    constexpr int T = NB / E;
+    const long long L = a.L;
 #pragma unroll
     for (int q = 0; q < E; ++q) {
         const int pos = t + T * q;
@@ -188,8 +221,42 @@ __device__ __forceinline__ void process_block(const BlockJob& a, const TwReg<NB,
             for (int p = 0; p < NPOL; ++p) a.dst[p * L + o] = v[p][q];
         }
     }
+}
+
+// The same through a buffer resource spanning the signal (NPOL * L * 8 bytes
+// < 2^31): lanes outside the centre get an offset past the resource, which
+// the hardware's range check discards, so every lane issues the same stores
+// and the count of outstanding memory operations is the same on every path.
+template <int NB, int E, int NPOL>
+__device__ __forceinline__ void store_block_rsrc(const float2 (&v)[NPOL][E], const BlockJob& a, int t) {
+    typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+    constexpr int T = NB / E;
+    const long long L = a.L;
+    const __amdgpu_buffer_rsrc_t r =
+        __builtin_amdgcn_make_buffer_rsrc(a.dst, 0, (int)(NPOL * L * (long long)sizeof(float2)), 0x00020000);
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+        const int pos = t + T * q;
+        const long long o = (long long)a.blk * a.V + pos - a.halo;
+        const bool ok = pos >= a.halo && pos < a.halo + a.V && o < L;
+        const unsigned off = ok ? (unsigned)o * (unsigned)sizeof(float2) : 0x80000000u;
+#pragma unroll
+        for (int p = 0; p < NPOL; ++p)
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v[p][q]), r,
+                                                  off + (unsigned)(p * L * (long long)sizeof(float2)), 0, 0);
+    }
+}
+
+template <int NB, int E, int NPOL, bool PHASE64, int NT>
+__device__ __forceinline__ void process_block(const BlockJob& a, const TwReg<NB, E>& twr,
+                                              BlockSmem<NB, E, NPOL, NT>& sm) {
+    const int t = threadIdx.x;
+    float2 v[NPOL][E];
+    load_block<NB, E, NPOL>(v, a.src, a.L, (long long)a.blk * a.V - a.halo, t);
+    run_steps<NB, E, NPOL, PHASE64, NT>(v, a, twr, sm, nullptr);
+    store_block<NB, E, NPOL>(v, a, t);
     // before the LDS is reused by a following job, every wave is done with it
-    if constexpr (S::T > 64) __syncthreads();
+    if constexpr (NB / E > 64) __syncthreads();
 }
 
 // Polarization-split block routine: two groups of NB/E threads, group g
@@ -330,6 +397,78 @@ __global__ __launch_bounds__(NB / E) void dbp_pass_kernel(PassArgs a) {
     j.taps = a.taps;
     j.ntaps = a.ntaps;
     process_block<NB, E, NPOL, PHASE64, NT>(j, twr, sm);
+}
+
+// Streaming pass kernel: a resident grid (a multiple of 8 workgroups) walks
+// the launch's blocks.  XCD x (the workgroups with blockIdx.x = x mod 8)
+// takes the contiguous eighth [x n / 8, (x + 1) n / 8) of the n blocks, its
+// workgroups interleaved so that neighbouring blocks, which share halo
+// samples, run together under one L2.  While a workgroup computes one block
+// it has the next block's input in flight into registers, and the plan's
+// dispersion table (the launcher requires that every step uses one) stays in
+// LDS, so that no other memory load waits behind the prefetch: the HBM
+// traffic of a pass overlaps its FFT arithmetic instead of alternating with it.
+template <int NB, int E, int NPOL, int NT> struct StreamSmem {
+    BlockSmem<NB, E, NPOL, NT> b;
+    float2 h[NB];
+};
+
+template <int NB, int E, int NPOL, bool PHASE64, int NT>
+__global__ __launch_bounds__(NB / E) void dbp_stream_kernel(PassArgs a) {
+    constexpr int T = NB / E;
+    __shared__ StreamSmem<NB, E, NPOL, NT> sm;
+    const int t = threadIdx.x;
+    const int per = gridDim.x >> 3;
+    const int x = blockIdx.x & 7;
+    const int hi = (int)(((long long)a.n_wg * (x + 1)) >> 3);
+    int it = (int)(((long long)a.n_wg * x) >> 3) + (int)(blockIdx.x >> 3);
+    if (it >= hi) return;
+    TwReg<NB, E> twr;
+    load_twiddles<NB, E>(twr, a.tw, t);
+    const int h0 = load_step(a.steps + a.s0).h_off;
+#pragma unroll
+    for (int q = 0; q < E; ++q) sm.h[t + T * q] = a.H[h0 + t + T * q];
+
+    const long long sig_elems = (long long)NPOL * a.L;
+    int sig = it / a.n_blk, blk = it - sig * a.n_blk;
+    float2 v[NPOL][E];
+    load_block<NB, E, NPOL>(v, a.in + sig * sig_elems, a.L, (long long)blk * a.V - a.halo, t);
+    // Wait for the first block here (vmcnt(0)).  Otherwise the compiler, whose
+    // memory-counter waits are not path-sensitive, places a wait for it at the
+    // top of the step loop, where on every later block it would also wait for
+    // the prefetch of the next one.
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    for (;;) {
+        const int nx = it + per;
+        const bool more = nx < hi;
+        const int nsig = nx / a.n_blk, nblk = nx - nsig * a.n_blk;
+        float2 w[NPOL][E];
+        if (more) load_block<NB, E, NPOL>(w, a.in + nsig * sig_elems, a.L, (long long)nblk * a.V - a.halo, t);
+        BlockJob j;
+        j.dst = a.out + sig * sig_elems;
+        j.L = a.L;
+        j.V = a.V;
+        j.halo = a.halo;
+        j.blk = blk;
+        j.steps = a.steps;
+        j.s0 = a.s0;
+        j.ks = a.ks;
+        j.H = a.H;
+        j.taps = a.taps;
+        j.ntaps = a.ntaps;
+        run_steps<NB, E, NPOL, PHASE64, NT, true>(v, j, twr, sm.b, sm.h);
+        store_block_rsrc<NB, E, NPOL>(v, j, t);
+        // the next block's exchanges reuse the LDS: every wave is done with it
+        if constexpr (T > 64) __syncthreads();
+        if (!more) break;
+#pragma unroll
+        for (int p = 0; p < NPOL; ++p)
+#pragma unroll
+            for (int q = 0; q < E; ++q) v[p][q] = w[p][q];
+        it = nx;
+        sig = nsig;
+        blk = nblk;
+    }
 }
 
 }  // namespace dbp
