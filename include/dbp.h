@@ -164,7 +164,8 @@ dbp_status dbp_schedule(const dbp_desc* desc, double* b, double* phi, int32_t n)
 dbp_status dbp_fir_taps(const dbp_desc* desc, int32_t step, float* out);
 
 /* Bytes of device workspace dbp_backprop (grad = 0) or dbp_backprop_grad
- * (grad = 1) needs with this plan.  0 for an invalid plan. */
+ * (grad = 1) needs with this plan.  0 for an invalid plan (and, grad = 1, for
+ * a plan whose gradient is not supported). */
 size_t dbp_workspace_size(dbp_plan_t plan, int32_t grad);
 
 /* Backpropagate (or, with DBP_FLAG_FORWARD, propagate) in -> out.
@@ -180,18 +181,26 @@ size_t dbp_workspace_size(dbp_plan_t plan, int32_t grad);
 dbp_status dbp_backprop(dbp_plan_t plan, const void* in, void* out, const float* taps,
                         const void* fir, void* ws, size_t ws_bytes, void* stream);
 
-/* Gradient of a real loss through dbp_backprop (reverse mode), for plans
- * with the FIR linear step (DBP_ERR_UNSUPPORTED otherwise).  Given
+/* Gradient of a real loss through dbp_backprop (reverse mode).  Given
  * grad_out = dL/dRe(out) + j dL/dIm(out) (device complex64, same shape as
  * in), writes grad_in (same convention; may be NULL; must not overlap
  * grad_out), grad_taps (device float32 [N_s][n_taps], ESSFM; may be NULL)
- * and grad_fir (device complex64 [N_s][n_fir]; may be NULL).  taps and fir
- * override the plan's parameters as in dbp_backprop.  The forward pass runs
- * once storing the state every 8 steps; each 8-step segment is then
- * recomputed from its checkpoint and its adjoint steps run in reverse.
- * Parameter gradients are summed over the batch in a fixed order (bitwise
- * reproducible).  ws_bytes >= dbp_workspace_size(plan, 1).  Gradients are
- * overwritten, not accumulated. */
+ * and grad_fir (device complex64 [N_s][n_fir], FIR plans; may be NULL; must
+ * be NULL for FFT-step plans, which have no FIR taps).  taps and fir
+ * override the plan's parameters as in dbp_backprop.
+ *   FIR plans: the forward pass runs once storing the state every 8 steps;
+ *     each 8-step segment is then recomputed from its checkpoint and its
+ *     adjoint steps run in reverse.
+ *   FFT-step plans (overlap-and-save, Sec. III): the derivative of exactly the
+ *     blocked cascade dbp_backprop computes (same Nb, O, k).  The passes run
+ *     forward once storing every pass input; then each pass, in reverse,
+ *     re-runs every block's steps from that input and their adjoints, and the
+ *     window gradients of overlapping blocks are summed per sample in block
+ *     order.  Block sizes 256..4096; not the BF16X3 precision (UNSUPPORTED).
+ *     The phase argument of the recomputed steps is formed in FP64.
+ * Parameter gradients are summed over blocks, tiles and the batch in a fixed
+ * order (bitwise reproducible).  ws_bytes >= dbp_workspace_size(plan, 1).
+ * Gradients are overwritten, not accumulated. */
 dbp_status dbp_backprop_grad(dbp_plan_t plan, const void* in, const float* taps,
                              const void* fir, const void* grad_out, void* grad_in,
                              float* grad_taps, void* grad_fir, void* ws, size_t ws_bytes,

@@ -262,7 +262,8 @@ class Plan:
         """Reverse-mode gradient through backprop(x, taps, fir) for upstream grad_out.
 
         Returns (grad_x or None, grad_taps [N_s][n_taps] float32 or None (SSFM),
-        grad_fir [N_s][n_fir] complex64).  Complex gradients are dL/dRe + j dL/dIm.
+        grad_fir [N_s][n_fir] complex64 or None (FFT-step plans)).  Complex gradients are
+        dL/dRe + j dL/dIm.
         """
         import torch
         self._check_field(x, "input")
@@ -272,7 +273,8 @@ class Plan:
         gx = torch.empty_like(x) if want_input else None
         gt = (torch.empty(ns, self.desc.n_taps, dtype=torch.float32, device=x.device)
               if self.desc.method == ESSFM else None)
-        gf = torch.empty(ns, self.desc.n_fir, dtype=torch.complex64, device=x.device)
+        gf = (torch.empty(ns, self.desc.n_fir, dtype=torch.complex64, device=x.device)
+              if self.desc.linear == LINEAR_FIR else None)
         if workspace is None:
             workspace = self.workspace(grad=True)
         st = lib().dbp_backprop_grad(self._h, _ptr(x), _ptr(taps), _ptr(fir), _ptr(grad_out), _ptr(gx),
@@ -361,7 +363,7 @@ def _autograd_function():
     import torch
 
     class DBPFunction(torch.autograd.Function):
-        """out = plan.backprop(x, taps, fir) with a hand-written adjoint (FIR linear step plans).
+        """out = plan.backprop(x, taps, fir) with a hand-written adjoint (FIR or FFT linear step).
 
         x: complex64 [batch][n_pol][L]; taps: float32 [N_s][n_taps] (ESSFM) or None;
         fir: complex64 [N_s][n_fir].  Gradients follow PyTorch's convention for
@@ -381,7 +383,7 @@ def _autograd_function():
             gx, gt, gf = ctx.plan.backprop_grad(x, g.contiguous(), taps=taps, fir=fir,
                                                 want_input=ctx.needs_input_grad[0])
             return (gx, gt if ctx.needs_input_grad[1] else None,
-                    gf if ctx.needs_input_grad[2] else None, None)
+                    gf if ctx.needs_input_grad[2] and gf is not None else None, None)
 
     return DBPFunction
 

@@ -1,0 +1,279 @@
+// Reverse mode of the fused overlap-and-save pass (FFT linear substep, Sec. II
+// ops (i)-(iv) on the blocks of Sec. III), for gradients with respect to the
+// input field and the ESSFM taps.
+//
+// Per step z = u exp(-j phi J), J = w (*) I, I = sum_p |u_p|^2,
+// u = IDFT(H DFT(x)) on a block (circular within the block).  With upstream
+// gradient g = dL/dRe(z) + j dL/dIm(z):
+//   Jbar_n = phi sum_p Im(conj(g_p,n) z_p,n)
+//   dL/dw[m] += sum_n Jbar_n I_{n-(m-c)}            (block-circular)
+//   Ibar_n = sum_m w[m] Jbar_{n+(m-c)}               (transpose of the tap filter)
+//   g_u = g exp(+j phi J) + 2 Ibar u
+//   g_x = IDFT(conj(H) DFT(g_u))                     (H with 1/Nb folded in)
+// A pass gathers its blocks from the signal and keeps their centres; its
+// reverse takes the centre gradient (halo zero), runs the block's steps
+// backwards, and scatter-adds the whole window gradient into the signal.  Here
+// every block writes its window gradient to its own slot, and the earlier
+// pass (or the final gather) sums, for each sample, the slots of the blocks
+// whose window covers it, in block order: no atomics, the same result on
+// every run.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "dbp.h"
+#include "step_kernel.hpp"
+
+namespace dbp {
+
+struct AdjArgs {
+    const float2* x;        // pass input [n_sig][NPOL][L]
+    const float2* gsig;     // gradient at the pass output [n_sig][NPOL][L], or nullptr:
+    const float2* gprev;    //   then gathered from the following pass's window gradients
+    float2* gout;           // this pass's window gradients [n_wg][NPOL][NB]
+    float2* xs;             // block states of steps 1..ks-1 [n_wg][kmax - 1][NPOL][NB]
+    int kmax;               // steps per pass of the plan (slot count of xs + 1)
+    long long L;
+    int V, halo, n_blk, n_wg;
+    const StepDev* steps;
+    int s0, ks;
+    const float2* H;
+    const float2* tw;
+    const float* taps;      // [N_s][ntaps], nullptr for SSFM
+    int ntaps;
+    float* part;            // dL/dw partial sums [N_s][ntaps][n_wg]
+};
+
+// Sum, over the blocks whose window covers sample n of a signal, of their
+// window gradient at n (block b covers samples (b V - halo + m) mod L, m < nb;
+// G holds the signal's blocks [n_blk][NPOL][nb]).  Fixed order: the unwrapped
+// positions n - L, n, n + L, and blocks in increasing order for each.
+template <int NPOL>
+__device__ __forceinline__ float2 gather_window_grad(const float2* __restrict__ G, int p, long long n, long long L,
+                                                     int nb, int V, int halo, int n_blk) {
+    float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int sh = -1; sh <= 1; ++sh) {
+        const long long m = n + sh * L;
+        const long long lo = m + halo - nb + 1;      // b V >= lo
+        const long long hi = m + halo;               // b V <= hi
+        if (hi < 0) continue;
+        long long b = lo <= 0 ? 0 : (lo + V - 1) / V;
+        const long long bhi = hi / V < n_blk - 1 ? hi / V : n_blk - 1;
+        for (; b <= bhi; ++b) {
+            const float2 gv = G[(b * NPOL + p) * nb + (m - (b * V - halo))];
+            acc.x += gv.x;
+            acc.y += gv.y;
+        }
+    }
+    return acc;
+}
+
+template <int NB, int E, int NPOL, int NT> struct AdjSmem {
+    static constexpr int NW = NB / E / 64 > 0 ? NB / E / 64 : 1;     // waves per block
+    static constexpr int NR = NT > 0 ? NT : (NT == 0 ? 1 : DBP_MAX_TAPS);
+    float2 lds[Exchange<NB, E, NPOL>::FLOATS2];
+    float inten[NB];
+    float jb[NB];
+    float red[NR * NW];
+};
+
+// Wave-wide sum (lanes combined in a fixed butterfly order).
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+template <int NB, int E, int NPOL, bool PHASE64, int NT>
+__global__ __launch_bounds__(NB / E) void dbp_adjoint_kernel(AdjArgs a) {
+    using S = FftShape<NB, E>;
+    using Sm = AdjSmem<NB, E, NPOL, NT>;
+    constexpr int T = S::T;
+    __shared__ Sm sm;
+    const int t = threadIdx.x;
+    const int wg = blockIdx.x;
+    const int sig = wg / a.n_blk, blk = wg - sig * a.n_blk;
+    const long long L = a.L;
+    const long long start = (long long)blk * a.V - a.halo;
+    TwReg<NB, E> twr;
+    load_twiddles<NB, E>(twr, a.tw, t);
+    const float2* __restrict__ xsig = a.x + (long long)sig * NPOL * L;
+    float2* __restrict__ xs = a.xs + (long long)wg * (a.kmax - 1) * NPOL * NB;
+    const int ntaps = NT >= 0 ? NT : a.ntaps;
+    const int c = (ntaps - 1) >> 1;
+
+    // forward through the pass on the block, keeping the inputs of steps 1..ks-1
+    float2 v[NPOL][E];
+    load_block<NB, E, NPOL>(v, xsig, L, start, t);
+    BlockJob job;
+    job.L = L;
+    job.V = a.V;
+    job.halo = a.halo;
+    job.blk = blk;
+    job.steps = a.steps;
+    job.ks = 1;
+    job.H = a.H;
+    job.taps = a.taps;
+    job.ntaps = a.ntaps;
+    for (int j = 0; j + 1 < a.ks; ++j) {
+        job.s0 = a.s0 + j;
+        BlockSmem<NB, E, NPOL, NT>& fs = *reinterpret_cast<BlockSmem<NB, E, NPOL, NT>*>(&sm);
+        static_assert(sizeof(BlockSmem<NB, E, NPOL, NT>) <= sizeof(Sm), "forward step workspace");
+        run_steps<NB, E, NPOL, PHASE64, NT>(v, job, twr, fs, nullptr);
+        __syncthreads();
+#pragma unroll
+        for (int p = 0; p < NPOL; ++p)
+#pragma unroll
+            for (int q = 0; q < E; ++q) xs[((long long)j * NPOL + p) * NB + t + T * q] = v[p][q];
+    }
+
+    // gradient at the pass output: the kept centre, zero in the halo
+    float2 g[NPOL][E];
+    const float2* __restrict__ gprev = a.gprev + (long long)sig * a.n_blk * NPOL * NB;
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+        const int pos = t + T * q;
+        const long long o = (long long)blk * a.V + pos - a.halo;
+        const bool keep = pos >= a.halo && pos < a.halo + a.V && o < L;
+#pragma unroll
+        for (int p = 0; p < NPOL; ++p) {
+            if (!keep) {
+                g[p][q] = make_float2(0.f, 0.f);
+            } else if (a.gsig) {
+                g[p][q] = a.gsig[((long long)sig * NPOL + p) * L + o];
+            } else {
+                g[p][q] = gather_window_grad<NPOL>(gprev, p, o, L, NB, a.V, a.halo, a.n_blk);
+            }
+        }
+    }
+
+    for (int j = a.ks - 1; j >= 0; --j) {
+        const int s = a.s0 + j;
+        if (j == 0) {
+            load_block<NB, E, NPOL>(v, xsig, L, start, t);
+        } else {
+#pragma unroll
+            for (int p = 0; p < NPOL; ++p)
+#pragma unroll
+                for (int q = 0; q < E; ++q) v[p][q] = xs[((long long)(j - 1) * NPOL + p) * NB + t + T * q];
+        }
+        const StepDev st = load_step(a.steps + s);
+        float2 h[E];
+#pragma unroll
+        for (int q = 0; q < E; ++q) h[q] = a.H[st.h_off + t + T * q];
+        // recompute u, I, J and the phase factor f = exp(-j phi J) of step s
+        block_fft<NB, E, NPOL, false>(v, sm.lds, twr, t);
+#pragma unroll
+        for (int q = 0; q < E; ++q)
+#pragma unroll
+            for (int p = 0; p < NPOL; ++p) v[p][q] = cmul(v[p][q], h[q]);
+        block_fft<NB, E, NPOL, true>(v, sm.lds, twr, t);
+        float J[E];
+#pragma unroll
+        for (int q = 0; q < E; ++q) {
+            float in = 0.f;
+#pragma unroll
+            for (int p = 0; p < NPOL; ++p) in = fmaf(v[p][q].x, v[p][q].x, fmaf(v[p][q].y, v[p][q].y, in));
+            J[q] = in;
+        }
+        const float* __restrict__ w = a.taps + (long long)s * ntaps;
+        if constexpr (NT != 0) {
+#pragma unroll
+            for (int q = 0; q < E; ++q) sm.inten[t + T * q] = J[q];
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < E; ++q) J[q] = 0.f;
+            for (int m = 0; m < ntaps; ++m) {
+                const float wm = w[m];
+#pragma unroll
+                for (int q = 0; q < E; ++q) J[q] = fmaf(wm, sm.inten[(t + T * q - m + c) & (NB - 1)], J[q]);
+            }
+        }
+        // adjoint of the phase rotation: Jbar, and g <- g conj(f)
+        float jb[E];
+#pragma unroll
+        for (int q = 0; q < E; ++q) {
+            const float2 f = phase_factor<PHASE64>(J[q], st);
+            float acc = 0.f;
+#pragma unroll
+            for (int p = 0; p < NPOL; ++p) {
+                const float2 z = cmul(v[p][q], f);
+                acc = fmaf(g[p][q].x, z.y, fmaf(-g[p][q].y, z.x, acc));
+                g[p][q] = cmulc(g[p][q], f);
+            }
+            jb[q] = st.phi * acc;
+        }
+        float ib[E];
+        if constexpr (NT != 0) {
+            // dL/dw[m] over this block: sum_n Jbar_n I_{n-(m-c)}, reduced in a fixed order
+            constexpr int NW = Sm::NW;
+            const int lane = t & 63, wave = t >> 6;
+            for (int m = 0; m < ntaps; ++m) {
+                float pm = 0.f;
+#pragma unroll
+                for (int q = 0; q < E; ++q) pm = fmaf(jb[q], sm.inten[(t + T * q - m + c) & (NB - 1)], pm);
+                pm = wave_sum(pm);
+                if (lane == 0) sm.red[m * NW + wave] = pm;
+            }
+            // transpose of the tap filter: Ibar_n = sum_m w[m] Jbar_{n+(m-c)}
+#pragma unroll
+            for (int q = 0; q < E; ++q) sm.jb[t + T * q] = jb[q];
+            __syncthreads();
+            for (int m = t; m < ntaps; m += T) {
+                float sum = 0.f;
+                for (int k = 0; k < NW; ++k) sum += sm.red[m * NW + k];
+                a.part[((long long)s * ntaps + m) * a.n_wg + wg] = sum;
+            }
+#pragma unroll
+            for (int q = 0; q < E; ++q) ib[q] = 0.f;
+            for (int m = 0; m < ntaps; ++m) {
+                const float wm = w[m];
+#pragma unroll
+                for (int q = 0; q < E; ++q) ib[q] = fmaf(wm, sm.jb[(t + T * q + m - c) & (NB - 1)], ib[q]);
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < E; ++q) ib[q] = jb[q];
+        }
+        // g_u = g exp(+j phi J) + 2 Ibar u, then the adjoint of the linear substep
+#pragma unroll
+        for (int q = 0; q < E; ++q)
+#pragma unroll
+            for (int p = 0; p < NPOL; ++p) {
+                g[p][q].x = fmaf(2.f * ib[q], v[p][q].x, g[p][q].x);
+                g[p][q].y = fmaf(2.f * ib[q], v[p][q].y, g[p][q].y);
+            }
+        block_fft<NB, E, NPOL, false>(g, sm.lds, twr, t);
+#pragma unroll
+        for (int q = 0; q < E; ++q)
+#pragma unroll
+            for (int p = 0; p < NPOL; ++p) g[p][q] = cmulc(g[p][q], h[q]);
+        block_fft<NB, E, NPOL, true>(g, sm.lds, twr, t);
+        // inten, jb and red are rewritten only after the barriers of the next step's transforms
+    }
+
+    // this block's window gradient
+    float2* __restrict__ gout = a.gout + (long long)wg * NPOL * NB;
+#pragma unroll
+    for (int p = 0; p < NPOL; ++p)
+#pragma unroll
+        for (int q = 0; q < E; ++q) gout[p * NB + t + T * q] = g[p][q];
+}
+
+// Input gradient of the first pass: for every sample, the sum of the window
+// gradients of the blocks covering it.
+template <int NPOL>
+__global__ __launch_bounds__(256) void grad_gather_kernel(const float2* __restrict__ G, float2* __restrict__ gin,
+                                                          long long L, int nb, int V, int halo, int n_blk,
+                                                          int n_sig) {
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= (long long)n_sig * L) return;
+    const int sig = (int)(i / L);
+    const long long n = i - (long long)sig * L;
+    const float2* Gs = G + (long long)sig * n_blk * NPOL * nb;
+#pragma unroll
+    for (int p = 0; p < NPOL; ++p)
+        gin[((long long)sig * NPOL + p) * L + n] = gather_window_grad<NPOL>(Gs, p, n, L, nb, V, halo, n_blk);
+}
+
+}  // namespace dbp

@@ -16,6 +16,7 @@
 #include "dbp.h"
 #include "plan.hpp"
 #include "registry.hpp"
+#include "adj_launch.hpp"
 #include "fir_launch.hpp"
 #include "mfma_kernel.hpp"
 
@@ -747,6 +748,42 @@ static size_t grad_ws_bytes(const Plan* p) {
     return (size_t)(f.n_ckpt - 1 + f.seg - 1 + 2) * state + part;
 }
 
+// FFT-step plans: geometry of the reverse pass.
+struct FftGradGeo {
+    int nb, V, halo, n_blk, n_wg, k, n_passes, nw;
+    size_t state, window, xs, part;
+};
+
+static bool fft_grad_supported(const Plan* p) {
+    return p->desc.linear == DBP_LINEAR_FFT && p->desc.precision != DBP_BF16X3 && p->launch &&
+           have_fft_adjoint(p->geo.block);
+}
+
+static FftGradGeo fft_grad_geo(const Plan* p) {
+    FftGradGeo f;
+    f.nb = p->geo.block;
+    f.V = p->geo.block - p->geo.overlap;
+    f.halo = p->geo.overlap / 2;
+    f.n_blk = (int)((p->desc.n_samples + f.V - 1) / f.V);
+    f.n_wg = f.n_blk * p->desc.batch;
+    f.k = p->geo.k;
+    f.n_passes = p->geo.n_passes;
+    f.nw = p->desc.method == DBP_ESSFM ? p->desc.n_taps : 0;
+    f.state = p->state_bytes();
+    f.window = (size_t)f.n_wg * p->desc.n_pol * f.nb * sizeof(float2);
+    f.xs = (size_t)(f.k - 1) * f.window;
+    f.part = (size_t)p->geo.n_steps * f.nw * f.n_wg * sizeof(float);
+    return f;
+}
+
+// Workspace of the FFT-step gradient: the inputs of passes 1.., the block
+// states of steps 1.. of a pass, two sets of window gradients, the partials.
+static size_t fft_grad_ws_bytes(const Plan* p) {
+    if (!fft_grad_supported(p)) return 0;
+    const FftGradGeo f = fft_grad_geo(p);
+    return (size_t)(f.n_passes - 1) * f.state + f.xs + 2 * f.window + f.part;
+}
+
 static FirArgs fir_args(const Plan* p, int s, const float* taps, const void* fir) {
     FirArgs a{};
     const FirGeo f = fir_geo(p);
@@ -763,13 +800,94 @@ static FirArgs fir_args(const Plan* p, int s, const float* taps, const void* fir
 
 }  // namespace dbp
 
+// Reverse mode of dbp_backprop for FFT-step plans: the passes run forward once
+// storing every pass input; then, pass by pass in reverse, every block re-runs
+// its steps from the stored pass input and runs their adjoints, leaving its
+// window gradient for the earlier pass to gather.
+static dbp_status fft_backprop_grad(Plan* p, const void* in, const float* taps, const void* grad_out,
+                                    void* grad_in, float* grad_taps, void* grad_fir, void* ws, size_t ws_bytes,
+                                    void* stream) {
+    if (!fft_grad_supported(p)) return DBP_ERR_UNSUPPORTED;
+    if (grad_fir) return DBP_ERR_INVALID_ARG;   // no FIR taps in an FFT-step plan
+    const FftGradGeo f = fft_grad_geo(p);
+    const char* go = (const char*)grad_out;
+    const char* gi = (const char*)grad_in;
+    if (grad_in && gi < go + f.state && go < gi + f.state) return DBP_ERR_INVALID_ARG;
+    if (!ws || ws_bytes < fft_grad_ws_bytes(p)) return DBP_ERR_WORKSPACE;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return DBP_ERR_HIP;
+    if (dev != p->device) return DBP_ERR_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    char* w = (char*)ws;
+    auto ckpt = [&](int pass) {   // input of pass `pass`
+        return pass == 0 ? (const float2*)in : (const float2*)(w + (size_t)(pass - 1) * f.state);
+    };
+    float2* xs = (float2*)(w + (size_t)(f.n_passes - 1) * f.state);
+    float2* G[2] = {(float2*)((char*)xs + f.xs), (float2*)((char*)xs + f.xs + f.window)};
+    float* part = (float*)((char*)G[1] + f.window);
+    const float* tp = p->desc.method == DBP_ESSFM ? (taps ? taps : p->d_taps) : nullptr;
+
+    // forward: the inputs of passes 1..P-1
+    LaunchFn fn = (LaunchFn)(p->launch_stream ? p->launch_stream : p->launch);
+    PassArgs a{};
+    a.L = p->desc.n_samples;
+    a.V = f.V;
+    a.halo = f.halo;
+    a.n_blk = f.n_blk;
+    a.n_wg = f.n_wg;
+    a.steps = p->d_steps;
+    a.H = p->d_h;
+    a.tw = p->d_tw;
+    a.taps = tp;
+    a.ntaps = p->desc.method == DBP_ESSFM ? p->desc.n_taps : 1;
+    const int grid = p->launch_stream ? p->stream_grid : a.n_wg;
+    for (int pass = 0; pass + 1 < f.n_passes; ++pass) {
+        a.in = ckpt(pass);
+        a.out = (float2*)ckpt(pass + 1);
+        a.s0 = pass * f.k;
+        a.ks = std::min(f.k, p->geo.n_steps - a.s0);
+        if (fn(a, grid, s) != hipSuccess) return DBP_ERR_HIP;
+    }
+    // reverse
+    AdjArgs r{};
+    r.xs = xs;
+    r.kmax = f.k;
+    r.L = p->desc.n_samples;
+    r.V = f.V;
+    r.halo = f.halo;
+    r.n_blk = f.n_blk;
+    r.n_wg = f.n_wg;
+    r.steps = p->d_steps;
+    r.H = p->d_h;
+    r.tw = p->d_tw;
+    r.taps = tp;
+    r.ntaps = a.ntaps;
+    r.part = part;
+    for (int pass = f.n_passes - 1, i = 0; pass >= 0; --pass, ++i) {
+        r.x = ckpt(pass);
+        r.gsig = i == 0 ? (const float2*)grad_out : nullptr;
+        r.gprev = i == 0 ? nullptr : G[(i - 1) & 1];
+        r.gout = G[i & 1];
+        r.s0 = pass * f.k;
+        r.ks = std::min(f.k, p->geo.n_steps - r.s0);
+        if (launch_fft_adjoint(f.nb, p->desc.n_pol, r, s) != hipSuccess) return DBP_ERR_HIP;
+    }
+    if (grad_in && launch_grad_gather(p->desc.n_pol, G[(f.n_passes - 1) & 1], (float2*)grad_in, r.L, f.nb, f.V,
+                                      f.halo, f.n_blk, p->desc.batch, s) != hipSuccess)
+        return DBP_ERR_HIP;
+    if (grad_taps && f.nw &&
+        launch_reduce_partials(part, p->geo.n_steps, f.n_wg, f.nw, 0, grad_taps, nullptr, s) != hipSuccess)
+        return DBP_ERR_HIP;
+    return DBP_OK;
+}
+
 extern "C" {
 
 size_t dbp_workspace_size(dbp_plan_t p, int32_t grad) {
     if (!p) return 0;
     const size_t state = p->state_bytes();
     if (p->is_batch) return grad ? 0 : 2 * state;
-    if (grad) return p->desc.linear == DBP_LINEAR_FIR ? grad_ws_bytes(p) : 0;
+    if (grad) return p->desc.linear == DBP_LINEAR_FIR ? grad_ws_bytes(p) : fft_grad_ws_bytes(p);
     return p->geo.n_passes == 1 ? state : 2 * state;
 }
 
@@ -857,6 +975,8 @@ dbp_status dbp_backprop_grad(dbp_plan_t p, const void* in, const float* taps, co
                              const void* grad_out, void* grad_in, float* grad_taps, void* grad_fir,
                              void* ws, size_t ws_bytes, void* stream) {
     if (!p || !in || !grad_out || p->is_batch) return DBP_ERR_INVALID_ARG;
+    if (p->desc.linear == DBP_LINEAR_FFT)
+        return fft_backprop_grad(p, in, taps, grad_out, grad_in, grad_taps, grad_fir, ws, ws_bytes, stream);
     if (p->desc.linear != DBP_LINEAR_FIR) return DBP_ERR_UNSUPPORTED;
     const size_t state = p->state_bytes();
     const char* go = (const char*)grad_out;

@@ -1,0 +1,126 @@
+"""GPU parity of the reverse mode of the overlap-and-save FFT cascade (dbp_backprop_grad on
+FFT-step plans) against the oracle's FP64 adjoint of the same blocked cascade.
+
+Both sides take the same complex64-rounded input, the same FP32-rounded taps and the same
+seeded upstream gradient; the oracle differentiates exactly the blocked function the GPU
+computes (same Nb, O, k).  Tolerances: input gradient relative L2 <= 1e-5 up to 40 steps
+(the FP32 budget of the forward path), tap gradients relative L2 <= 1e-4 (sums of
+products over every sample, reduced in FP64 on the GPU).
+"""
+import numpy as np
+import pytest
+
+import siggen
+from oracle import adjoint as A
+from oracle import dbp_ref as R
+
+from gpu_inputs import B2, FS, received, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def dbp():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1507_00921_amd as m
+    m.lib()
+    return m
+
+
+def dev(a, dtype):
+    return torch.from_numpy(np.ascontiguousarray(a.astype(dtype))).cuda()
+
+
+def case(seed, batch, n_pol, n, n_spans, nc):
+    xs = np.stack([received(4, seed * 10 + i, n_pol, n, 3.0, n_spans, 1)[0] for i in range(batch)])
+    taps = (np.stack([siggen.symmetric_taps(siggen.rng(4, seed, s), nc) for s in range(n_spans)])
+            .astype(np.float32) if nc is not None else None)
+    g = np.random.default_rng([4, seed, 99])
+    gout = (g.standard_normal(xs.shape) + 1j * g.standard_normal(xs.shape)).astype(np.complex64)
+    return xs, taps, gout
+
+
+@pytest.mark.parametrize("nb,o,k,n_pol,nc,n_spans,n,batch", [
+    (1024, 256, 5, 2, 4, 10, 8000, 1),      # headline geometry, 2 passes of 5 steps, ragged tail
+    (512, 128, 1, 1, None, 6, 3000, 2),     # SSFM, one polarization, two signals, 6 passes
+    (256, 64, 2, 2, 3, 5, 2000, 1),         # 7 taps (run-time tap count), odd pass count
+    (2048, 512, 3, 2, 4, 6, 9000, 1),
+    (4096, 1024, 2, 2, None, 4, 10000, 1),
+    (1024, 256, 3, 2, 4, 3, 1024, 1),       # one block: its window wraps around the signal
+])
+def test_fft_grad_matches_oracle(dbp, nb, o, k, n_pol, nc, n_spans, n, batch):
+    xs, taps, gout = case(nb + k, batch, n_pol, n, n_spans, nc)
+    p = dbp.plan(n, n_spans, 1, batch=batch, n_pol=n_pol, taps=None if taps is None else taps[0], block=nb,
+                 overlap=o, steps_per_pass=k, beta2_ps2_km=B2)
+    assert (p.block, p.overlap, p.steps_per_pass) == (nb, o, k)
+    t_dev = None if taps is None else dev(taps, np.float32)
+    gx, gt, gf = p.backprop_grad(dev(xs, np.complex64), dev(gout, np.complex64), taps=t_dev)
+    assert gf is None
+    gx = gx.cpu().numpy().astype(np.complex128)
+    base = R.schedule(n_spans, 80.0, 1, B2, siggen.GAMMA_W_KM, siggen.ALPHA_DB_KM)
+    steps = [R.Step(b=st.b, phi=st.phi, w=None if taps is None else taps[s].astype(np.float64))
+             for s, st in enumerate(base)]
+    wsum = np.zeros((n_spans, 2 * nc + 1)) if taps is not None else None
+    for i in range(batch):
+        ref = A.grad_blocked(xs[i], steps, FS, nb, o, k, gout[i].astype(np.complex128))
+        err = rel_l2(gx[i], ref.x)
+        print(f"Nb={nb} O={o} k={k} pol={n_pol} signal {i}: grad_in rel L2 {err:.3e}")
+        assert err <= 1e-5
+        if taps is not None:
+            wsum += np.stack(ref.w)
+    if taps is not None:
+        got = gt.cpu().numpy().astype(np.float64)
+        err = rel_l2(got, wsum)
+        print(f"  grad_taps rel L2 {err:.3e}")
+        assert err <= 1e-4
+    else:
+        assert gt is None
+
+
+def test_fft_grad_is_deterministic_and_matches_autograd(dbp):
+    # two runs are bitwise equal, and the autograd Function returns the same gradients
+    n, n_spans = 6000, 5
+    xs, taps, gout = case(7, 2, 2, n, n_spans, 4)
+    p = dbp.plan(n, n_spans, 1, batch=2, taps=taps[0], block=1024, overlap=256, steps_per_pass=2,
+                 beta2_ps2_km=B2)
+    x = dev(xs, np.complex64)
+    t = dev(taps, np.float32)
+    g = dev(gout, np.complex64)
+    a = p.backprop_grad(x, g, taps=t)
+    b = p.backprop_grad(x, g, taps=t)
+    torch.cuda.synchronize()
+    assert torch.equal(a[0].view(torch.float32), b[0].view(torch.float32))
+    assert torch.equal(a[1], b[1])
+    fn = dbp.dbp_function()
+    xr = x.clone().requires_grad_(True)
+    tr = t.clone().requires_grad_(True)
+    y = fn.apply(xr, tr, None, p)
+    loss = (torch.view_as_real(y) * torch.view_as_real(g)).sum()   # dL/dy = g (real-pair convention)
+    loss.backward()
+    assert torch.equal(xr.grad.view(torch.float32), a[0].view(torch.float32))
+    assert torch.equal(tr.grad, a[1])
+
+
+def test_fft_grad_finite_difference_of_gpu_forward(dbp):
+    # d/dw of <g, DBP(x; w)> along a tap direction, by central differences of the GPU forward
+    n, n_spans = 4096, 4
+    xs, taps, gout = case(11, 1, 2, n, n_spans, 4)
+    p = dbp.plan(n, n_spans, 1, taps=taps[0], block=1024, overlap=256, steps_per_pass=2, beta2_ps2_km=B2)
+    x = dev(xs, np.complex64)
+    g = dev(gout, np.complex64)
+    _, gt, _ = p.backprop_grad(x, g, taps=dev(taps, np.float32))
+    d = np.zeros_like(taps)
+    d[:, 4] = 1.0      # centre tap of every step
+    h = 1e-2
+
+    def f(tp):
+        y = p.backprop(x, taps=dev(tp, np.float32)).cpu().numpy().astype(np.complex128)
+        return float(np.sum(np.real(np.conj(gout.astype(np.complex128)) * y)))
+
+    fd = (f(taps + h * d) - f(taps - h * d)) / (2 * h)
+    an = float(np.sum(gt.cpu().numpy().astype(np.float64) * d))
+    print(f"directional derivative: adjoint {an:.6e}, central difference {fd:.6e}")
+    assert abs(an - fd) <= 2e-3 * abs(fd) + 1e-6
