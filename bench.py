@@ -64,28 +64,42 @@ def gpu_field(dbp, torch, p_dbm=P_DBM):
     return torch.from_numpy(r.astype(np.complex64)).reshape(1, 2, N).cuda(), sym
 
 
-def fit_taps(dbp, torch, rx, target, n_fit=100000, iters=8, nc=NC, plan_kw=None):
+def fit_taps(dbp, torch, rx, target, n_fit=100000, iters=8, nc=NC, plan_kw=None, method="auto"):
     """ESSFM coefficient fit of Sec. IV: least squares against the multi-step SSFM output
-    on the first n_fit samples; Nc+1 symmetric coefficients shared by every step,
-    Gauss-Newton with a forward-difference Jacobian, every evaluation on the GPU.
-    plan_kw: the ESSFM plan's link and geometry (default 1 step per span, Nb=1024 O=256)."""
+    on the first n_fit samples; Nc+1 symmetric coefficients shared by every step, every
+    evaluation on the GPU.  method "adjoint": L-BFGS on the objective and its gradient from
+    the library's reverse mode (forward + reverse per evaluation); "gauss_newton":
+    Gauss-Newton with a forward-difference Jacobian (Nc + 2 forward runs per iteration);
+    "auto": the adjoint where the plan's block size has a reverse kernel.
+    plan_kw: the ESSFM plan's link and geometry (default 1 step per span, Nb=1024 O=256).
+    Returns (taps, info)."""
+    from paper_1507_00921_amd import fit as G
     b2 = siggen.beta2_ps2_km()
-    kw = plan_kw or dict(n_spans=SPANS, steps_per_span=1, block=BLOCK, overlap=OVERLAP)
+    kw = dict(plan_kw or dict(n_spans=SPANS, steps_per_span=1, block=BLOCK, overlap=OVERLAP))
     sl = slice(BLOCK, n_fit)            # away from the circular wrap of the first block
+    c = np.zeros(nc + 1)
+    c[0] = 1.0
+    plan = dbp.plan(N, kw.pop("n_spans"), kw.pop("steps_per_span"), taps=G.symmetric_full(c), beta2_ps2_km=b2,
+                    **kw)
+    if method == "auto":
+        method = "adjoint" if plan.workspace_size(grad=True) > 0 else "gauss_newton"
+    t0 = time.perf_counter()
+    if method == "adjoint":
+        c, info = G.fit_coefficients(plan, rx, nc, target=target, sl=sl)
+        info = {"method": "adjoint L-BFGS", **{k: v for k, v in info.items() if k != "message"}}
+        return G.symmetric_full(c), info
 
-    def full(c):
-        return np.concatenate([c[:0:-1], c]).astype(np.float32)
+    ns = plan.n_steps
 
     def resid(c):
-        k = dict(kw)
-        p = dbp.plan(N, k.pop("n_spans"), k.pop("steps_per_span"), taps=full(c), beta2_ps2_km=b2, **k)
-        y = p.backprop(rx)
+        w = torch.from_numpy(np.tile(G.symmetric_full(c), (ns, 1))).cuda()
+        y = plan.backprop(rx, taps=w)
         r = (y[0, :, sl] - target[0, :, sl]).reshape(-1)
         return torch.view_as_real(r).reshape(-1).double()
 
-    c = np.zeros(nc + 1)
-    c[0] = 1.0
     r0 = resid(c)
+    f_start = float(r0.square().sum())
+    n_eval = 1
     for _ in range(iters):
         h = 1e-3
         cols = []
@@ -97,11 +111,15 @@ def fit_taps(dbp, torch, rx, target, n_fit=100000, iters=8, nc=NC, plan_kw=None)
         step = torch.linalg.lstsq(jac, -r0.unsqueeze(1)).solution.squeeze(1).cpu().numpy()
         c = c + step
         r1 = resid(c)
+        n_eval += nc + 2
         if float(r1.norm()) > float(r0.norm()):
             c = c - step
             break
         r0 = r1
-    return full(c)
+    torch.cuda.synchronize()
+    info = {"method": "Gauss-Newton, forward-difference Jacobian", "objective_start": f_start,
+            "objective": float(r0.square().sum()), "evaluations": n_eval, "seconds": time.perf_counter() - t0}
+    return G.symmetric_full(c), info
 
 
 def paper_arrangement(dbp, torch, rx, sym, target, sweep, reps=20):
@@ -111,7 +129,7 @@ def paper_arrangement(dbp, torch, rx, sym, target, sweep, reps=20):
     the headline field; EVMs per launch power from the sweep."""
     b2 = siggen.beta2_ps2_km()
     out = torch.empty_like(rx)
-    taps = fit_taps(dbp, torch, rx, target, nc=32, plan_kw=dict(n_spans=SPANS, steps_per_span=1,
+    taps, _ = fit_taps(dbp, torch, rx, target, nc=32, plan_kw=dict(n_spans=SPANS, steps_per_span=1,
                                                                  spans_per_step=SPANS))
     res = {}
     for name, kw in [("essfm_1_step_link_nc32", dict(spans_per_step=SPANS, taps=taps)),
@@ -434,13 +452,13 @@ def evm_sweep_power(dbp, torch, powers):
         rx, sym = gpu_field(dbp, torch, pw)
         ssfm = dbp.plan(N, SPANS, 20, block=BLOCK, overlap=OVERLAP, beta2_ps2_km=b2)
         target = ssfm.backprop(rx)
-        taps = fit_taps(dbp, torch, rx, target)
+        taps, _ = fit_taps(dbp, torch, rx, target)
         essfm = dbp.plan(N, SPANS, 1, taps=taps, block=BLOCK, overlap=OVERLAP, beta2_ps2_km=b2)
         ssfm1 = dbp.plan(N, SPANS, 1, block=BLOCK, overlap=OVERLAP, beta2_ps2_km=b2)
         cd = dbp.plan(N, 1, 1, span_km=80.0 * SPANS, gamma_w_km=0.0, block=8192, overlap=2048,
                       beta2_ps2_km=b2)
         # the experiment's arrangement: one ESSFM step for the link (Nc = 32), SSFM over 2 spans
-        taps_link = fit_taps(dbp, torch, rx, target, nc=32,
+        taps_link, _ = fit_taps(dbp, torch, rx, target, nc=32,
                              plan_kw=dict(n_spans=SPANS, steps_per_span=1, spans_per_step=SPANS))
         essfm_link = dbp.plan(N, SPANS, 1, spans_per_step=SPANS, taps=taps_link, beta2_ps2_km=b2)
         ssfm_2span = dbp.plan(N, SPANS, 1, spans_per_step=2, beta2_ps2_km=b2)
@@ -510,8 +528,8 @@ def main():
     ssfm = dbp.plan(N, SPANS, 20, block=BLOCK, overlap=OVERLAP, beta2_ps2_km=b2)
     target = ssfm.backprop(rx)
     torch.cuda.synchronize()
-    taps = fit_taps(dbp, torch, rx, target)
-    log(f"fitted taps {np.round(taps, 5).tolist()}")
+    taps, fit_info = fit_taps(dbp, torch, rx, target)
+    log(f"fitted taps {np.round(taps, 5).tolist()} {json.dumps(fit_info)}")
     essfm = dbp.plan(N, SPANS, 1, taps=taps, block=BLOCK, overlap=OVERLAP, beta2_ps2_km=b2)
     evm_e = evm_db(essfm.backprop(rx), sym)
     evm_s = evm_db(target, sym)
@@ -541,6 +559,15 @@ def main():
             "essfm_vs_matching_ssfm_speedup": round(steps[n_eq]["ms"] / ms_e, 2) if n_eq else None,
             "ssfm_sweep": steps,
         }
+        taps_gn, info_gn = fit_taps(dbp, torch, rx, target, method="gauss_newton")
+        extras["coefficient_fit"] = {
+            "adjoint": {**{k: (round(v, 9) if isinstance(v, float) else v) for k, v in fit_info.items()},
+                        "c": [round(float(t), 6) for t in taps[NC:]]},
+            "gauss_newton": {**{k: (round(v, 9) if isinstance(v, float) else v) for k, v in info_gn.items()},
+                             "c": [round(float(t), 6) for t in taps_gn[NC:]]},
+            "objective": "sum over samples 1024..99999 of |ESSFM(c) - SSFM 20 steps/span|^2, both pols",
+        }
+        log("coefficient fit " + json.dumps(extras["coefficient_fit"]))
         extras["paper_arrangement"] = paper_arrangement(dbp, torch, rx, sym, target, sweep)
         log("paper arrangement " + json.dumps(extras["paper_arrangement"]))
         extras["paper_context"] = paper_context(extras["paper_arrangement"], ms_e, ms_s)
