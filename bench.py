@@ -192,7 +192,7 @@ def time_dbp_settled(torch, p, x, out, ws, reps=10, batches=5, warm_s=0.5):
     return float(np.median([time_dbp(torch, p, x, out, ws, 0, reps)[0] for _ in range(batches)]))
 
 
-def hbm_working_set(dbp, torch, rx, taps, batch=64, reps=10):
+def hbm_working_set(dbp, torch, rx, taps, batch=64, reps=10, only=None):
     """The ESSFM pass kernel on the field replicated `batch` times (256 MiB per state,
     beyond the 256 MB Infinity Cache), one launch per pass: k = 1 (one HBM round trip per
     step) and k = 2 on the smallest valid block, Nb=512 O=128 (and SSFM at k = 1), and k = 1 and k = 5 on
@@ -207,7 +207,11 @@ def hbm_working_set(dbp, torch, rx, taps, batch=64, reps=10):
     for name, k, nb, o, tp in (("k1_nb512", 1, 512, 128, taps), ("k2_nb512", 2, 512, 128, taps),
                                ("k1_nb512_ssfm", 1, 512, 128, None),
                                ("k1", 1, BLOCK, OVERLAP, taps), ("k5", 5, BLOCK, OVERLAP, taps)):
+        if only is not None and name != only:
+            continue
         for variant in ("stream", "per_block"):
+            if only is not None and variant != "stream":
+                continue
             if variant == "per_block":
                 os.environ["DBP_STREAM"] = "0"
             try:
@@ -220,7 +224,8 @@ def hbm_working_set(dbp, torch, rx, taps, batch=64, reps=10):
                 p.close()
                 continue
             ws = p.workspace()
-            ms = time_dbp_settled(torch, p, xb, out, ws, reps)
+            ms = (time_dbp_settled(torch, p, xb, out, ws, reps) if only is None
+                  else time_dbp(torch, p, xb, out, ws, 2, reps)[0])
             byts = batch * N * 2 * 8 * (nb / (nb - o) + 1)
             res[name if variant == "stream" else f"{name}_{variant}"] = {
                 "kernel": p.kernel, "us_per_launch": round(ms * 1e3, 2),
@@ -495,6 +500,9 @@ def main():
                     help="only the 0 dBm ESSFM/SSFM headline (for profiler runs)")
     ap.add_argument("--hbm-only", action="store_true",
                     help="only the large-working-set pass-kernel measurement")
+    ap.add_argument("--hbm-case", default=None,
+                    help="with --hbm-only: one case (e.g. k1_nb512), streaming kernel, 2 + 10 launches "
+                         "(for counter runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a plain 1 GiB device copy three times and exit (counter calibration)")
     args = ap.parse_args()
@@ -515,7 +523,7 @@ def main():
     if args.hbm_only:
         rx, _ = gpu_field(dbp, torch, P_DBM)
         taps = siggen.symmetric_taps(siggen.rng(1, 0, 7), NC)
-        print(json.dumps(hbm_working_set(dbp, torch, rx, taps)), flush=True)
+        print(json.dumps(hbm_working_set(dbp, torch, rx, taps, only=args.hbm_case)), flush=True)
         return
 
     sweep = None
