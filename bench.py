@@ -237,6 +237,27 @@ def hbm_working_set(dbp, torch, rx, taps, batch=64, reps=10, only=None):
     return res
 
 
+def fft_gradient(torch, plan, rx, reps=10):
+    """Reverse mode of the headline ESSFM cascade (Nb=1024 O=256, k=5): input and tap
+    gradients for a fixed upstream gradient; one call = forward storing the 8 pass inputs +
+    8 reverse passes + the input-gradient gather + the tap reduction."""
+    g = torch.view_as_complex(torch.randn(*rx.shape, 2, device="cuda", generator=torch.Generator(
+        device="cuda").manual_seed(5)))
+    ws = plan.workspace(grad=True)
+    for _ in range(2):
+        plan.backprop_grad(rx, g, workspace=ws)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        plan.backprop_grad(rx, g, workspace=ws)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    return {"workload": "headline ESSFM 40 steps on 2x262144, Nb=1024 O=256 k=5: d/dx and d/dw",
+            "fwd_bwd_ms": round(ms, 4), "workspace_mib": round(ws.numel() / 2**20, 1)}
+
+
 def grad_workload(dbp, torch, reps=5):
     """Differentiation workload: 64 PM signals x 32768 samples at 3200 km, ESSFM 40 steps with
     per-step 9-tap c_k and 33-tap complex dispersion FIRs (least-squares fit of Eq. (1) over
@@ -576,6 +597,8 @@ def main():
             "objective": "sum over samples 1024..99999 of |ESSFM(c) - SSFM 20 steps/span|^2, both pols",
         }
         log("coefficient fit " + json.dumps(extras["coefficient_fit"]))
+        extras["fft_gradient"] = fft_gradient(torch, essfm, rx)
+        log("FFT-step gradient " + json.dumps(extras["fft_gradient"]))
         extras["paper_arrangement"] = paper_arrangement(dbp, torch, rx, sym, target, sweep)
         log("paper arrangement " + json.dumps(extras["paper_arrangement"]))
         extras["paper_context"] = paper_context(extras["paper_arrangement"], ms_e, ms_s)

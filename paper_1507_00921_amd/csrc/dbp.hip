@@ -75,10 +75,9 @@ int default_e(int nb, long long n_wg) {
 }
 
 // Polarization-split blocks: measured on the 2x262144 workload at Nb = 1024
-// (342 blocks), SSFM runs 3% faster split and ESSFM 50% slower (the tap filter
-// then reads both groups' intensities), so only SSFM launches with fewer blocks
-// than two per CU are split.  DBP_FORCE_SPLIT=0/1 overrides where a split
-// variant exists.
+// (342 blocks), SSFM runs 7% faster split and ESSFM equally fast, so only SSFM
+// launches with fewer blocks than two per CU are split.  DBP_FORCE_SPLIT=0/1
+// overrides where a split variant exists.
 static bool default_split(int nb, int e, int npol, int nt, long long n_wg) {
     if (npol != 2 || !find_kernel(nb, e, 2, false, -1, true)) return false;
     if (const char* f = std::getenv("DBP_FORCE_SPLIT")) return std::atoi(f) != 0;

@@ -299,14 +299,19 @@ __device__ __forceinline__ void process_block(const BlockJob& a, const TwReg<NB,
 }
 
 // Polarization-split block routine: two groups of NB/E threads, group g
-// transforms polarization g (its own exchange buffers, shared barriers), and
-// the groups meet once per step in LDS for the total intensity.  Twice the
-// waves per block with half the registers per thread: for launches with too
-// few blocks to fill the chip.
+// transforms polarization g (its own exchange buffers, shared barriers).  Both
+// groups hold the same sample positions, so the nonlinear substep is shared
+// out instead of repeated: group g sums the two intensities, filters them
+// (ESSFM) and forms the phase factor for half of the positions (its values
+// q < E/2 or q >= E/2) and the factors meet in LDS.  Twice the waves per
+// block with half the registers per thread and about the same arithmetic per
+// block: for launches with too few blocks to fill the chip.
 template <int NB, int E> struct SplitSmem {
     using X = Exchange<NB, E, 1>;
     float2 lds[2 * X::FLOATS2];
     float ipol[2][NB];
+    float isum[NB];
+    float2 fac[NB];
 };
 
 template <int NB, int E, bool PHASE64, int NT>
@@ -315,9 +320,11 @@ __device__ __forceinline__ void process_block_split(const BlockJob& a, const TwR
     using S = FftShape<NB, E>;
     using X = Exchange<NB, E, 1>;
     constexpr int T = S::T;
-    static_assert(T > 64 && X::NBUF == 2, "split blocks exchange through two buffers per group");
+    constexpr int H = E / 2;
+    static_assert(T > 64 && X::NBUF == 2 && E % 2 == 0, "split blocks exchange through two buffers per group");
     const int grp = threadIdx.x >= T ? 1 : 0;
     const int t = threadIdx.x - grp * T;
+    const int q0 = grp * H;       // this group's half of the positions for the nonlinear substep
     float2* lds = sm.lds + grp * X::FLOATS2;
     const long long L = a.L;
     const long long start = (long long)a.blk * a.V - a.halo;
@@ -333,12 +340,12 @@ __device__ __forceinline__ void process_block_split(const BlockJob& a, const TwR
     const int ntaps = NT >= 0 ? NT : a.ntaps;
     const int c = (ntaps - 1) >> 1;
     for (int s = a.s0; s < a.s0 + a.ks; ++s) {
-        const StepDev st = a.steps[s];
+        const StepDev st = load_step(a.steps + s);
         const float2* __restrict__ hs = a.H + st.h_off;
         float2 h[E];
 #pragma unroll
         for (int q = 0; q < E; ++q) h[q] = hs[t + T * q];
-        const float* __restrict__ w = a.taps + (long long)s * ntaps;
+        const auto w = as_const(a.taps) + (long long)s * ntaps;
         float wr[NT > 0 ? NT : 1];
         if constexpr (NT > 0) {
 #pragma unroll
@@ -349,41 +356,45 @@ __device__ __forceinline__ void process_block_split(const BlockJob& a, const TwR
 #pragma unroll
         for (int q = 0; q < E; ++q) v[0][q] = cmul(v[0][q], h[q]);
         block_fft<NB, E, 1, true>(v, lds, twr, t);
-        // (iv): |y_g|^2 of each group, summed over both when read back
+        // (iv): |y_g|^2 of each group; total intensity, tap filter and phase factor
+        // for this group's half of the positions
 #pragma unroll
         for (int q = 0; q < E; ++q) sm.ipol[grp][t + T * q] = fmaf(v[0][q].x, v[0][q].x, v[0][q].y * v[0][q].y);
         __syncthreads();
-        float J[E];
-        if constexpr (NT == 0) {
+        float J[H];
 #pragma unroll
-            for (int q = 0; q < E; ++q) J[q] = sm.ipol[0][t + T * q] + sm.ipol[1][t + T * q];
-        } else {
+        for (int k = 0; k < H; ++k) {
+            const int i = t + T * (q0 + k);
+            J[k] = sm.ipol[0][i] + sm.ipol[1][i];
+        }
+        if constexpr (NT != 0) {
 #pragma unroll
-            for (int q = 0; q < E; ++q) J[q] = 0.f;
+            for (int k = 0; k < H; ++k) sm.isum[t + T * (q0 + k)] = J[k];
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < H; ++k) J[k] = 0.f;
             if constexpr (NT > 0) {
 #pragma unroll
                 for (int m = 0; m < NT; ++m)
 #pragma unroll
-                    for (int q = 0; q < E; ++q) {
-                        const int i = (t + T * q - m + c) & (NB - 1);
-                        J[q] = fmaf(wr[m], sm.ipol[0][i] + sm.ipol[1][i], J[q]);
-                    }
+                    for (int k = 0; k < H; ++k)
+                        J[k] = fmaf(wr[m], sm.isum[(t + T * (q0 + k) - m + c) & (NB - 1)], J[k]);
             } else {
                 for (int m = 0; m < ntaps; ++m) {
                     const float wm = w[m];
 #pragma unroll
-                    for (int q = 0; q < E; ++q) {
-                        const int i = (t + T * q - m + c) & (NB - 1);
-                        J[q] = fmaf(wm, sm.ipol[0][i] + sm.ipol[1][i], J[q]);
-                    }
+                    for (int k = 0; k < H; ++k) J[k] = fmaf(wm, sm.isum[(t + T * (q0 + k) - m + c) & (NB - 1)], J[k]);
                 }
             }
         }
-        float2 r[E];
-        phase_factors<PHASE64, E>(J, st, r);
+        float2 f[H];
+        phase_factors<PHASE64, H>(J, st, f);
 #pragma unroll
-        for (int q = 0; q < E; ++q) v[0][q] = cmul(v[0][q], r[q]);
-        // ipol is rewritten after the next step's exchanges, each behind a barrier
+        for (int k = 0; k < H; ++k) sm.fac[t + T * (q0 + k)] = f[k];
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < E; ++q) v[0][q] = cmul(v[0][q], sm.fac[t + T * q]);
+        // ipol, isum and fac are rewritten only after the next step's exchange barriers
     }
 
 #pragma unroll
