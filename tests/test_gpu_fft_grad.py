@@ -124,3 +124,43 @@ def test_fft_grad_finite_difference_of_gpu_forward(dbp):
     an = float(np.sum(gt.cpu().numpy().astype(np.float64) * d))
     print(f"directional derivative: adjoint {an:.6e}, central difference {fd:.6e}")
     assert abs(an - fd) <= 2e-3 * abs(fd) + 1e-6
+
+
+def test_fft_grad_argument_rules(dbp):
+    # workspace sizes, the FIR-only argument, unsupported plans and overlapping buffers
+    import ctypes
+    n = 4096
+    p = dbp.plan(n, 4, 1, taps=np.full(9, 0.1, np.float32), block=1024, overlap=256, steps_per_pass=2,
+                 beta2_ps2_km=B2)
+    ws = p.workspace_size(grad=True)
+    # pass inputs 1..: one state; block states of step 2 of a pass, two window sets, partials
+    n_wg = -(-n // 768)
+    state = 2 * n * 8
+    window = n_wg * 2 * 1024 * 8
+    assert ws == state + window + 2 * window + 4 * 9 * n_wg * 4
+    x = torch.zeros(1, 2, n, dtype=torch.complex64, device="cuda")
+    g = torch.zeros_like(x)
+    L = dbp.lib()
+    w = p.workspace(grad=True)
+    gf = torch.zeros(4, 33, dtype=torch.complex64, device="cuda")
+    st = L.dbp_backprop_grad(p.handle, ctypes.c_void_p(x.data_ptr()), None, None, ctypes.c_void_p(g.data_ptr()),
+                             None, None, ctypes.c_void_p(gf.data_ptr()), ctypes.c_void_p(w.data_ptr()), w.numel(),
+                             None)
+    assert st == 1          # grad_fir given for an FFT-step plan
+    st = L.dbp_backprop_grad(p.handle, ctypes.c_void_p(x.data_ptr()), None, None, ctypes.c_void_p(g.data_ptr()),
+                             ctypes.c_void_p(g.data_ptr()), None, None, ctypes.c_void_p(w.data_ptr()), w.numel(),
+                             None)
+    assert st == 1          # grad_in overlaps grad_out
+    st = L.dbp_backprop_grad(p.handle, ctypes.c_void_p(x.data_ptr()), None, None, ctypes.c_void_p(g.data_ptr()),
+                             None, None, None, ctypes.c_void_p(w.data_ptr()), w.numel() - 1, None)
+    assert st == 3          # workspace too small
+    torch.cuda.synchronize()
+    # no reverse kernel: the split-precision variant and 8192-point blocks
+    for q in (dbp.plan(n, 4, 1, block=1024, overlap=256, precision=dbp.BF16X3, beta2_ps2_km=B2),
+              dbp.plan(16384, 2, 1, block=8192, overlap=1024, beta2_ps2_km=B2)):
+        assert q.workspace_size(grad=True) == 0
+        with pytest.raises(dbp.DbpError) as e:
+            q.backprop_grad(torch.zeros(1, 2, q.shape[2], dtype=torch.complex64, device="cuda"),
+                            torch.zeros(1, 2, q.shape[2], dtype=torch.complex64, device="cuda"),
+                            workspace=torch.zeros(16, dtype=torch.uint8, device="cuda"))
+        assert e.value.status == 2
