@@ -258,6 +258,36 @@ def fft_gradient(torch, plan, rx, reps=10):
             "fwd_bwd_ms": round(ms, 4), "workspace_mib": round(ws.numel() / 2**20, 1)}
 
 
+def receiver_workload(dbp, torch, rx_field, taps, chunk_blocks=64, pushes=40):
+    """Receiver mode on the headline link: the 2x262144 field pushed as a stream in chunks of
+    chunk_blocks x 768 samples, ESSFM (1 step/span, 9 taps) and SSFM (20 steps/span).  Time
+    per push (HIP events, after a warm-up), throughput, and the latency the block pipeline
+    adds (samples and ns at 56 GSa/s)."""
+    b2 = siggen.beta2_ps2_km()
+    chunk = chunk_blocks * (BLOCK - OVERLAP)
+    x = rx_field.reshape(2, N)
+    res = {"chunk": chunk}
+    for name, kw in (("essfm", dict(steps_per_span=1, taps=taps)), ("ssfm_20", dict(steps_per_span=20))):
+        r = dbp.receiver(chunk, SPANS, kw.pop("steps_per_span"), block=BLOCK, overlap=OVERLAP, beta2_ps2_km=b2, **kw)
+        chunks = [x[:, (i * chunk) % (N - chunk):(i * chunk) % (N - chunk) + chunk].contiguous() for i in range(8)]
+        out = torch.empty_like(chunks[0])
+        for i in range(8):
+            r.push(chunks[i], out=out)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for i in range(pushes):
+            r.push(chunks[i % 8], out=out)
+        e1.record()
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) / pushes * 1e3
+        res[name] = {"passes": r.n_passes, "steps_per_pass": r.steps_per_pass, "us_per_push": round(us, 2),
+                     "msamples_per_s": round(chunk / us, 1), "latency_samples": r.latency,
+                     "latency_ns": round(r.latency / siggen.FS_THZ / 1e3, 1)}
+        r.close()
+    return res
+
+
 def grad_workload(dbp, torch, reps=5):
     """Differentiation workload: 64 PM signals x 32768 samples at 3200 km, ESSFM 40 steps with
     per-step 9-tap c_k and 33-tap complex dispersion FIRs (least-squares fit of Eq. (1) over
@@ -599,6 +629,8 @@ def main():
         log("coefficient fit " + json.dumps(extras["coefficient_fit"]))
         extras["fft_gradient"] = fft_gradient(torch, essfm, rx)
         log("FFT-step gradient " + json.dumps(extras["fft_gradient"]))
+        extras["receiver"] = receiver_workload(dbp, torch, rx, taps)
+        log("receiver mode " + json.dumps(extras["receiver"]))
         extras["paper_arrangement"] = paper_arrangement(dbp, torch, rx, sym, target, sweep)
         log("paper arrangement " + json.dumps(extras["paper_arrangement"]))
         extras["paper_context"] = paper_context(extras["paper_arrangement"], ms_e, ms_s)

@@ -235,6 +235,43 @@ dbp_status dbp_backprop_batch(dbp_plan_t plan, const void* in_packed, void* out_
  * a dependency wait exceeded its bound and the block was skipped). */
 dbp_status dbp_batch_status(dbp_plan_t plan, int32_t* flags);
 
+/* Receiver mode (the latency discussion of Sec. III): the received field as an
+ * unbounded stream x[n], n >= 0, preceded by silence, pushed in chunks and
+ * backpropagated through the same passes and overlap-and-save blocks as
+ * dbp_backprop, without the wrap at the signal ends: block b of every pass has
+ * the window [bV - O/2, bV - O/2 + Nb) and keeps [bV, bV + V), and a pass
+ * computes a block once its window lies inside the samples it has.  Each pass
+ * trails the previous one by c = ceil((O/2) / V) blocks, so the output trails the
+ * input by D = n_passes * c * V samples: push i (counted from creation or the
+ * last reset) returns the output samples [i C - D, (i + 1) C - D), zeros before
+ * n = 0.  The output equals that of dbp_backprop on the whole stream preceded by
+ * enough silence, up to the end effects of the latter's wrap. */
+typedef struct dbp_rx_s* dbp_rx_t;
+
+/* Create a receiver for desc's link, method and geometry (batch 1, FFT linear
+ * step, not BF16X3, not DBP_FLAG_WHOLE; desc->n_samples is ignored: the planner
+ * sees the chunk length).  chunk: samples per polarization per push, >= Nb and a
+ * multiple of V = Nb - O (DBP_ERR_INVALID_ARG otherwise).  Block sizes
+ * 256..4096 (DBP_ERR_UNSUPPORTED otherwise).  The receiver owns its device
+ * state (one ring per pass, allocated and cleared here, synchronously, on the
+ * current device); *out is NULL on error. */
+dbp_status dbp_rx_create(const dbp_desc* desc, int64_t chunk, dbp_rx_t* out);
+
+/* Latency D in samples and the geometry in use.  Any pointer may be NULL. */
+dbp_status dbp_rx_info(dbp_rx_t rx, int64_t* latency, int32_t* block, int32_t* overlap,
+                       int32_t* steps_per_pass, int32_t* n_passes);
+
+/* Push the next chunk: in and out are device complex64 [n_pol][chunk] (not
+ * overlapping).  Asynchronous on stream; pushes on one receiver must be issued in
+ * order on one stream (the receiver's state advances on the host at each call). */
+dbp_status dbp_rx_push(dbp_rx_t rx, const void* in, void* out, void* stream);
+
+/* Restart at n = 0 with silence before it (asynchronous on stream). */
+dbp_status dbp_rx_reset(dbp_rx_t rx, void* stream);
+
+/* Release the receiver (NULL is a no-op); no push may still be running. */
+void dbp_rx_destroy(dbp_rx_t rx);
+
 /* Short static description of a status code. */
 const char* dbp_status_string(dbp_status s);
 

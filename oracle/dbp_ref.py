@@ -205,6 +205,43 @@ def run_blocked(x: np.ndarray, steps: Sequence[Step], fs_thz: float, nb: int, ov
     return y
 
 
+def run_streaming(x: np.ndarray, steps: Sequence[Step], fs_thz: float, nb: int, overlap: int,
+                  k: int) -> np.ndarray:
+    """Receiver mode of the overlap-and-save cascade: a stream x[n], n >= 0, preceded by
+    silence, with nothing known after its last sample.
+
+    Blocks b have the windows [bV - O/2, bV - O/2 + Nb) of run_blocked, without the wrap, on
+    the silence-extended stream: each pass of k steps computes the blocks whose window lies
+    inside the samples it has (the silence, then what the previous pass produced) and keeps
+    their centres [bV, bV + V).  Returns every output sample n >= 0 computable from x."""
+    u = np.asarray(x, dtype=np.complex128)
+    v = nb - overlap
+    h = overlap // 2
+    # silence before the stream, a whole number of blocks, long enough that the first block
+    # every pass needs starts inside it: pass p reads from block -(passes - 1 - p) ceil(h/V)
+    z = ((passes(len(steps), k) - 1) * (-(-h // v)) + 1) * v
+    u = np.concatenate([np.zeros(u.shape[:-1] + (z,), dtype=np.complex128), u], axis=-1)
+    for p0 in range(0, len(steps), k):
+        e = u.shape[-1]
+        n_blk = max((e - h) // v, 0)
+        padded = np.concatenate([np.zeros(u.shape[:-1] + (h,), dtype=np.complex128), u], axis=-1)
+        out = np.zeros(u.shape[:-1] + (n_blk * v,), dtype=np.complex128)
+        for b in range(n_blk):
+            g = padded[..., b * v:b * v + nb]                      # samples bV - h .. bV - h + Nb - 1
+            for st in steps[p0:p0 + k]:
+                g = step(g, st, fs_thz)
+            out[..., b * v:(b + 1) * v] = g[..., h:h + v]
+        u = out
+    return u[..., z:]
+
+
+def streaming_latency(n_steps: int, nb: int, overlap: int, k: int) -> int:
+    """Samples by which the receiver-mode output trails its input: one block per pass."""
+    v = nb - overlap
+    h = overlap // 2
+    return passes(n_steps, k) * (-(-h // v)) * v
+
+
 def passes(n_steps: int, k: int) -> int:
     return -(-n_steps // k)
 

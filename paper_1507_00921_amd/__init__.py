@@ -92,6 +92,16 @@ def lib():
         L.dbp_batch_status.restype = c_int32
         L.dbp_fir_taps.argtypes = [POINTER(Desc), c_int32, POINTER(c_float)]
         L.dbp_fir_taps.restype = c_int32
+        L.dbp_rx_create.argtypes = [POINTER(Desc), c_int64, POINTER(c_void_p)]
+        L.dbp_rx_create.restype = c_int32
+        L.dbp_rx_info.argtypes = [c_void_p, POINTER(c_int64)] + [POINTER(c_int32)] * 4
+        L.dbp_rx_info.restype = c_int32
+        L.dbp_rx_push.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p]
+        L.dbp_rx_push.restype = c_int32
+        L.dbp_rx_reset.argtypes = [c_void_p, c_void_p]
+        L.dbp_rx_reset.restype = c_int32
+        L.dbp_rx_destroy.argtypes = [c_void_p]
+        L.dbp_rx_destroy.restype = None
         L.dbp_status_string.argtypes = [c_int32]
         L.dbp_status_string.restype = ctypes.c_char_p
         L.dbp_version.argtypes = []
@@ -353,6 +363,54 @@ class BatchPlan:
         v = c_int32()
         _check(lib().dbp_batch_status(self._h, ctypes.byref(v)), "dbp_batch_status")
         return v.value
+
+
+class Receiver:
+    """A dbp_rx: the receiver mode (an unbounded stream pushed in chunks, fixed latency)."""
+
+    def __init__(self, desc: Desc, chunk: int):
+        self.desc = desc
+        h = c_void_p()
+        _check(lib().dbp_rx_create(ctypes.byref(desc), chunk, ctypes.byref(h)), "dbp_rx_create")
+        self._h = h
+        lat = c_int64()
+        nb, o, k, npass = (c_int32() for _ in range(4))
+        _check(lib().dbp_rx_info(h, ctypes.byref(lat), ctypes.byref(nb), ctypes.byref(o), ctypes.byref(k),
+                                 ctypes.byref(npass)), "dbp_rx_info")
+        self.latency = lat.value
+        self.block, self.overlap, self.steps_per_pass, self.n_passes = nb.value, o.value, k.value, npass.value
+        self.chunk = chunk
+        self.n_pol = desc.n_pol
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().dbp_rx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def push(self, x, out=None, stream=None):
+        """Push complex64 [n_pol][chunk] (CUDA); returns the output samples
+        [i C - latency, (i + 1) C - latency) of push i."""
+        import torch
+        if x.dtype != torch.complex64 or not x.is_cuda or not x.is_contiguous() or \
+                x.numel() != self.n_pol * self.chunk:
+            raise ValueError(f"chunk must be a contiguous complex64 CUDA tensor of {self.n_pol} x {self.chunk}")
+        if out is None:
+            out = torch.empty_like(x)
+        _check(lib().dbp_rx_push(self._h, _ptr(x), _ptr(out), _stream_ptr(stream)), "dbp_rx_push")
+        return out
+
+    def reset(self, stream=None):
+        _check(lib().dbp_rx_reset(self._h, _stream_ptr(stream)), "dbp_rx_reset")
+
+
+def receiver(chunk: int, n_spans: int, steps_per_span: int = 1, **kw) -> Receiver:
+    return Receiver(make_desc(chunk, n_spans, steps_per_span, **kw), chunk)
 
 
 def plan_batch(descs) -> BatchPlan:

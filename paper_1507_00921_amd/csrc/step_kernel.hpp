@@ -523,4 +523,54 @@ __global__ __launch_bounds__(NB / E) void dbp_stream_kernel(PassArgs a) {
     }
 }
 
+// Receiver-mode pass: the blocks [blk0, blk0 + gridDim.x) of an unbounded
+// stream whose samples live in power-of-two rings indexed by the sample number
+// (sample n of polarization p at ring[p * stride + (n & mask)], n may be
+// negative).  Same block routine as the circular pass; no wrap at signal ends,
+// the caller keeps every sample a block reads in its ring.
+struct RingArgs {
+    long long blk0;
+    int in_mask, out_mask;
+    long long in_stride, out_stride;
+};
+
+template <int NB, int E, int NPOL, bool PHASE64, int NT>
+__global__ __launch_bounds__(NB / E) void dbp_ring_pass_kernel(PassArgs a, RingArgs r) {
+    constexpr int T = NB / E;
+    __shared__ BlockSmem<NB, E, NPOL, NT> sm;
+    const int t = threadIdx.x;
+    TwReg<NB, E> twr;
+    load_twiddles<NB, E>(twr, a.tw, t);
+    const long long b = r.blk0 + blockIdx.x;
+    const long long start = b * a.V - a.halo;
+    float2 v[NPOL][E];
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+        const long long i = (start + t + T * q) & r.in_mask;
+#pragma unroll
+        for (int p = 0; p < NPOL; ++p) v[p][q] = a.in[p * r.in_stride + i];
+    }
+    BlockJob j;
+    j.L = a.L;
+    j.V = a.V;
+    j.halo = a.halo;
+    j.blk = 0;
+    j.steps = a.steps;
+    j.s0 = a.s0;
+    j.ks = a.ks;
+    j.H = a.H;
+    j.taps = a.taps;
+    j.ntaps = a.ntaps;
+    run_steps<NB, E, NPOL, PHASE64, NT>(v, j, twr, sm, nullptr);
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+        const int pos = t + T * q;
+        if (pos >= a.halo && pos < a.halo + a.V) {
+            const long long o = (b * a.V + pos - a.halo) & r.out_mask;
+#pragma unroll
+            for (int p = 0; p < NPOL; ++p) a.out[p * r.out_stride + o] = v[p][q];
+        }
+    }
+}
+
 }  // namespace dbp
