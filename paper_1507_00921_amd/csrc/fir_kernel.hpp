@@ -22,6 +22,7 @@ constexpr int FT_THREADS = 256;
 constexpr int FT_TS = 1024;       // output samples per tile
 constexpr int FT_MAXH = 64;       // largest FIR half-width
 constexpr int FT_MAXC = 64;       // largest tap half-width
+constexpr int FR = 4;             // consecutive outputs per thread in the compile-time-tap FIR loops
 
 struct FirArgs {
     const float2* x;        // step input [n_sig][NPOL][L]
@@ -61,6 +62,46 @@ __device__ __forceinline__ void fir_u(float2* us, float* is, const float2* xs, i
                                       const float2* hs, int nfir_rt) {
     const int nfir = NF > 0 ? NF : nfir_rt;
     const int hf2 = nfir - 1;
+    if constexpr (NF > 0) {
+        // FR consecutive outputs per thread from a window of FR + NF - 1 samples held in
+        // registers: every sample read from LDS serves up to FR outputs
+        constexpr int W = FR + NF - 1;
+        for (int base = threadIdx.x * FR; base < n_out; base += FT_THREADS * FR) {
+            float in[FR];
+#pragma unroll
+            for (int r = 0; r < FR; ++r) in[r] = 0.f;
+#pragma unroll
+            for (int p = 0; p < NPOL; ++p) {
+                // u[i] = sum_m h[m] x[i + NF - 1 - m]: window j = r - m + NF - 1
+                float2 win[W];
+#pragma unroll
+                for (int j = 0; j < W; ++j)
+                    win[j] = base + j < nx ? xs[p * nx + base + j] : make_float2(0.f, 0.f);
+                float2 acc[FR];
+#pragma unroll
+                for (int r = 0; r < FR; ++r) acc[r] = make_float2(0.f, 0.f);
+#pragma unroll
+                for (int m = 0; m < NF; ++m) {
+                    const float2 hv = hs[m];
+#pragma unroll
+                    for (int r = 0; r < FR; ++r) {
+                        const float2 xv = win[r - m + NF - 1];
+                        acc[r].x = fmaf(hv.x, xv.x, fmaf(-hv.y, xv.y, acc[r].x));
+                        acc[r].y = fmaf(hv.x, xv.y, fmaf(hv.y, xv.x, acc[r].y));
+                    }
+                }
+#pragma unroll
+                for (int r = 0; r < FR; ++r) {
+                    if (base + r < n_out) us[p * n_out + base + r] = acc[r];
+                    in[r] = fmaf(acc[r].x, acc[r].x, fmaf(acc[r].y, acc[r].y, in[r]));
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < FR; ++r)
+                if (base + r < n_out) is[base + r] = in[r];
+        }
+        return;
+    }
     for (int i = threadIdx.x; i < n_out; i += FT_THREADS) {
         float in = 0.f;
 #pragma unroll
@@ -231,6 +272,35 @@ __global__ __launch_bounds__(FT_THREADS) void fir_adjoint_kernel(FirArgs a) {
     }
     __syncthreads();
     // input gradient: g_x[o] = sum_m conj(h[m]) g_u[o + m - HF]
+    if constexpr (NF > 0) {
+        // FR consecutive outputs per thread, window j = r + m of g_u in registers
+        constexpr int W = FR + NF - 1;
+        for (int base = t * FR; base < FT_TS; base += FT_THREADS * FR) {
+#pragma unroll
+            for (int p = 0; p < NPOL; ++p) {
+                const float2* gr = gzs + p * nz + NC + base;     // g_u at base - HF
+                float2 win[W];
+#pragma unroll
+                for (int j = 0; j < W; ++j) win[j] = gr[j];
+                float2 acc[FR];
+#pragma unroll
+                for (int r = 0; r < FR; ++r) acc[r] = make_float2(0.f, 0.f);
+#pragma unroll
+                for (int m = 0; m < NF; ++m) {
+                    const float2 hv = hs[m];
+#pragma unroll
+                    for (int r = 0; r < FR; ++r) {
+                        const float2 g = win[r + m];
+                        acc[r].x = fmaf(hv.x, g.x, fmaf(hv.y, g.y, acc[r].x));
+                        acc[r].y = fmaf(hv.x, g.y, fmaf(-hv.y, g.x, acc[r].y));
+                    }
+                }
+#pragma unroll
+                for (int r = 0; r < FR; ++r)
+                    if (a0 + base + r < L) gx[p * L + a0 + base + r] = acc[r];
+            }
+        }
+    } else
     for (int o = t; o < FT_TS; o += FT_THREADS) {
         if (a0 + o >= L) break;
 #pragma unroll
@@ -262,22 +332,39 @@ __global__ __launch_bounds__(FT_THREADS) void fir_adjoint_kernel(FirArgs a) {
         float acc[W];
 #pragma unroll
         for (int j = 0; j < W; ++j) acc[j] = 0.f;
-        for (int o = t; o < n_own; o += FT_THREADS) {
+        // FR consecutive outputs o0 + r per thread; x[o + 3HF + 2NC - l] from a window
+        // j = r - l + NF - 1 held in registers
+        constexpr int WX = FR + NF - 1;
+        for (int o0 = t * FR; o0 < n_own; o0 += FT_THREADS * FR) {
 #pragma unroll
             for (int p = 0; p < NPOL; ++p) {
-                const float2 g = gzs[p * nz + NC + HF + o];
-                const float2* xr = xs + p * nx + o + 3 * HF + 2 * NC;
+                float2 g[FR];
 #pragma unroll
-                for (int l = 0; l < NF; ++l) {
-                    const float2 xv = xr[-l];
-                    acc[NWC + 2 * l] = fmaf(g.x, xv.x, fmaf(g.y, xv.y, acc[NWC + 2 * l]));
-                    acc[NWC + 2 * l + 1] = fmaf(g.y, xv.x, fmaf(-g.x, xv.y, acc[NWC + 2 * l + 1]));
-                }
+                for (int r = 0; r < FR; ++r)
+                    g[r] = o0 + r < n_own ? gzs[p * nz + NC + HF + o0 + r] : make_float2(0.f, 0.f);
+                const float2* xr = xs + p * nx + o0 + 3 * HF + 2 * NC - (NF - 1);
+                float2 win[WX];
+#pragma unroll
+                for (int j = 0; j < WX; ++j) win[j] = xr[j];
+#pragma unroll
+                for (int l = 0; l < NF; ++l)
+#pragma unroll
+                    for (int r = 0; r < FR; ++r) {
+                        const float2 xv = win[r - l + NF - 1];
+                        acc[NWC + 2 * l] = fmaf(g[r].x, xv.x, fmaf(g[r].y, xv.y, acc[NWC + 2 * l]));
+                        acc[NWC + 2 * l + 1] = fmaf(g[r].y, xv.x, fmaf(-g[r].x, xv.y, acc[NWC + 2 * l + 1]));
+                    }
             }
             if constexpr (NWC > 0) {
-                const float jv = jb[o + HF + NC];
 #pragma unroll
-                for (int m = 0; m < NWC; ++m) acc[m] = fmaf(jv, is[o + HF + 3 * NC - m], acc[m]);
+                for (int r = 0; r < FR; ++r) {
+                    const int o = o0 + r;
+                    if (o < n_own) {
+                        const float jv = jb[o + HF + NC];
+#pragma unroll
+                        for (int m = 0; m < NWC; ++m) acc[m] = fmaf(jv, is[o + HF + 3 * NC - m], acc[m]);
+                    }
+                }
             }
         }
         // x, u and g_z are no longer read: their LDS holds the reduction, 16 parameters
