@@ -139,7 +139,7 @@ struct BlockJob {
 template <int NB, int E, int NPOL, int NT> struct BlockSmem {
     using X = Exchange<NB, E, NPOL>;
     static constexpr bool OWN_I = X::NBUF == 2 && NT != 0;
-    float2 lds[X::FLOATS2];
+    alignas(16) float2 lds[X::FLOATS2];
     float ilds_own[OWN_I ? NB : 1];
 };
 
@@ -215,7 +215,41 @@ __device__ __forceinline__ void run_steps(float2 (&v)[NPOL][E], const BlockJob& 
             for (int p = 0; p < NPOL; ++p) in = fmaf(v[p][q].x, v[p][q].x, fmaf(v[p][q].y, v[p][q].y, in));
             J[q] = in;
         }
-        if constexpr (NT != 0) {
+        if constexpr (NT > 0 && T == 64) {
+            // one wave: LDS operations run in order, no barrier.  Each thread filters the
+            // E consecutive positions E t .. E t + E - 1 from a window read as float4s,
+            // writes them back in place (every lane's reads precede every write), then
+            // reads the filtered values of its own positions t + T q.
+            constexpr int C = (NT - 1) / 2;
+            constexpr int CA = (C + 3) & ~3;
+            constexpr int WN = E + 2 * CA;
+            static_assert(E % 4 == 0, "float4 window");
+#pragma unroll
+            for (int q = 0; q < E; ++q) ilds[t + T * q] = J[q];
+            float win[WN];
+#pragma unroll
+            for (int i = 0; i < WN / 4; ++i) {
+                const float4 f = *reinterpret_cast<const float4*>(ilds + ((E * t - CA + 4 * i) & (NB - 1)));
+                win[4 * i] = f.x;
+                win[4 * i + 1] = f.y;
+                win[4 * i + 2] = f.z;
+                win[4 * i + 3] = f.w;
+            }
+            float jb[E];
+#pragma unroll
+            for (int k = 0; k < E; ++k) {
+                float acc = 0.f;
+#pragma unroll
+                for (int m = 0; m < NT; ++m) acc = fmaf(wr[m], win[k - m + C + CA], acc);
+                jb[k] = acc;
+            }
+#pragma unroll
+            for (int i = 0; i < E / 4; ++i)
+                *reinterpret_cast<float4*>(ilds + E * t + 4 * i) =
+                    make_float4(jb[4 * i], jb[4 * i + 1], jb[4 * i + 2], jb[4 * i + 3]);
+#pragma unroll
+            for (int q = 0; q < E; ++q) J[q] = ilds[t + T * q];
+        } else if constexpr (NT != 0) {
 #pragma unroll
             for (int q = 0; q < E; ++q) ilds[t + T * q] = J[q];
             __syncthreads();
