@@ -121,3 +121,30 @@ def test_precision_report_800_steps(dbp):
     assert report["bf16x3"][0] <= split_bound(800)
     for name, (_, d) in report.items():
         assert abs(d) <= 0.01, name
+
+
+def test_precision_workload_full_size_sampled(dbp):
+    """The precision workload at its full size, 2 x 4194304 samples, SSFM 800 steps on
+    Nb = 1024, O = 256 with the planner's steps per pass (the launches bench.py times),
+    checked on sampled blocks.  A block's output after P passes depends on the input within
+    about P blocks of it, so the oracle runs the same blocked cascade on a window aligned to
+    the block grid with P + 2 blocks of margin on each side: the window's own circular wrap
+    reaches at most one block further per pass, and the centre block is exact.  Input: the
+    launched field (the path's arithmetic does not depend on it having crossed the link)."""
+    n = 4194304
+    x, _ = siggen.transmitted_field(4, 1, 2, n, 0.0)
+    x = x.astype(np.complex64).astype(np.complex128)
+    steps = R.schedule(40, 80.0, 20, B2, siggen.GAMMA_W_KM, siggen.ALPHA_DB_KM)
+    for name, prec, tol in [("fp32_fp64phase", dbp.FP32_FP64PHASE, 2e-4), ("bf16x3", dbp.BF16X3, split_bound(800))]:
+        p, y = run(dbp, x, 40, 20, prec, block=1024, overlap=256)
+        v = p.block - p.overlap
+        n_blk = -(-n // v)
+        m = p.n_passes + 2
+        for b in [m, n_blk // 2, n_blk - m - 2]:
+            idx = ((b - m) * v + np.arange((2 * m + 1) * v)) % n
+            w = R.run_blocked(x[:, idx], steps, FS, p.block, p.overlap, p.steps_per_pass)
+            got = y[:, b * v:(b + 1) * v]
+            want = w[:, m * v:(m + 1) * v]
+            err = rel_l2(got, want)
+            print(f"{name} k={p.steps_per_pass} passes={p.n_passes} block {b}: rel L2 {err:.3e}")
+            assert err <= tol
