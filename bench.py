@@ -260,13 +260,15 @@ def fft_gradient(torch, plan, rx, reps=10):
 
 def receiver_workload(dbp, torch, rx_field, taps, chunk_blocks=64, pushes=40):
     """Receiver mode on the headline link: the 2x262144 field pushed as a stream in chunks of
-    chunk_blocks x 768 samples, ESSFM (1 step/span, 9 taps) and SSFM (20 steps/span).  Time
-    per push (HIP events, after a warm-up), throughput, and the latency the block pipeline
-    adds (samples and ns at 56 GSa/s)."""
+    chunk_blocks x 768 samples (chunks taken cyclically from the field), ESSFM (1 step/span,
+    9 taps) and SSFM (20 steps/span).  Time per push (HIP events, after a warm-up),
+    throughput, and the latency the block pipeline adds (samples and ns at 56 GSa/s); larger
+    chunks fill the GPU better, smaller ones return each sample sooner."""
     b2 = siggen.beta2_ps2_km()
     chunk = chunk_blocks * (BLOCK - OVERLAP)
     x = rx_field.reshape(2, N)
     res = {"chunk": chunk}
+    assert chunk < N
     for name, kw in (("essfm", dict(steps_per_span=1, taps=taps)), ("ssfm_20", dict(steps_per_span=20))):
         r = dbp.receiver(chunk, SPANS, kw.pop("steps_per_span"), block=BLOCK, overlap=OVERLAP, beta2_ps2_km=b2, **kw)
         chunks = [x[:, (i * chunk) % (N - chunk):(i * chunk) % (N - chunk) + chunk].contiguous() for i in range(8)]
@@ -629,7 +631,8 @@ def main():
         log("coefficient fit " + json.dumps(extras["coefficient_fit"]))
         extras["fft_gradient"] = fft_gradient(torch, essfm, rx)
         log("FFT-step gradient " + json.dumps(extras["fft_gradient"]))
-        extras["receiver"] = receiver_workload(dbp, torch, rx, taps)
+        extras["receiver"] = {f"chunk_{cb}_blocks": receiver_workload(dbp, torch, rx, taps, chunk_blocks=cb)
+                              for cb in (64, 336)}
         log("receiver mode " + json.dumps(extras["receiver"]))
         extras["paper_arrangement"] = paper_arrangement(dbp, torch, rx, sym, target, sweep)
         log("paper arrangement " + json.dumps(extras["paper_arrangement"]))
