@@ -41,6 +41,14 @@
  *            the ABI.  Validation errors are returned before any device work.
  *   Threads  a plan is immutable after creation; concurrent calls on one plan
  *            are safe when each call has its own workspace.
+ *   Tuning   the planner reads four environment variables when a plan is made
+ *            (for measurements and tests; results differ between variants by
+ *            FP32 rounding only, and the streaming kernel reproduces the
+ *            per-block kernel bit for bit):
+ *            DBP_FORCE_E=4|8|16 values per thread of the pass kernel;
+ *            DBP_FORCE_SPLIT=0|1 polarization-split blocks off / on;
+ *            DBP_STREAM=0|1 the streaming (resident-grid) pass kernel off / on
+ *            where one is built, DBP_STREAM_GRID=n its grid (a multiple of 8).
  */
 #ifndef DBP_H
 #define DBP_H
