@@ -64,7 +64,8 @@ def gpu_field(dbp, torch, p_dbm=P_DBM):
     return torch.from_numpy(r.astype(np.complex64)).reshape(1, 2, N).cuda(), sym
 
 
-def fit_taps(dbp, torch, rx, target, n_fit=100000, iters=8, nc=NC, plan_kw=None, method="auto"):
+def fit_taps(dbp, torch, rx, target, n_fit=100000, iters=8, nc=NC, plan_kw=None, method="auto", per_step=False,
+             c0=None):
     """ESSFM coefficient fit of Sec. IV: least squares against the multi-step SSFM output
     on the first n_fit samples; Nc+1 symmetric coefficients shared by every step, every
     evaluation on the GPU.  method "adjoint": L-BFGS on the objective and its gradient from
@@ -72,7 +73,8 @@ def fit_taps(dbp, torch, rx, target, n_fit=100000, iters=8, nc=NC, plan_kw=None,
     Gauss-Newton with a forward-difference Jacobian (Nc + 2 forward runs per iteration);
     "auto": the adjoint where the plan's block size has a reverse kernel.
     plan_kw: the ESSFM plan's link and geometry (default 1 step per span, Nb=1024 O=256).
-    Returns (taps, info)."""
+    per_step: one coefficient set per step (adjoint only), started from c0 (e.g. the shared
+    fit).  Returns (taps, info): taps [2 Nc + 1], or [N_s][2 Nc + 1] with per_step."""
     from paper_1507_00921_amd import fit as G
     b2 = siggen.beta2_ps2_km()
     kw = dict(plan_kw or dict(n_spans=SPANS, steps_per_span=1, block=BLOCK, overlap=OVERLAP))
@@ -84,9 +86,14 @@ def fit_taps(dbp, torch, rx, target, n_fit=100000, iters=8, nc=NC, plan_kw=None,
     if method == "auto":
         method = "adjoint" if plan.workspace_size(grad=True) > 0 else "gauss_newton"
     t0 = time.perf_counter()
+    if per_step and method != "adjoint":
+        raise ValueError("per-step coefficients are fitted through the adjoint only")
     if method == "adjoint":
-        c, info = G.fit_coefficients(plan, rx, nc, target=target, sl=sl)
+        c, info = G.fit_coefficients(plan, rx, nc, target=target, sl=sl, c0=c0, per_step=per_step,
+                                     maxiter=200 if per_step else 60)
         info = {"method": "adjoint L-BFGS", **{k: v for k, v in info.items() if k != "message"}}
+        if per_step:
+            return np.stack([G.symmetric_full(ci) for ci in c]), info
         return G.symmetric_full(c), info
 
     ns = plan.n_steps
@@ -512,6 +519,10 @@ def evm_sweep_power(dbp, torch, powers):
         target = ssfm.backprop(rx)
         taps, _ = fit_taps(dbp, torch, rx, target)
         essfm = dbp.plan(N, SPANS, 1, taps=taps, block=BLOCK, overlap=OVERLAP, beta2_ps2_km=b2)
+        # one coefficient set per step, started from the shared fit
+        taps_ps, info_ps = fit_taps(dbp, torch, rx, target, per_step=True, c0=taps[NC:].astype(np.float64))
+        essfm_ps = dbp.plan(N, SPANS, 1, taps=taps_ps, taps_per_step=True, block=BLOCK, overlap=OVERLAP,
+                            beta2_ps2_km=b2)
         ssfm1 = dbp.plan(N, SPANS, 1, block=BLOCK, overlap=OVERLAP, beta2_ps2_km=b2)
         cd = dbp.plan(N, 1, 1, span_km=80.0 * SPANS, gamma_w_km=0.0, block=8192, overlap=2048,
                       beta2_ps2_km=b2)
@@ -521,12 +532,14 @@ def evm_sweep_power(dbp, torch, powers):
         essfm_link = dbp.plan(N, SPANS, 1, spans_per_step=SPANS, taps=taps_link, beta2_ps2_km=b2)
         ssfm_2span = dbp.plan(N, SPANS, 1, spans_per_step=2, beta2_ps2_km=b2)
         out[pw] = {"essfm_1_per_span": evm_db(essfm.backprop(rx), sym),
+                   "essfm_1_per_span_per_step_taps": evm_db(essfm_ps.backprop(rx), sym),
                    "ssfm_20_per_span": evm_db(target, sym),
                    "ssfm_1_per_span": evm_db(ssfm1.backprop(rx), sym),
                    "cd_only": evm_db(cd.backprop(rx), sym),
                    "essfm_1_step_link_nc32": evm_db(essfm_link.backprop(rx), sym),
                    "ssfm_1_per_2_spans": evm_db(ssfm_2span.backprop(rx), sym)}
-        log(f"{pw:+.0f} dBm EVM " + json.dumps({k: round(v, 3) for k, v in out[pw].items()}))
+        log(f"{pw:+.0f} dBm EVM " + json.dumps({k: round(v, 3) for k, v in out[pw].items()})
+            + f" per-step fit {info_ps['evaluations']} evaluations {info_ps['seconds']:.2f} s")
     return out
 
 

@@ -26,14 +26,17 @@ def symmetric_full(c) -> np.ndarray:
     return np.concatenate([c[:0:-1], c]).astype(np.float32)
 
 
-def fold_symmetric(g_full: np.ndarray) -> np.ndarray:
-    """dF/dw summed over steps [N_s][2 Nc + 1] -> dF/dc (adjoint of symmetric_full)."""
-    g = np.asarray(g_full, dtype=np.float64).sum(axis=0)
-    nc = (g.shape[0] - 1) // 2
-    out = np.empty(nc + 1)
-    out[0] = g[nc]
-    out[1:] = g[nc + 1:] + g[nc - 1::-1]
-    return out
+def fold_symmetric(g_full: np.ndarray, per_step: bool = False) -> np.ndarray:
+    """dF/dw [N_s][2 Nc + 1] -> dF/dc (adjoint of symmetric_full): summed over the steps
+    (shared coefficients) or kept per step ([N_s][Nc + 1], flattened)."""
+    g = np.asarray(g_full, dtype=np.float64)
+    if not per_step:
+        g = g.sum(axis=0, keepdims=True)
+    nc = (g.shape[1] - 1) // 2
+    out = np.empty((g.shape[0], nc + 1))
+    out[:, 0] = g[:, nc]
+    out[:, 1:] = g[:, nc + 1:] + g[:, nc - 1::-1]
+    return out.ravel() if per_step else out[0]
 
 
 def field_residual_loss(target, sl: slice):
@@ -50,12 +53,15 @@ def field_residual_loss(target, sl: slice):
 
 
 def fit_coefficients(plan, x, n_c: int, target=None, sl: Optional[slice] = None,
-                     loss: Optional[Callable] = None, c0=None, maxiter: int = 60):
-    """Fit the shared symmetric ESSFM coefficients of an ESSFM plan (2 n_c + 1 taps).
+                     loss: Optional[Callable] = None, c0=None, maxiter: int = 60, per_step: bool = False):
+    """Fit the symmetric ESSFM coefficients of an ESSFM plan (2 n_c + 1 taps), shared by
+    every step (Sec. IV) or, with per_step, one set per step (N_s (n_c + 1) unknowns, the
+    same objective and the same single reverse pass per evaluation).
 
     x: complex64 CUDA tensor [batch][n_pol][L]; either (target, sl) for the Sec. IV field
     residual or `loss(y) -> (value, dL/dy)`.  Starts from SSFM (c = [1, 0, ..]) unless c0
-    is given.  Returns (c, info) with the objective before and after, the number of
+    is given ([n_c + 1], or [N_s][n_c + 1] with per_step).  Returns (c, info): c is
+    [n_c + 1] or [N_s][n_c + 1]; info holds the objective before and after, the number of
     forward + reverse evaluations and the wall time.
     """
     import torch
@@ -69,28 +75,37 @@ def fit_coefficients(plan, x, n_c: int, target=None, sl: Optional[slice] = None,
     if c0 is None:
         c0 = np.zeros(n_c + 1)
         c0[0] = 1.0
+    c0 = np.asarray(c0, dtype=np.float64)
+    if per_step and c0.ndim == 1:
+        c0 = np.tile(c0, (ns, 1))
+    shape = c0.shape
+    c0 = c0.ravel()
     ws = plan.workspace(grad=True)
     n_eval = [0]
 
+    def taps_of(c):
+        if per_step:
+            return np.stack([symmetric_full(ci) for ci in c.reshape(shape)])
+        return np.tile(symmetric_full(c), (ns, 1))
+
     def value_and_grad(c):
-        w = torch.from_numpy(np.tile(symmetric_full(c), (ns, 1))).cuda()
+        w = torch.from_numpy(np.ascontiguousarray(taps_of(c))).cuda()
         y = plan.backprop(x, taps=w)
         f, g = loss(y)
         _, gt, _ = plan.backprop_grad(x, g.contiguous(), taps=w, want_input=False, workspace=ws)
         n_eval[0] += 1
-        return f, fold_symmetric(gt.cpu().numpy())
+        return f, fold_symmetric(gt.cpu().numpy(), per_step)
 
     t0 = time.perf_counter()
-    f0, _ = value_and_grad(np.asarray(c0, dtype=np.float64))
+    f0, _ = value_and_grad(c0)
     scale = 1.0 / f0 if f0 > 0 else 1.0
 
     def fun(c):
         f, g = value_and_grad(c)
         return f * scale, g * scale
 
-    res = minimize(fun, np.asarray(c0, dtype=np.float64), jac=True, method="L-BFGS-B",
-                   options=dict(maxiter=maxiter, ftol=1e-12, gtol=1e-9))
+    res = minimize(fun, c0, jac=True, method="L-BFGS-B", options=dict(maxiter=maxiter, ftol=1e-12, gtol=1e-9))
     torch.cuda.synchronize()
     info = {"objective_start": f0, "objective": float(res.fun) / scale, "evaluations": n_eval[0],
             "iterations": int(res.nit), "seconds": time.perf_counter() - t0, "message": str(res.message)}
-    return res.x, info
+    return res.x.reshape(shape), info

@@ -71,3 +71,22 @@ def test_gpu_fit_matches_oracle_fit_to_multistep_ssfm(dbp):
     print("oracle", c_ref, obj_ref, "gpu", c, obj, info)
     assert np.max(np.abs(c - c_ref)) < 1e-4
     assert abs(obj - obj_ref) <= 1e-4 * obj_ref
+
+
+def test_gpu_fit_per_step_recovers_known_coefficients(dbp):
+    # one coefficient set per step: the target is the oracle's blocked ESSFM with four
+    # different symmetric filters, and the per-step fit recovers each of them
+    from paper_1507_00921_amd import fit as G
+    rx = _field()
+    base = R.schedule(4, 80.0, 1, B2, siggen.GAMMA_W_KM, siggen.ALPHA_DB_KM)
+    c_true = np.array([[0.70, 0.12, 0.03], [0.58, 0.18, 0.03], [0.64, 0.14, 0.04], [0.55, 0.20, 0.025]])
+    steps = [R.Step(b=st.b, phi=st.phi, w=F.symmetric_full(c_true[s])) for s, st in enumerate(base)]
+    target = R.run_blocked(rx, steps, FS, 1024, 256, 2)
+    p = dbp.plan(rx.shape[-1], 4, 1, taps=G.symmetric_full([1.0, 0.0, 0.0]), block=1024, overlap=256,
+                 steps_per_pass=2, beta2_ps2_km=B2)
+    c, info = G.fit_coefficients(p, _gpu(rx), 2, target=_gpu(target), sl=slice(1024, 3072), per_step=True,
+                                 maxiter=200)
+    print("recovered", c, info)
+    assert c.shape == (4, 3)
+    assert np.max(np.abs(c - c_true)) < 1e-3
+    assert info["objective"] < 1e-6 * info["objective_start"]
