@@ -119,7 +119,7 @@ __global__ __launch_bounds__(NB / E) void dbp_adjoint_kernel(AdjArgs a) {
         job.s0 = a.s0 + j;
         BlockSmem<NB, E, NPOL, NT>& fs = *reinterpret_cast<BlockSmem<NB, E, NPOL, NT>*>(&sm);
         static_assert(sizeof(BlockSmem<NB, E, NPOL, NT>) <= sizeof(Sm), "forward step workspace");
-        run_steps<NB, E, NPOL, PHASE64, NT>(v, job, twr, fs, nullptr);
+        run_steps<NB, E, NPOL, PHASE64, NT, false, false>(v, job, twr, fs, nullptr);
         __syncthreads();
 #pragma unroll
         for (int p = 0; p < NPOL; ++p)

@@ -73,7 +73,7 @@ __global__ __launch_bounds__(NB / E) void dbp_batch_kernel(BatchArgs a) {
     __shared__ int item_s, ok_s;
     const int t = threadIdx.x;
     TwReg<NB, E> twr;
-    load_twiddles<NB, E>(twr, a.tw, t);
+    load_step_twiddles<NB, E>(twr, a.tw, t);
     for (;;) {
         int v = 0;
         if (t == 0) v = atomicAdd(a.counter, 1);

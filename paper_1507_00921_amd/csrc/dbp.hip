@@ -75,7 +75,7 @@ int default_e(int nb, long long n_wg) {
 }
 
 // Polarization-split blocks: measured on the 2x262144 workload at Nb = 1024
-// (342 blocks), SSFM runs 7% faster split and ESSFM equally fast, so only SSFM
+// (342 blocks), SSFM runs 2% faster split and ESSFM 4% slower, so only SSFM
 // launches with fewer blocks than two per CU are split.  DBP_FORCE_SPLIT=0/1
 // overrides where a split variant exists.
 static bool default_split(int nb, int e, int npol, int nt, long long n_wg) {

@@ -7,6 +7,7 @@
 
 #include "fft.hpp"
 #include "phase.hpp"
+#include "wave_fft.hpp"
 
 namespace dbp {
 
@@ -162,8 +163,10 @@ __device__ __forceinline__ void load_block(float2 (&v)[NPOL][E], const float2* _
 // known at compile time; 0: SSFM, J = I; -1: taken from the job at run time).
 // HLDS: every step of the pass uses one dispersion table, copied to hl in
 // LDS with each thread holding the entries of its own bins (so no barrier
-// orders the copy).  Every thread of the workgroup must call this.
-template <int NB, int E, int NPOL, bool PHASE64, int NT, bool HLDS = false>
+// orders the copy).  WF: the in-wave 1024-point transform (twiddles from
+// load_step_twiddles) instead of the Stockham one.  Every thread of the
+// workgroup must call this.
+template <int NB, int E, int NPOL, bool PHASE64, int NT, bool HLDS = false, bool WF = wave_fft_default<NB, E>>
 __device__ __forceinline__ void run_steps(float2 (&v)[NPOL][E], const BlockJob& a, const TwReg<NB, E>& twr,
                                           BlockSmem<NB, E, NPOL, NT>& sm, const float2* __restrict__ hl) {
     using S = FftShape<NB, E>;
@@ -189,7 +192,7 @@ __device__ __forceinline__ void run_steps(float2 (&v)[NPOL][E], const BlockJob& 
         } else {
             const float2* __restrict__ hs = a.H + st.h_off;
 #pragma unroll
-            for (int q = 0; q < E; ++q) h[q] = hs[t + T * q];
+            for (int q = 0; q < E; ++q) h[q] = hs[disp_index<NB, E, WF>(t, q)];
         }
         const auto w = as_const(a.taps) + (long long)s * ntaps;
         float wr[NT > 0 ? NT : 1];
@@ -197,15 +200,26 @@ __device__ __forceinline__ void run_steps(float2 (&v)[NPOL][E], const BlockJob& 
 #pragma unroll
             for (int m = 0; m < NT; ++m) wr[m] = w[m];
         }
-        // (i) forward FFT of both polarizations
-        block_fft<NB, E, NPOL, false>(v, lds, twr, t);
-        // (ii) dispersion, Eq. (1), with the inverse FFT's 1/Nb folded in
+        if constexpr (WF) {
+            // (i)-(iii) with one exchange per transform; the two exchanges use the two
+            // buffers, so a buffer is rewritten only after the other one's barrier
+            wave_fft_1024<NPOL, false>(v, lds, twr, t);
 #pragma unroll
-        for (int q = 0; q < E; ++q)
+            for (int q = 0; q < E; ++q)
 #pragma unroll
-            for (int p = 0; p < NPOL; ++p) v[p][q] = cmul(v[p][q], h[q]);
-        // (iii) inverse FFT
-        block_fft<NB, E, NPOL, true>(v, lds, twr, t);
+                for (int p = 0; p < NPOL; ++p) v[p][q] = cmul(v[p][q], h[q]);
+            wave_fft_1024<NPOL, true>(v, lds + NPOL * NB, twr, t);
+        } else {
+            // (i) forward FFT of both polarizations
+            block_fft<NB, E, NPOL, false>(v, lds, twr, t);
+            // (ii) dispersion, Eq. (1), with the inverse FFT's 1/Nb folded in
+#pragma unroll
+            for (int q = 0; q < E; ++q)
+#pragma unroll
+                for (int p = 0; p < NPOL; ++p) v[p][q] = cmul(v[p][q], h[q]);
+            // (iii) inverse FFT
+            block_fft<NB, E, NPOL, true>(v, lds, twr, t);
+        }
         // (iv) nonlinear phase driven by the total intensity, Eqs. (2)-(3)
         float J[E];
 #pragma unroll
@@ -378,7 +392,7 @@ __device__ __forceinline__ void process_block_split(const BlockJob& a, const TwR
         const float2* __restrict__ hs = a.H + st.h_off;
         float2 h[E];
 #pragma unroll
-        for (int q = 0; q < E; ++q) h[q] = hs[t + T * q];
+        for (int q = 0; q < E; ++q) h[q] = hs[disp_index<NB, E>(t, q)];
         const auto w = as_const(a.taps) + (long long)s * ntaps;
         float wr[NT > 0 ? NT : 1];
         if constexpr (NT > 0) {
@@ -386,10 +400,17 @@ __device__ __forceinline__ void process_block_split(const BlockJob& a, const TwR
             for (int m = 0; m < NT; ++m) wr[m] = w[m];
         }
         // (i)-(iii): this group's polarization through Eq. (1)
-        block_fft<NB, E, 1, false>(v, lds, twr, t);
+        if constexpr (wave_fft_default<NB, E>) {
+            wave_fft_1024<1, false>(v, lds, twr, t);
 #pragma unroll
-        for (int q = 0; q < E; ++q) v[0][q] = cmul(v[0][q], h[q]);
-        block_fft<NB, E, 1, true>(v, lds, twr, t);
+            for (int q = 0; q < E; ++q) v[0][q] = cmul(v[0][q], h[q]);
+            wave_fft_1024<1, true>(v, lds + NB, twr, t);
+        } else {
+            block_fft<NB, E, 1, false>(v, lds, twr, t);
+#pragma unroll
+            for (int q = 0; q < E; ++q) v[0][q] = cmul(v[0][q], h[q]);
+            block_fft<NB, E, 1, true>(v, lds, twr, t);
+        }
         // (iv): |y_g|^2 of each group; total intensity, tap filter and phase factor
         // for this group's half of the positions
 #pragma unroll
@@ -445,7 +466,7 @@ __global__ __launch_bounds__(2 * NB / E) void dbp_pass_kernel_split(PassArgs a) 
     const int wg = xcd_remap(blockIdx.x, a.n_wg);
     const int sig = wg / a.n_blk;
     TwReg<NB, E> twr;
-    load_twiddles<NB, E>(twr, a.tw, threadIdx.x >= NB / E ? threadIdx.x - NB / E : threadIdx.x);
+    load_step_twiddles<NB, E>(twr, a.tw, threadIdx.x >= NB / E ? threadIdx.x - NB / E : threadIdx.x);
     BlockJob j;
     j.src = a.in + (long long)sig * 2 * a.L;
     j.dst = a.out + (long long)sig * 2 * a.L;
@@ -468,7 +489,7 @@ __global__ __launch_bounds__(NB / E) void dbp_pass_kernel(PassArgs a) {
     const int wg = xcd_remap(blockIdx.x, a.n_wg);
     const int sig = wg / a.n_blk;
     TwReg<NB, E> twr;
-    load_twiddles<NB, E>(twr, a.tw, threadIdx.x);
+    load_step_twiddles<NB, E>(twr, a.tw, threadIdx.x);
     BlockJob j;
     j.src = a.in + (long long)sig * NPOL * a.L;
     j.dst = a.out + (long long)sig * NPOL * a.L;
@@ -510,10 +531,10 @@ __global__ __launch_bounds__(NB / E) void dbp_stream_kernel(PassArgs a) {
     int it = (int)(((long long)a.n_wg * x) >> 3) + (int)(blockIdx.x >> 3);
     if (it >= hi) return;
     TwReg<NB, E> twr;
-    load_twiddles<NB, E>(twr, a.tw, t);
+    load_step_twiddles<NB, E>(twr, a.tw, t);
     const int h0 = load_step(a.steps + a.s0).h_off;
 #pragma unroll
-    for (int q = 0; q < E; ++q) sm.h[t + T * q] = a.H[h0 + t + T * q];
+    for (int q = 0; q < E; ++q) sm.h[t + T * q] = a.H[h0 + disp_index<NB, E>(t, q)];
 
     const long long sig_elems = (long long)NPOL * a.L;
     int sig = it / a.n_blk, blk = it - sig * a.n_blk;
@@ -574,7 +595,7 @@ __global__ __launch_bounds__(NB / E) void dbp_ring_pass_kernel(PassArgs a, RingA
     __shared__ BlockSmem<NB, E, NPOL, NT> sm;
     const int t = threadIdx.x;
     TwReg<NB, E> twr;
-    load_twiddles<NB, E>(twr, a.tw, t);
+    load_step_twiddles<NB, E>(twr, a.tw, t);
     const long long b = r.blk0 + blockIdx.x;
     const long long start = b * a.V - a.halo;
     float2 v[NPOL][E];
