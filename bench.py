@@ -468,7 +468,7 @@ def cpu_baseline(rx_np, taps, k, budget_s=12.0):
                       f"(single-threaded pocketfft), {el:.1f} s"}
 
 
-KERNEL_SOURCES = ["fft.hpp", "phase.hpp", "step_kernel.hpp", "registry.hpp", "kern_1024.hip"]
+KERNEL_SOURCES = ["fft.hpp", "wave_fft.hpp", "phase.hpp", "step_kernel.hpp", "registry.hpp", "kern_1024.hip"]
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "pass_kernel_1024_essfm_2x262144_traffic.md")
 
 
