@@ -51,16 +51,18 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def gpu_field(dbp, torch, p_dbm=P_DBM):
+def gpu_field(dbp, torch, p_dbm=P_DBM, ase_ref_dbm=0.0):
     """Launch at p_dbm, forward-propagate (library, physical direction, 100 steps per span)
-    and add ASE whose power is fixed at the 0 dBm, 20 dB OSNR value (ASE-limited link)."""
+    and add ASE whose power is that of 20 dB OSNR at ase_ref_dbm: fixed at the 0 dBm value by
+    default (ASE-limited link), or at p_dbm itself (constant OSNR) with ase_ref_dbm=None."""
     x, sym = siggen.transmitted_field(1, 0, 2, N, p_dbm)
     fwd = dbp.plan(N, SPANS, 100, forward=True, beta2_ps2_km=siggen.beta2_ps2_km())
     xt = torch.from_numpy(x.astype(np.complex64)).reshape(1, 2, N).cuda()
     rx = fwd.backprop(xt)
     torch.cuda.synchronize()
     r = rx.cpu().numpy().reshape(2, N).astype(np.complex128)
-    r = siggen.add_awgn(siggen.rng(1, 0, 2), r, siggen.awgn_sigma2(siggen.dbm_to_w(0.0), OSNR_DB))
+    ref = p_dbm if ase_ref_dbm is None else ase_ref_dbm
+    r = siggen.add_awgn(siggen.rng(1, 0, 2), r, siggen.awgn_sigma2(siggen.dbm_to_w(ref), OSNR_DB))
     return torch.from_numpy(r.astype(np.complex64)).reshape(1, 2, N).cuda(), sym
 
 
@@ -540,6 +542,17 @@ def evm_sweep_power(dbp, torch, powers):
                    "ssfm_1_per_2_spans": evm_db(ssfm_2span.backprop(rx), sym)}
         log(f"{pw:+.0f} dBm EVM " + json.dumps({k: round(v, 3) for k, v in out[pw].items()})
             + f" per-step fit {info_ps['evaluations']} evaluations {info_ps['seconds']:.2f} s")
+        # the alternative noise model: OSNR held at 20 dB at every launch power
+        rxc, symc = gpu_field(dbp, torch, pw, ase_ref_dbm=None)
+        targetc = ssfm.backprop(rxc)
+        tapsc, _ = fit_taps(dbp, torch, rxc, targetc)
+        essfmc = dbp.plan(N, SPANS, 1, taps=tapsc, block=BLOCK, overlap=OVERLAP, beta2_ps2_km=b2)
+        out[pw]["constant_osnr"] = {"essfm_1_per_span": evm_db(essfmc.backprop(rxc), symc),
+                                    "ssfm_20_per_span": evm_db(targetc, symc),
+                                    "ssfm_1_per_span": evm_db(ssfm1.backprop(rxc), symc),
+                                    "cd_only": evm_db(cd.backprop(rxc), symc)}
+        log(f"{pw:+.0f} dBm EVM at constant OSNR "
+            + json.dumps({k: round(v, 3) for k, v in out[pw]["constant_osnr"].items()}))
     return out
 
 
@@ -650,8 +663,10 @@ def main():
         extras["paper_arrangement"] = paper_arrangement(dbp, torch, rx, sym, target, sweep)
         log("paper arrangement " + json.dumps(extras["paper_arrangement"]))
         extras["paper_context"] = paper_context(extras["paper_arrangement"], ms_e, ms_s)
-        extras["evm_vs_launch_power_db"] = {f"{pw:+.0f}": {k: round(v, 3) for k, v in e.items()}
-                                            for pw, e in sweep.items()}
+        extras["evm_vs_launch_power_db"] = {
+            f"{pw:+.0f}": {k: ({kk: round(vv, 3) for kk, vv in v.items()} if isinstance(v, dict) else round(v, 3))
+                           for k, v in e.items()}
+            for pw, e in sweep.items()}
         hbm = hbm_working_set(dbp, torch, rx, taps)
         log("large working set " + json.dumps(hbm))
         extras["gradient"] = grad_workload(dbp, torch)
