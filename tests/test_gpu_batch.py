@@ -140,3 +140,23 @@ def test_grouped_blocks_long_signals(dbp):
         err = rel_l2(y[i].astype(np.complex128), ref)
         print(f"grouped signal {i}: L={w['n']} blocks={-(-w['n'] // 384)} steps={ns} rel L2 {err:.3e}")
         assert err <= 1e-5
+
+
+def test_batch_kernel_reproduces_the_pass_kernel_on_1024_point_blocks(dbp):
+    # the batch kernel runs the same block routine (the in-wave transform at Nb = 1024):
+    # per signal, bit for bit the output of a single plan with that geometry, and the oracle
+    work = [dict(n=n, n_spans=5, steps_per_span=1, taps=siggen.symmetric_taps(siggen.rng(2, 950 + i, 0), 4))
+            for i, n in enumerate((20000, 9000, 31112))]
+    ds = descs_for(dbp, work, block=1024, overlap=256, steps_per_pass=3)
+    bp = dbp.plan_batch(ds)
+    xs = fields_for(work, 11)
+    y = bp.unpack(bp.backprop(bp.pack(xs)))
+    torch.cuda.synchronize()
+    assert bp.status() == 0
+    for i, w in enumerate(work):
+        assert bp.geometry(i) == (1024, 256, 3)
+        p = dbp.plan(w["n"], 5, 1, taps=w["taps"], block=1024, overlap=256, steps_per_pass=3, beta2_ps2_km=B2)
+        yp = p.backprop(torch.from_numpy(xs[i]).reshape(1, 2, -1).cuda()).cpu().numpy().reshape(2, -1)
+        assert np.array_equal(y[i].view(np.float32), yp.view(np.float32))
+        ref, ns = oracle_one(xs[i], w, (1024, 256, 3))
+        assert rel_l2(y[i].astype(np.complex128), ref) <= 1e-5

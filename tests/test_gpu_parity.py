@@ -73,7 +73,8 @@ def test_cfg0_whole_signal_single_polarization(dbp):
 
 @pytest.mark.parametrize("block,overlap,n_pol,essfm,n_spans,sps,k,n", [
     (1024, 256, 2, True, 40, 1, 0, 65536 + 1002),     # cfg1 geometry, ragged tail (256 threads)
-    (1024, 256, 2, True, 3, 1, 0, 400000),            # > 512 blocks: one wave per block
+    (1024, 256, 2, True, 3, 1, 0, 400000),            # 521 blocks: more than two per CU
+    (1024, 256, 1, False, 6, 2, 3, 20000),            # one polarization through the in-wave transform
     (1024, 256, 2, False, 8, 20, 0, 40000),           # SSFM 20 steps/span, k-fused
     (256, 64, 2, True, 6, 1, 1, 5000),
     (512, 128, 1, False, 4, 3, 3, 7777 * 2),
