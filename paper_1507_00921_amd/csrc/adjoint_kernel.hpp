@@ -84,6 +84,18 @@ __device__ __forceinline__ float wave_sum(float v) {
     return v;
 }
 
+// Forward or inverse block transform: the in-wave one (WF; forward exchange in the first
+// buffer of lds, inverse in the second) or the Stockham one.
+template <bool WF, bool INV, int NB, int E, int NPOL>
+__device__ __forceinline__ void transform(float2 (&v)[NPOL][E], float2* __restrict__ lds, const TwReg<NB, E>& twr,
+                                          int t) {
+    if constexpr (WF) {
+        wave_fft_1024<NPOL, INV>(v, INV ? lds + NPOL * NB : lds, twr, t);
+    } else {
+        block_fft<NB, E, NPOL, INV>(v, lds, twr, t);
+    }
+}
+
 template <int NB, int E, int NPOL, bool PHASE64, int NT>
 __global__ __launch_bounds__(NB / E) void dbp_adjoint_kernel(AdjArgs a) {
     using S = FftShape<NB, E>;
@@ -95,8 +107,11 @@ __global__ __launch_bounds__(NB / E) void dbp_adjoint_kernel(AdjArgs a) {
     const int sig = wg / a.n_blk, blk = wg - sig * a.n_blk;
     const long long L = a.L;
     const long long start = (long long)blk * a.V - a.halo;
+    // transforms as in the pass kernels (the in-wave one for 1024-point blocks), so that the
+    // recomputed states are those of the forward pass
+    constexpr bool WF = wave_fft_default<NB, E>;
     TwReg<NB, E> twr;
-    load_twiddles<NB, E>(twr, a.tw, t);
+    load_step_twiddles<NB, E>(twr, a.tw, t);
     const float2* __restrict__ xsig = a.x + (long long)sig * NPOL * L;
     float2* __restrict__ xs = a.xs + (long long)wg * (a.kmax - 1) * NPOL * NB;
     const int ntaps = NT >= 0 ? NT : a.ntaps;
@@ -119,7 +134,7 @@ __global__ __launch_bounds__(NB / E) void dbp_adjoint_kernel(AdjArgs a) {
         job.s0 = a.s0 + j;
         BlockSmem<NB, E, NPOL, NT>& fs = *reinterpret_cast<BlockSmem<NB, E, NPOL, NT>*>(&sm);
         static_assert(sizeof(BlockSmem<NB, E, NPOL, NT>) <= sizeof(Sm), "forward step workspace");
-        run_steps<NB, E, NPOL, PHASE64, NT, false, false>(v, job, twr, fs, nullptr);
+        run_steps<NB, E, NPOL, PHASE64, NT>(v, job, twr, fs, nullptr);
         __syncthreads();
 #pragma unroll
         for (int p = 0; p < NPOL; ++p)
@@ -160,14 +175,14 @@ __global__ __launch_bounds__(NB / E) void dbp_adjoint_kernel(AdjArgs a) {
         const StepDev st = load_step(a.steps + s);
         float2 h[E];
 #pragma unroll
-        for (int q = 0; q < E; ++q) h[q] = a.H[st.h_off + t + T * q];
+        for (int q = 0; q < E; ++q) h[q] = a.H[st.h_off + disp_index<NB, E>(t, q)];
         // recompute u, I, J and the phase factor f = exp(-j phi J) of step s
-        block_fft<NB, E, NPOL, false>(v, sm.lds, twr, t);
+        transform<WF, false, NB, E, NPOL>(v, sm.lds, twr, t);
 #pragma unroll
         for (int q = 0; q < E; ++q)
 #pragma unroll
             for (int p = 0; p < NPOL; ++p) v[p][q] = cmul(v[p][q], h[q]);
-        block_fft<NB, E, NPOL, true>(v, sm.lds, twr, t);
+        transform<WF, true, NB, E, NPOL>(v, sm.lds, twr, t);
         float J[E];
 #pragma unroll
         for (int q = 0; q < E; ++q) {
@@ -243,12 +258,12 @@ __global__ __launch_bounds__(NB / E) void dbp_adjoint_kernel(AdjArgs a) {
                 g[p][q].x = fmaf(2.f * ib[q], v[p][q].x, g[p][q].x);
                 g[p][q].y = fmaf(2.f * ib[q], v[p][q].y, g[p][q].y);
             }
-        block_fft<NB, E, NPOL, false>(g, sm.lds, twr, t);
+        transform<WF, false, NB, E, NPOL>(g, sm.lds, twr, t);
 #pragma unroll
         for (int q = 0; q < E; ++q)
 #pragma unroll
             for (int p = 0; p < NPOL; ++p) g[p][q] = cmulc(g[p][q], h[q]);
-        block_fft<NB, E, NPOL, true>(g, sm.lds, twr, t);
+        transform<WF, true, NB, E, NPOL>(g, sm.lds, twr, t);
         // inten, jb and red are rewritten only after the barriers of the next step's transforms
     }
 
