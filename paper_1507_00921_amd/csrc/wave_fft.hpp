@@ -159,9 +159,9 @@ __device__ __forceinline__ void load_wave_twiddles(float2 (&twr)[12], const floa
 // Forward (INV = false) or inverse 1024-point transform of NPOL polarizations;
 // buf: NPOL x 1024 float2 of LDS (polarization stride 1024) for the exchange
 // between waves; the in-wave exchange of digit 1:0 uses the quarter of buf
-// that only wave w reads (forward) or writes (inverse) in that exchange.  Stages run for every polarization before
-// the next one, so the two chains interleave.  Every thread of the four waves
-// must call it.
+// that only wave w reads (forward) or writes (inverse) in that exchange.
+// Each stage runs for every polarization before the next one, so the two
+// chains interleave.  Every thread of the four waves must call it.
 template <int NPOL, bool INV>
 __device__ __forceinline__ void wave_fft_1024(float2 (&v)[NPOL][4], float2* __restrict__ buf,
                                               const float2 (&tw)[12], int t) {
