@@ -553,6 +553,31 @@ def calibrate_copy():
     log("copied 3 x 1 GiB")
 
 
+def copy_bandwidth(torch, reps=20):
+    """Achieved bandwidth of a plain 1 GiB device-to-device copy (read + write = 2 GiB per
+    copy), median of 5 timed groups: the practical HBM ceiling beside the 8 TB/s datasheet."""
+    a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    r = []
+    for _ in range(5):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        r.append(e0.elapsed_time(e1) / reps)
+    ms = float(np.median(r))
+    gbs = 2 * (1 << 30) / (ms * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return {"bytes_per_copy": 2 * (1 << 30), "ms": round(ms, 4), "gbs": round(gbs, 1),
+            "frac_of_8tbs": round(gbs / HBM_PEAK_GBS, 4)}
+
+
 def evm_sweep_power(dbp, torch, powers):
     """Launch-power sweep: per power the field is regenerated and forward-propagated, the
     ESSFM taps are refitted and the EVM of each receiver is computed."""
@@ -711,6 +736,7 @@ def main():
                            for k, v in e.items()}
             for pw, e in sweep.items()}
         hbm = hbm_working_set(dbp, torch, rx, taps)
+        hbm["plain_copy"] = copy_bandwidth(torch)
         log("large working set " + json.dumps(hbm))
         extras["gradient"] = grad_workload(dbp, torch)
         log("gradient workload " + json.dumps(extras["gradient"]))
