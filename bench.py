@@ -204,8 +204,8 @@ def time_dbp_settled(torch, p, x, out, ws, reps=10, batches=5, warm_s=0.5):
 def hbm_working_set(dbp, torch, rx, taps, batch=64, reps=10, only=None):
     """The ESSFM pass kernel on the field replicated `batch` times (256 MiB per state,
     beyond the 256 MB Infinity Cache), one launch per pass: k = 1 (one HBM round trip per
-    step) and k = 2 on the smallest valid block, Nb=512 O=128 (and SSFM at k = 1), and k = 1 and k = 5 on
-    Nb=1024 O=256; algorithmic bytes = 2*8*Nb/(Nb-O) B read + 16 B written per sample and
+    step) and k = 2 on the smallest valid block, Nb=512 O=128 (and SSFM at k = 1, and ESSFM
+    at k = 1 with the smallest overlap one step needs), and k = 1 and k = 5 on Nb=1024 O=256; algorithmic bytes = 2*8*Nb/(Nb-O) B read + 16 B written per sample and
     pass.  Where the planner picks the streaming kernel (single-wave blocks: resident grid,
     next block prefetched) the one-workgroup-per-block kernel is timed beside it.  Each time
     is the median of five runs of `reps` launches after half a second of the same work."""
@@ -213,7 +213,10 @@ def hbm_working_set(dbp, torch, rx, taps, batch=64, reps=10, only=None):
     xb = rx.expand(batch, 2, N).contiguous()
     out = torch.empty_like(xb)
     res = {}
-    for name, k, nb, o, tp in (("k1_nb512", 1, 512, 128, taps), ("k2_nb512", 2, 512, 128, taps),
+    # the overlap one ESSFM step needs under the planner's rule, 2 ceil(spread + margin) = 76
+    o1 = 2 * int(np.ceil(np.pi * abs(b2) * 80.0 * siggen.FS_THZ ** 2 + NC + 16))
+    for name, k, nb, o, tp in (("k1_nb512", 1, 512, 128, taps), (f"k1_nb512_o{o1}", 1, 512, o1, taps),
+                               ("k2_nb512", 2, 512, 128, taps),
                                ("k1_nb512_ssfm", 1, 512, 128, None),
                                ("k1", 1, BLOCK, OVERLAP, taps), ("k5", 5, BLOCK, OVERLAP, taps)):
         if only is not None and name != only:
