@@ -14,6 +14,8 @@ Modules:
   adjoint     reverse-mode gradient of a real loss through the cascade
   complexity  the real-operation counts of Sec. III and the channel-memory rule
   fit         least-squares fit of the ESSFM coefficients (Sec. IV)
+  rxdsp       receiver DSP after backpropagation (Sec. IV): resampling to two samples
+              per symbol, butterfly equalizer, carrier-phase recovery, decisions
 
 Parity status: every function is pinned by tests under tests/ against closed
 forms, invariants, brute force or numbers printed in the paper, except the

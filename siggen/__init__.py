@@ -100,6 +100,49 @@ def shape(symbols: np.ndarray, sps: int = SPS, rolloff: float = ROLLOFF) -> np.n
     return np.fft.ifft(np.fft.fft(up, axis=-1) * rrc_response(n_sym * sps, sps, rolloff), axis=-1)
 
 
+def shape_at_rate(symbols: np.ndarray, fs_thz: float, rolloff: float = ROLLOFF,
+                  symbol_rate_thz: float = SYMBOL_RATE_THZ) -> np.ndarray:
+    """The same RRC pulse train sampled at any rate fs_thz above its bandwidth (e.g. a
+    50 GSa/s scope, about 1.8 samples per symbol): the periodic band-limited signal whose
+    spectrum on the n-point grid (n = n_sym fs / R, an integer) is the symbols' n_sym-point
+    DFT, repeated with period R, times the RRC response, scaled so that every rate samples
+    the same continuous signal; at fs = 2R it equals shape()."""
+    n_sym = symbols.shape[-1]
+    n_f = n_sym * fs_thz / symbol_rate_thz
+    n = int(round(n_f))
+    assert abs(n - n_f) < 1e-9, "n_sym * fs / R must be an integer"
+    assert (1.0 + rolloff) * symbol_rate_thz / 2.0 < fs_thz / 2.0, "rate below the signal bandwidth"
+    k = np.fft.fftfreq(n, d=1.0 / n).round().astype(np.int64)    # signed bin index
+    S = np.fft.fft(symbols, axis=-1)
+    f_norm = k / n_sym                                             # frequency in units of R
+    # the DFT of samples of one continuous signal scales with the sampling rate
+    X = S[..., k % n_sym] * np.sqrt(2.0 * raised_cosine(f_norm, rolloff)) * (fs_thz / (2.0 * symbol_rate_thz))
+    return np.fft.ifft(X, axis=-1)
+
+
+def transmitted_field_at_rate(cfg: int, idx: int, n_pol: int, n_sym: int, p_dbm: float, fs_thz: float,
+                              rolloff: float = ROLLOFF):
+    """transmitted_field() sampled at fs_thz instead of two samples per symbol."""
+    sym = qpsk_symbols(rng(cfg, idx, 0), n_pol, n_sym)
+    return set_power(shape_at_rate(sym, fs_thz, rolloff), dbm_to_w(p_dbm)), sym
+
+
+def polarization_rotation(gen: np.random.Generator) -> np.ndarray:
+    """A random constant SU(2) matrix [[a, b], [-conj(b), conj(a)]], |a|^2 + |b|^2 = 1:
+    the lossless polarization state change a fibre leaves between transmitter and receiver."""
+    v = gen.standard_normal(4)
+    v /= np.linalg.norm(v)
+    a, b = v[0] + 1j * v[1], v[2] + 1j * v[3]
+    return np.array([[a, b], [-np.conj(b), np.conj(a)]])
+
+
+def laser_phase_noise(gen: np.random.Generator, n: int, linewidth_hz: float, fs_thz: float) -> np.ndarray:
+    """Wiener phase of the transmitter and local-oscillator lasers (summed linewidth, Hz),
+    one sample per field sample: increments of variance 2 pi linewidth / fs."""
+    var = 2.0 * math.pi * linewidth_hz / (fs_thz * 1e12)
+    return np.cumsum(gen.standard_normal(n) * math.sqrt(var))
+
+
 def set_power(field: np.ndarray, p_w: float) -> np.ndarray:
     """Scale each polarization so its empirical mean |x|^2 is p_w / n_pol (total power p_w)."""
     n_pol = field.shape[-2]
