@@ -280,6 +280,73 @@ dbp_status dbp_rx_reset(dbp_rx_t rx, void* stream);
 /* Release the receiver (NULL is a no-op); no push may still be running. */
 void dbp_rx_destroy(dbp_rx_t rx);
 
+/* Receiver DSP after backpropagation (Sec. IV): the captured blocks are
+ * backpropagated at the scope's sampling rate (about 1.8 samples per symbol),
+ * resampled to two samples per symbol, passed through a butterfly equalizer
+ * that adapts to polarization effects and residual dispersion, and detected at
+ * the symbol rate with phase-noise tracking.  The paper names these stages but
+ * not their algorithms; this library implements:
+ *   resampling   y[m] = sum_k x[(i_m + k) mod n] h(t_m - i_m - k), t_m = m down / up,
+ *                i_m = floor(t_m), k = -K/2+1 .. K/2, h(tau) = sinc(tau) I0(beta
+ *                sqrt(1 - (tau / (K/2))^2)) / I0(beta) (Kaiser-windowed sinc), up >= down
+ *   equalizer    y_p[k] = sum_q sum_j W[p][q][j] x_q[(2k + j - N/2) mod n2], the taps the
+ *                data-aided least-squares (Wiener) solution on the first n_train symbols
+ *   phase        theta_k = arg(-sum_{|j|<=W} y[(k+j) mod n]^4) / 4 per polarization,
+ *                phi_k = theta_0 + sum_{0<j<=k} wrap_{pi/2}(theta_j - theta_{j-1}),
+ *                z = y exp(-j phi) (quarter turns resolved on known symbols);
+ *                QPSK decisions by the signs of Re z and Im z.
+ * All fields are complex64 [2][n] (two polarizations) on the current device. */
+typedef struct dbp_dsp_s* dbp_dsp_t;
+
+typedef struct {
+    int32_t up, down;          /* output/input rate ratio, 1 <= down <= up <= 4096 (e.g. 28/25) */
+    int32_t resample_taps;     /* K: even, 2..64 */
+    double  kaiser_beta;       /* beta >= 0 */
+    int32_t eq_taps;           /* N: odd, 1..31, taps per butterfly branch (T/2-spaced) */
+    int32_t cpr_half_window;   /* W: 0..256 */
+} dbp_dsp_desc;
+
+/* Create the receiver DSP for input blocks of n_in samples per polarization at
+ * the input rate; n_out = n_in up / down must be an integer and even (n_sym =
+ * n_out / 2 symbols).  Allocates its tables and scratch on the current device
+ * (synchronously); *out is NULL on error (DBP_ERR_INVALID_ARG for a bad desc or
+ * size). */
+dbp_status dbp_dsp_create(const dbp_dsp_desc* desc, int64_t n_in, dbp_dsp_t* out);
+
+/* Sizes: n_out samples per polarization after resampling, n_sym symbols.  Either
+ * pointer may be NULL. */
+dbp_status dbp_dsp_info(dbp_dsp_t dsp, int64_t* n_out, int64_t* n_sym);
+
+/* in [2][n_in] -> out [2][n_out] (device, not overlapping).  Asynchronous on stream. */
+dbp_status dbp_dsp_resample(dbp_dsp_t dsp, const void* in, void* out, void* stream);
+
+/* Least-squares butterfly taps from the resampled field x2 [2][n_out] and the
+ * transmitted symbols sym [2][n_sym] (device): the normal equations are summed
+ * on the GPU (per-chunk FP32 sums added in FP64 in a fixed order) and solved on
+ * the host in FP64 (LU with partial pivoting); taps [2][2][N] complex64 are
+ * written to device memory.  1 <= n_train <= n_sym.  Synchronizes stream (the
+ * solve needs the sums); DBP_ERR_UNSUPPORTED if the system is singular. */
+dbp_status dbp_dsp_train(dbp_dsp_t dsp, const void* x2, const void* sym, int64_t n_train, void* taps,
+                         void* stream);
+
+/* y [2][n_sym] = the butterfly with device taps [2][2][N] applied to x2 [2][n_out].
+ * Asynchronous on stream. */
+dbp_status dbp_dsp_equalize(dbp_dsp_t dsp, const void* x2, const void* taps, void* y, void* stream);
+
+/* Carrier-phase recovery and decisions: z [2][n_sym] from y [2][n_sym].  The
+ * fourth-power estimate is blind to quarter turns; with the transmitted symbols
+ * sym (device [2][n_sym]) and 0 < n_ref <= n_sym, the rotation by q pi/2 that best
+ * aligns the first n_ref derotated symbols with them (q the nearest integer to
+ * arg(sum z_k conj(s_k)) / (pi/2), per polarization) is applied as well (n_ref = 0:
+ * none).  With sym and bit_errors (host) the number of wrong decision bits is
+ * counted on the GPU and returned (then the call synchronizes stream); otherwise
+ * asynchronous.  sym may be NULL when n_ref = 0; z may not overlap y. */
+dbp_status dbp_dsp_cpr(dbp_dsp_t dsp, const void* y, const void* sym, int64_t n_ref, void* z, int64_t* bit_errors,
+                       void* stream);
+
+/* Release (NULL is a no-op); no call on it may still be running. */
+void dbp_dsp_destroy(dbp_dsp_t dsp);
+
 /* Short static description of a status code. */
 const char* dbp_status_string(dbp_status s);
 

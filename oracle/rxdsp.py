@@ -14,7 +14,8 @@ decisions.  The paper names the blocks, not their algorithms; these are the read
                data-aided least-squares (Wiener) solution over a training prefix of symbols
   cpr          Viterbi-Viterbi fourth-power phase estimate per polarization over 2W + 1
                symbols, theta_k = arg(-sum y^4) / 4, unwrapped by quarter turns:
-               phi_k = theta_0 + sum_{j <= k} wrap(theta_j - theta_{j-1}), then y e^{-j phi}
+               phi_k = theta_0 + sum_{j <= k} wrap(theta_j - theta_{j-1}), then y e^{-j phi},
+               the estimate's quarter-turn ambiguity resolved on the training symbols
   decisions    QPSK quadrant decisions, bit errors against the transmitted symbols
 """
 from __future__ import annotations
@@ -91,8 +92,16 @@ def cpr_phase(y: np.ndarray, half_window: int) -> np.ndarray:
     return theta[..., :1] + np.concatenate([np.zeros(theta.shape[:-1] + (1,)), np.cumsum(d, axis=-1)], axis=-1)
 
 
-def cpr(y: np.ndarray, half_window: int) -> np.ndarray:
-    return y * np.exp(-1j * cpr_phase(y, half_window))
+def cpr(y: np.ndarray, half_window: int, sym: np.ndarray = None, n_ref: int = 0) -> np.ndarray:
+    """y e^{-j phi}; with n_ref > 0 known symbols the quarter-turn ambiguity of the fourth-power
+    estimate is resolved per polarization: the rotation by q pi/2, q the nearest integer to
+    arg(sum_{k < n_ref} z_k conj(s_k)) / (pi/2), that best aligns them."""
+    z = y * np.exp(-1j * cpr_phase(y, half_window))
+    if n_ref > 0:
+        c = np.sum(z[:, :n_ref] * np.conj(sym[:, :n_ref]), axis=-1)
+        q = np.round(np.angle(c) / QUARTER)
+        z = z * np.exp(-1j * QUARTER * q)[:, None]
+    return z
 
 
 def bit_errors(z: np.ndarray, sym: np.ndarray) -> int:
@@ -107,4 +116,4 @@ def receiver_chain(x: np.ndarray, sym: np.ndarray, up: int, down: int, n_taps_rs
     carrier phase: (symbols after phase recovery [2, n_sym], equalizer taps)."""
     x2 = resample(x, up, down, n_taps_rs, beta)
     W = equalizer_ls(x2, sym, n_eq, n_train)
-    return cpr(equalizer_apply(x2, W), half_window), W
+    return cpr(equalizer_apply(x2, W), half_window, sym, n_train), W

@@ -102,6 +102,20 @@ def lib():
         L.dbp_rx_reset.restype = c_int32
         L.dbp_rx_destroy.argtypes = [c_void_p]
         L.dbp_rx_destroy.restype = None
+        L.dbp_dsp_create.argtypes = [POINTER(DspDesc), c_int64, POINTER(c_void_p)]
+        L.dbp_dsp_create.restype = c_int32
+        L.dbp_dsp_info.argtypes = [c_void_p, POINTER(c_int64), POINTER(c_int64)]
+        L.dbp_dsp_info.restype = c_int32
+        L.dbp_dsp_resample.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p]
+        L.dbp_dsp_resample.restype = c_int32
+        L.dbp_dsp_train.argtypes = [c_void_p, c_void_p, c_void_p, c_int64, c_void_p, c_void_p]
+        L.dbp_dsp_train.restype = c_int32
+        L.dbp_dsp_equalize.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
+        L.dbp_dsp_equalize.restype = c_int32
+        L.dbp_dsp_cpr.argtypes = [c_void_p, c_void_p, c_void_p, c_int64, c_void_p, POINTER(c_int64), c_void_p]
+        L.dbp_dsp_cpr.restype = c_int32
+        L.dbp_dsp_destroy.argtypes = [c_void_p]
+        L.dbp_dsp_destroy.restype = None
         L.dbp_status_string.argtypes = [c_int32]
         L.dbp_status_string.restype = ctypes.c_char_p
         L.dbp_version.argtypes = []
@@ -415,6 +429,91 @@ def receiver(chunk: int, n_spans: int, steps_per_span: int = 1, **kw) -> Receive
 
 def plan_batch(descs) -> BatchPlan:
     return BatchPlan(descs)
+
+
+class DspDesc(ctypes.Structure):
+    _fields_ = [("up", c_int32), ("down", c_int32), ("resample_taps", c_int32), ("kaiser_beta", c_double),
+                ("eq_taps", c_int32), ("cpr_half_window", c_int32)]
+
+
+class ReceiverDsp:
+    """A dbp_dsp: resampling to two samples per symbol, least-squares butterfly equalizer,
+    carrier-phase recovery and decisions after backpropagation (Sec. IV).  Fields are
+    complex64 CUDA tensors [2][n]."""
+
+    def __init__(self, n_in: int, up: int = 28, down: int = 25, resample_taps: int = 48, kaiser_beta: float = 8.0,
+                 eq_taps: int = 15, cpr_half_window: int = 16):
+        self.desc = DspDesc(up, down, resample_taps, kaiser_beta, eq_taps, cpr_half_window)
+        h = c_void_p()
+        _check(lib().dbp_dsp_create(ctypes.byref(self.desc), n_in, ctypes.byref(h)), "dbp_dsp_create")
+        self._h = h
+        no, ns = c_int64(), c_int64()
+        _check(lib().dbp_dsp_info(h, ctypes.byref(no), ctypes.byref(ns)), "dbp_dsp_info")
+        self.n_in, self.n_out, self.n_sym = n_in, no.value, ns.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().dbp_dsp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def _field(t, n, what):
+        import torch
+        if t.dtype != torch.complex64 or not t.is_cuda or not t.is_contiguous() or t.numel() != 2 * n:
+            raise ValueError(f"{what} must be a contiguous complex64 CUDA tensor [2][{n}]")
+
+    def resample(self, x, out=None, stream=None):
+        import torch
+        self._field(x, self.n_in, "x")
+        if out is None:
+            out = torch.empty(2, self.n_out, dtype=torch.complex64, device=x.device)
+        _check(lib().dbp_dsp_resample(self._h, _ptr(x), _ptr(out), _stream_ptr(stream)), "dbp_dsp_resample")
+        return out
+
+    def train(self, x2, sym, n_train: int, stream=None):
+        """Least-squares butterfly taps [2][2][N] (complex64, device) from the first n_train symbols."""
+        import torch
+        self._field(x2, self.n_out, "x2")
+        self._field(sym, self.n_sym, "sym")
+        taps = torch.empty(2, 2, self.desc.eq_taps, dtype=torch.complex64, device=x2.device)
+        _check(lib().dbp_dsp_train(self._h, _ptr(x2), _ptr(sym), n_train, _ptr(taps), _stream_ptr(stream)),
+               "dbp_dsp_train")
+        return taps
+
+    def equalize(self, x2, taps, out=None, stream=None):
+        import torch
+        self._field(x2, self.n_out, "x2")
+        if taps.dtype != torch.complex64 or not taps.is_cuda or taps.numel() != 4 * self.desc.eq_taps:
+            raise ValueError("taps must be a complex64 CUDA tensor [2][2][eq_taps]")
+        if out is None:
+            out = torch.empty(2, self.n_sym, dtype=torch.complex64, device=x2.device)
+        _check(lib().dbp_dsp_equalize(self._h, _ptr(x2), _ptr(taps.contiguous()), _ptr(out), _stream_ptr(stream)),
+               "dbp_dsp_equalize")
+        return out
+
+    def cpr(self, y, sym=None, n_ref: int = 0, out=None, stream=None):
+        """(z, bit errors or None): phase-recovered symbols (the quarter turn resolved on the
+        first n_ref transmitted symbols) and, with sym, the number of wrong decision bits."""
+        import torch
+        self._field(y, self.n_sym, "y")
+        if sym is not None:
+            self._field(sym, self.n_sym, "sym")
+        if out is None:
+            out = torch.empty_like(y)
+        n = c_int64(-1)
+        _check(lib().dbp_dsp_cpr(self._h, _ptr(y), _ptr(sym), n_ref, _ptr(out),
+                                 ctypes.byref(n) if sym is not None else None, _stream_ptr(stream)), "dbp_dsp_cpr")
+        return out, (n.value if sym is not None else None)
+
+
+def receiver_dsp(n_in: int, **kw) -> ReceiverDsp:
+    return ReceiverDsp(n_in, **kw)
 
 
 def _autograd_function():

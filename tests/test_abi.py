@@ -67,6 +67,45 @@ def test_desc_struct_layout_matches_header(tmp_path):
     assert got == want
 
 
+def test_dsp_desc_struct_layout_matches_header(tmp_path):
+    dbp = _lib_or_skip()
+    fields = [f[0] for f in dbp.DspDesc._fields_]
+    body = "\n".join(f'printf("%zu\\n", offsetof(dbp_dsp_desc, {f}));' for f in fields)
+    src = tmp_path / "probe.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "dbp.h"\nint main(void){'
+                   + body + 'printf("%zu\\n", sizeof(dbp_dsp_desc));return 0;}\n')
+    exe = tmp_path / "probe"
+    assert os.system(f"gcc -std=c99 -I{ROOT}/include {src} -o {exe}") == 0
+    got = [int(v) for v in os.popen(str(exe)).read().split()]
+    want = [getattr(dbp.DspDesc, f).offset for f in fields] + [ctypes.sizeof(dbp.DspDesc)]
+    assert got == want
+
+
+@pytest.mark.parametrize("kw", [
+    dict(up=24), dict(down=0), dict(up=5000, down=1), dict(resample_taps=47), dict(resample_taps=66),
+    dict(kaiser_beta=-1.0), dict(eq_taps=14), dict(eq_taps=33), dict(cpr_half_window=-1),
+    dict(cpr_half_window=300),
+])
+def test_invalid_dsp_descriptors_rejected_without_device(kw):
+    dbp = _lib_or_skip()
+    args = dict(up=28, down=25, resample_taps=48, kaiser_beta=8.0, eq_taps=15, cpr_half_window=16)
+    args.update(kw)
+    d = dbp.DspDesc(**args)
+    h = ctypes.c_void_p(123)
+    assert dbp.lib().dbp_dsp_create(ctypes.byref(d), 2500, ctypes.byref(h)) == 1
+    assert h.value is None
+
+
+def test_invalid_dsp_sizes_rejected_without_device():
+    dbp = _lib_or_skip()
+    d = dbp.DspDesc(28, 25, 48, 8.0, 15, 16)
+    h = ctypes.c_void_p(123)
+    for n_in in (0, 2501, 10):                # not a whole number of outputs; shorter than the taps
+        assert dbp.lib().dbp_dsp_create(ctypes.byref(d), n_in, ctypes.byref(h)) == 1
+    d = dbp.DspDesc(3, 2, 4, 8.0, 3, 2)
+    assert dbp.lib().dbp_dsp_create(ctypes.byref(d), 102, ctypes.byref(h)) == 1   # 153 outputs: odd
+
+
 def _desc(**kw):
     dbp = _lib_or_skip()
     args = dict(n_samples=262144, n_spans=40, steps_per_span=1, beta2_ps2_km=siggen.beta2_ps2_km())

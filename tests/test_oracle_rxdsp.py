@@ -91,6 +91,16 @@ def test_cpr_tracks_a_ramp_through_many_quarter_turns():
     assert D.bit_errors(D.cpr(y, 16)[:, inner], s[:, inner]) == 0
 
 
+def test_cpr_resolves_the_quarter_turn_ambiguity_on_known_symbols():
+    # a phase of 0.3 + pi/2 reads as 0.3 to the fourth-power estimate; the reference symbols
+    # restore the quarter turn, per polarization
+    s = siggen.qpsk_symbols(siggen.rng(37, 0, 0), 2, 2000)
+    y = s * np.exp(1j * np.array([[0.3 + np.pi / 2], [-0.2 - np.pi]]))
+    assert D.bit_errors(D.cpr(y, 16), s) > 1000
+    z = D.cpr(y, 16, s, 100)
+    assert np.max(np.abs(z - s)) <= 1e-12
+
+
 def test_prefix_sum_unwrap_equals_sequential_unwrap():
     r = np.random.default_rng(5)
     theta = D.wrap_quarter(r.uniform(-3, 3, size=(2, 400)))
