@@ -556,6 +556,70 @@ def calibrate_copy():
     log("copied 3 x 1 GiB")
 
 
+def receiver_dsp_workload(dbp, torch, powers=(-2.0, -1.0, 0.0, 1.0, 2.0, 3.0, 4.0), osnr_db=14.0, n_sym=131068,
+                          n_train=8000, linewidth_hz=200e3):
+    """Sec. IV's receiver: a 50 GSa/s capture (about 1.8 samples per symbol) backpropagated at
+    that rate (ESSFM 1 step/span with taps fitted to SSFM 20 steps/span, SSFM 20 steps/span, CD
+    only), then on the GPU: resampling to 2 samples per symbol, least-squares butterfly
+    equalizer trained on the first n_train symbols, fourth-power phase recovery, decisions.
+    The link adds ASE (OSNR osnr_db for 0 dBm, fixed), a constant polarization rotation and
+    laser phase noise (summed linewidth).  BER on the symbols after the training prefix; the
+    time of the DSP chain for one capture (both polarizations)."""
+    from paper_1507_00921_amd import fit as G
+    fs = 0.050
+    n = n_sym * 25 // 14
+    b2 = siggen.beta2_ps2_km()
+    dsp = dbp.receiver_dsp(n)
+    fwd = dbp.plan(n, SPANS, 100, forward=True, fs_thz=fs, beta2_ps2_km=b2)
+    ssfm = dbp.plan(n, SPANS, 20, fs_thz=fs, block=BLOCK, overlap=OVERLAP, beta2_ps2_km=b2)
+    cd = dbp.plan(n, 1, 1, span_km=80.0 * SPANS, gamma_w_km=0.0, fs_thz=fs, block=8192, overlap=2048,
+                  beta2_ps2_km=b2)
+    c0 = np.zeros(NC + 1)
+    c0[0] = 1.0
+    fit_plan = dbp.plan(n, SPANS, 1, taps=G.symmetric_full(c0), fs_thz=fs, block=BLOCK, overlap=OVERLAP,
+                        beta2_ps2_km=b2)
+    res = {}
+    t_chain = []
+    for pw in powers:
+        x, sym = siggen.transmitted_field_at_rate(50, 0, 2, n_sym, pw, fs)
+        rx = fwd.backprop(torch.from_numpy(x.astype(np.complex64)).reshape(1, 2, n).cuda())
+        r = rx.cpu().numpy().reshape(2, n).astype(np.complex128)
+        r = siggen.add_awgn(siggen.rng(50, 0, 1), r, siggen.awgn_sigma2(siggen.dbm_to_w(0.0), osnr_db, fs_thz=fs))
+        r = siggen.polarization_rotation(siggen.rng(50, 0, 2)) @ r
+        r = r * np.exp(1j * siggen.laser_phase_noise(siggen.rng(50, 0, 3), n, linewidth_hz, fs))
+        rxd = torch.from_numpy(r.astype(np.complex64)).reshape(1, 2, n).cuda()
+        target = ssfm.backprop(rxd)
+        c, _ = G.fit_coefficients(fit_plan, rxd, NC, target=target, sl=slice(BLOCK, 100000))
+        essfm = dbp.plan(n, SPANS, 1, taps=G.symmetric_full(c), fs_thz=fs, block=BLOCK, overlap=OVERLAP,
+                         beta2_ps2_km=b2)
+        symd = torch.from_numpy(sym.astype(np.complex64)).cuda()
+        out = {}
+        for name, y in (("essfm_1_per_span", essfm.backprop(rxd)), ("ssfm_20_per_span", target),
+                        ("cd_only", cd.backprop(rxd))):
+            yf = y.reshape(2, n).contiguous()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            x2 = dsp.resample(yf)
+            taps = dsp.train(x2, symd, n_train)
+            z, _ = dsp.cpr(dsp.equalize(x2, taps), symd, n_train)
+            torch.cuda.synchronize()
+            t_chain.append(time.perf_counter() - t0)
+            zh = z.cpu().numpy()[:, n_train:]
+            sh = sym[:, n_train:]
+            errs = int(np.sum((zh.real < 0) != (sh.real < 0)) + np.sum((zh.imag < 0) != (sh.imag < 0)))
+            out[name] = {"ber": errs / (4 * zh.shape[1]), "bit_errors": errs,
+                         "evm_db": round(20 * np.log10(siggen.evm(zh, sh)), 3)}
+        res[f"{pw:+.0f}"] = out
+        log(f"receiver chain {pw:+.0f} dBm " + json.dumps(out))
+        essfm.close()
+    ms = float(np.median(t_chain)) * 1e3
+    return {"workload": f"PM-QPSK 28 GBd captured at 50 GSa/s, 2x{n} samples ({n_sym} symbols), 40x80 km, "
+                        f"ASE at {osnr_db:.0f} dB OSNR for 0 dBm, {linewidth_hz / 1e3:.0f} kHz summed linewidth, "
+                        f"random polarization rotation; equalizer 2x2x15 taps trained on {n_train} symbols, "
+                        f"phase window 33 symbols; BER on the {n_sym - n_train} symbols after the training",
+            "dsp_chain_ms": round(ms, 3), "dsp_msamples_per_s": round(n / ms / 1e3, 1), "ber_by_launch_dbm": res}
+
+
 def copy_bandwidth(torch, reps=20):
     """Achieved bandwidth of a plain 1 GiB device-to-device copy (read + write = 2 GiB per
     copy), median of 5 timed groups: the practical HBM ceiling beside the 8 TB/s datasheet."""
@@ -743,6 +807,8 @@ def main():
         log("large working set " + json.dumps(hbm))
         extras["gradient"] = grad_workload(dbp, torch)
         log("gradient workload " + json.dumps(extras["gradient"]))
+        extras["receiver_dsp"] = receiver_dsp_workload(dbp, torch)
+        log("receiver DSP " + json.dumps({k: v for k, v in extras["receiver_dsp"].items() if k != "ber_by_launch_dbm"}))
         extras["batch"] = batch_workload(dbp, torch)
         log("batch workload " + json.dumps(extras["batch"]))
         extras["precision"] = precision_workload(dbp, torch)

@@ -117,7 +117,7 @@ def shape_at_rate(symbols: np.ndarray, fs_thz: float, rolloff: float = ROLLOFF,
     f_norm = k / n_sym                                             # frequency in units of R
     # the DFT of samples of one continuous signal scales with the sampling rate
     X = S[..., k % n_sym] * np.sqrt(2.0 * raised_cosine(f_norm, rolloff)) * (fs_thz / (2.0 * symbol_rate_thz))
-    return np.fft.ifft(X, axis=-1)
+    return np.ascontiguousarray(np.fft.ifft(X, axis=-1))
 
 
 def transmitted_field_at_rate(cfg: int, idx: int, n_pol: int, n_sym: int, p_dbm: float, fs_thz: float,
