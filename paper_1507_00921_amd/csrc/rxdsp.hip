@@ -3,8 +3,9 @@
 // recovery and decisions.  Definitions and conventions in include/dbp.h.
 //
 // Kernels:
-//   rs_kernel      one output sample per thread, K-tap polyphase FIR (the table
-//                  holds the windowed sinc of every output phase, made in FP64)
+//   rs_kernel      one output sample per thread, K-tap polyphase FIR over the
+//                  workgroup's input window in LDS (the table holds the windowed
+//                  sinc of every output phase, made in FP64)
 //   gram_kernel    per chunk of training symbols, every entry of U^H U and U^H s
 //                  (FP32 sums over the chunk's regressors staged in LDS)
 //   gram_reduce    the chunk sums added in FP64, chunk by chunk in order
@@ -39,27 +40,40 @@ __device__ __forceinline__ long long wrap_index(long long i, long long n) {
     return i < 0 ? i + n : i;
 }
 
+// grid (ceil(n_out / 256), 2): 256 consecutive outputs of one polarization; their input
+// window (at most 256 down / up + K + 1 samples, down <= up) is staged in LDS once.
 __global__ __launch_bounds__(THREADS) void rs_kernel(const float2* __restrict__ in, float2* __restrict__ out,
                                                      long long n_in, long long n_out, int up, int down, int K,
                                                      const float* __restrict__ table) {
-    const long long i = (long long)blockIdx.x * THREADS + threadIdx.x;
-    if (i >= 2 * n_out) return;
-    const int p = i >= n_out ? 1 : 0;
-    const long long m = i - p * n_out;
+    extern __shared__ float2 xs[];
+    const int p = blockIdx.y, t = threadIdx.x;
+    const long long m0 = (long long)blockIdx.x * THREADS;
+    const long long m_last = (m0 + THREADS < n_out ? m0 + THREADS : n_out) - 1;
+    const long long i0 = (m0 * down) / up - K / 2 + 1;
+    const int span = (int)((m_last * down) / up - K / 2 + 1 + K - i0);
+    const float2* __restrict__ x = in + p * n_in;
+    for (int e = t; e < span; e += THREADS) {
+        long long j = i0 + e;                  // within (-K, n_in + K): n_in >= K
+        j = j < 0 ? j + n_in : (j >= n_in ? j - n_in : j);
+        xs[e] = x[j];
+    }
+    __syncthreads();
+    const long long m = m0 + t;
+    if (m > m_last) return;
     const long long md = m * down;
     const long long base = md / up;
     const int ph = (int)(md - base * up);
     const float* __restrict__ h = table + (long long)ph * K;
-    const float2* __restrict__ x = in + p * n_in;
-    const long long j0 = base - K / 2 + 1;
+    const float2* xw = xs + (base - K / 2 + 1 - i0);
     float ax = 0.f, ay = 0.f;
+#pragma unroll 8
     for (int k = 0; k < K; ++k) {
-        const float2 v = x[wrap_index(j0 + k, n_in)];
+        const float2 v = xw[k];
         const float w = h[k];
         ax = fmaf(w, v.x, ax);
         ay = fmaf(w, v.y, ay);
     }
-    out[i] = make_float2(ax, ay);
+    out[p * n_out + m] = make_float2(ax, ay);
 }
 
 // Regressor element i < 2N of symbol k: x_q[(2k + j - N/2) mod n2], q = i / N, j = i % N.
@@ -132,11 +146,12 @@ __global__ __launch_bounds__(THREADS) void eq_kernel(const float2* __restrict__ 
     const long long k = (long long)blockIdx.x * THREADS + threadIdx.x;
     if (k >= n_sym) return;
     const int c = N / 2;
+    const bool inner = 2 * k - c >= 0 && 2 * k - c + N <= n2;
     float a0x = 0.f, a0y = 0.f, a1x = 0.f, a1y = 0.f;
     for (int q = 0; q < 2; ++q) {
         const float2* __restrict__ xq = x2 + q * n2;
         for (int j = 0; j < N; ++j) {
-            const float2 v = xq[wrap_index(2 * k + j - c, n2)];
+            const float2 v = xq[inner ? 2 * k + j - c : wrap_index(2 * k + j - c, n2)];
             const float2 w0 = w[(0 * 2 + q) * N + j], w1 = w[(1 * 2 + q) * N + j];
             a0x = fmaf(w0.x, v.x, fmaf(-w0.y, v.y, a0x));
             a0y = fmaf(w0.x, v.y, fmaf(w0.y, v.x, a0y));
@@ -200,28 +215,51 @@ __global__ __launch_bounds__(CPR_B) void cpr_theta(const float2* __restrict__ y,
     if (t == CPR_B - 1) tot[p * n_blocks + b] = sc[t];
 }
 
-__global__ void cpr_offsets(const float* __restrict__ tot, int n_blocks, double* __restrict__ offs) {
-    const int p = threadIdx.x;
-    if (p >= 2) return;
+// Exclusive prefix of the block totals in FP64, one workgroup per polarization: thread t
+// sums its contiguous segment of blocks, thread 0 scans the segment sums in order, then each
+// thread writes its segment's offsets (a fixed order of additions for a given n_blocks).
+__global__ __launch_bounds__(THREADS) void cpr_offsets(const float* __restrict__ tot, int n_blocks,
+                                                       double* __restrict__ offs) {
+    __shared__ double seg[THREADS];
+    const int p = blockIdx.x, t = threadIdx.x;
+    const int per = (n_blocks + THREADS - 1) / THREADS;
+    const int b0 = t * per, b1 = min(n_blocks, b0 + per);
+    const float* __restrict__ tp = tot + (long long)p * n_blocks;
     double s = 0.0;
-    for (int b = 0; b < n_blocks; ++b) {
-        offs[p * n_blocks + b] = s;
-        s += (double)tot[p * n_blocks + b];
+    for (int b = b0; b < b1; ++b) s += (double)tp[b];
+    seg[t] = s;
+    __syncthreads();
+    if (t == 0) {
+        double run = 0.0;
+        for (int i = 0; i < THREADS; ++i) {
+            const double v = seg[i];
+            seg[i] = run;
+            run += v;
+        }
+    }
+    __syncthreads();
+    double run = seg[t];
+    double* __restrict__ op = offs + (long long)p * n_blocks;
+    for (int b = b0; b < b1; ++b) {
+        op[b] = run;
+        run += (double)tp[b];
     }
 }
 
 // Quarter-turn ambiguity against the first n_ref known symbols: the rotation q pi/2 with q
 // the nearest integer to arg(sum z_k conj(s_k)) / (pi/2), z the derotated symbols (FP64 sums,
 // fixed order); 0 when n_ref = 0.  One workgroup per polarization.
-__global__ __launch_bounds__(CPR_B) void cpr_quadrant(const float2* __restrict__ y, const float2* __restrict__ sym,
+constexpr int QUAD_THREADS = 1024;
+
+__global__ __launch_bounds__(QUAD_THREADS) void cpr_quadrant(const float2* __restrict__ y, const float2* __restrict__ sym,
                                                       long long n_sym, long long n_ref,
                                                       const float* __restrict__ theta0, const float* __restrict__ pre,
                                                       const double* __restrict__ offs, int n_blocks,
                                                       float* __restrict__ qrot) {
-    __shared__ double rx[CPR_B], ry[CPR_B];
+    __shared__ double rx[QUAD_THREADS], ry[QUAD_THREADS];
     const int p = blockIdx.x, t = threadIdx.x;
     double ax = 0.0, ay = 0.0;
-    for (long long k = t; k < n_ref; k += CPR_B) {
+    for (long long k = t; k < n_ref; k += QUAD_THREADS) {
         const float phi = (float)((double)theta0[p] + offs[p * n_blocks + k / CPR_B] + (double)pre[p * n_sym + k]);
         float sn, cs;
         sincosf(phi, &sn, &cs);
@@ -234,7 +272,7 @@ __global__ __launch_bounds__(CPR_B) void cpr_quadrant(const float2* __restrict__
     rx[t] = ax;
     ry[t] = ay;
     __syncthreads();
-    for (int off = CPR_B / 2; off > 0; off >>= 1) {
+    for (int off = QUAD_THREADS / 2; off > 0; off >>= 1) {
         if (t < off) {
             rx[t] += rx[t + off];
             ry[t] += ry[t + off];
@@ -421,7 +459,8 @@ dbp_status dbp_dsp_resample(dbp_dsp_t s, const void* in, void* out, void* stream
     const char* a = (const char*)in;
     const char* b = (const char*)out;
     if (a < b + 2 * s->n_out * sizeof(float2) && b < a + 2 * s->n_in * sizeof(float2)) return DBP_ERR_INVALID_ARG;
-    hipLaunchKernelGGL(rs_kernel, dim3(grid_of(2 * s->n_out, THREADS)), dim3(THREADS), 0, (hipStream_t)stream,
+    const size_t smem = (size_t)(THREADS + s->d.resample_taps + 2) * sizeof(float2);
+    hipLaunchKernelGGL(rs_kernel, dim3(grid_of(s->n_out, THREADS), 2), dim3(THREADS), smem, (hipStream_t)stream,
                        (const float2*)in, (float2*)out, (long long)s->n_in, (long long)s->n_out, s->d.up, s->d.down,
                        s->d.resample_taps, (const float*)s->table);
     return hipGetLastError() == hipSuccess ? DBP_OK : DBP_ERR_HIP;
@@ -487,8 +526,8 @@ dbp_status dbp_dsp_cpr(dbp_dsp_t s, const void* y, const void* sym, int64_t n_re
     const dim3 grid(s->n_blocks, 2);
     hipLaunchKernelGGL(cpr_theta, grid, dim3(CPR_B), 0, st, (const float2*)y, (long long)s->n_sym,
                        s->d.cpr_half_window, s->theta0, s->pre, s->tot, s->n_blocks);
-    hipLaunchKernelGGL(cpr_offsets, dim3(1), dim3(64), 0, st, (const float*)s->tot, s->n_blocks, s->offs);
-    hipLaunchKernelGGL(cpr_quadrant, dim3(2), dim3(CPR_B), 0, st, (const float2*)y, (const float2*)sym,
+    hipLaunchKernelGGL(cpr_offsets, dim3(2), dim3(THREADS), 0, st, (const float*)s->tot, s->n_blocks, s->offs);
+    hipLaunchKernelGGL(cpr_quadrant, dim3(2), dim3(QUAD_THREADS), 0, st, (const float2*)y, (const float2*)sym,
                        (long long)s->n_sym, (long long)n_ref, (const float*)s->theta0, (const float*)s->pre,
                        (const double*)s->offs, s->n_blocks, s->qrot);
     hipLaunchKernelGGL(cpr_apply, grid, dim3(CPR_B), 0, st, (const float2*)y, (const float2*)sym, (long long)s->n_sym,
