@@ -145,3 +145,40 @@ def test_argument_rules(dbp):
     z = torch.empty_like(y)
     assert L.dbp_dsp_cpr(d._h, ctypes.c_void_p(y.data_ptr()), None, 10, ctypes.c_void_p(z.data_ptr()), None,
                          None) == 1                                  # reference symbols missing
+
+
+def test_backpropagation_at_the_scope_rate_then_dsp_matches_oracle(dbp):
+    # the paper's order: ESSFM backpropagation at 50 GSa/s (about 1.8 samples per symbol), then
+    # resampling, equalizer and phase recovery; 4 x 80 km at +3 dBm, forward channel by the
+    # oracle at 20 steps per span, 16 dB OSNR for 0 dBm, rotation and phase noise after it
+    from oracle import dbp_ref as R
+    fs, n_spans, n_sym = 0.050, 4, 14000
+    x, s = siggen.transmitted_field_at_rate(41, 0, 2, n_sym, 3.0, fs)
+    fwd = R.schedule(n_spans, 80.0, 20, siggen.beta2_ps2_km(), siggen.GAMMA_W_KM, siggen.ALPHA_DB_KM,
+                     backward=False)
+    rx = R.run_whole(x, fwd, fs)
+    rx = siggen.add_awgn(siggen.rng(41, 0, 1), rx, siggen.awgn_sigma2(siggen.dbm_to_w(0.0), 16.0, fs_thz=fs))
+    rx = siggen.polarization_rotation(siggen.rng(41, 0, 2)) @ rx
+    rx = (rx * np.exp(1j * siggen.laser_phase_noise(siggen.rng(41, 0, 3), rx.shape[-1], 200e3, fs)))
+    rx = rx.astype(np.complex64)
+    n = rx.shape[-1]
+    taps = siggen.symmetric_taps(siggen.rng(41, 0, 4), 4).astype(np.float32)
+    p = dbp.plan(n, n_spans, 1, fs_thz=fs, taps=taps, block=1024, overlap=256, beta2_ps2_km=siggen.beta2_ps2_km())
+    y = p.backprop(dev(rx).reshape(1, 2, n)).reshape(2, n).contiguous()
+    steps = R.schedule(n_spans, 80.0, 1, siggen.beta2_ps2_km(), siggen.GAMMA_W_KM, siggen.ALPHA_DB_KM,
+                       taps=taps.astype(np.float64))
+    y_ref = R.run_blocked(rx.astype(np.complex128), steps, fs, p.block, p.overlap, p.steps_per_pass)
+    err = rel(host(y), y_ref)
+    print(f"ESSFM at 50 GSa/s, Nb={p.block} O={p.overlap} k={p.steps_per_pass}: rel L2 {err:.2e}")
+    assert err <= 1e-5
+    d = dbp.receiver_dsp(n)
+    x2 = d.resample(y)
+    taps_eq = d.train(x2, dev(s.astype(np.complex64)), 3000)
+    z, nerr = d.cpr(d.equalize(x2, taps_eq), dev(s.astype(np.complex64)), 3000)
+    z_ref, _ = D.receiver_chain(y_ref, s, 28, 25, 48, 8.0, 15, 3000, 16)
+    zh = host(z)
+    amb = int(np.sum(near_boundary(z_ref)))
+    print(f"bit errors GPU {nerr}, oracle chain {D.bit_errors(z_ref, s)}, near-boundary {amb}, "
+          f"EVM {20 * np.log10(siggen.evm(zh, s)):.3f} / {20 * np.log10(siggen.evm(z_ref, s)):.3f} dB")
+    assert abs(nerr - D.bit_errors(z_ref, s)) <= amb
+    assert abs(20 * np.log10(siggen.evm(zh, s)) - 20 * np.log10(siggen.evm(z_ref, s))) <= 0.01
