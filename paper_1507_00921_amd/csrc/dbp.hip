@@ -468,7 +468,9 @@ static dbp_status choose_stream(Plan* p, const KernelEntry* ke, int n_tables) {
     if (grid < 8) return DBP_OK;
     const long long v = p->geo.block - p->geo.overlap;
     const long long n_wg = (p->desc.n_samples + v - 1) / v * p->desc.batch;
-    if (!(on && std::atoi(on) == 1) && n_wg < 2LL * grid) return DBP_OK;
+    // measured on the 64-signal field: the streaming kernel is within noise of the per-block
+    // kernel at one step per pass and 4-7 % slower at two, so it is chosen for k = 1 only
+    if (!(on && std::atoi(on) == 1) && (n_wg < 2LL * grid || p->geo.k > 1)) return DBP_OK;
     p->launch_stream = (void*)ke->sfn;
     p->stream_grid = grid;
     std::snprintf(p->kernel_name, sizeof(p->kernel_name), "dbp_stream_kernel<%d, %d, %d, %s, %d>", ke->nb, ke->e,
