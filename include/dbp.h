@@ -308,9 +308,10 @@ typedef struct {
 
 /* Create the receiver DSP for input blocks of n_in samples per polarization at
  * the input rate; n_out = n_in up / down must be an integer and even (n_sym =
- * n_out / 2 symbols).  Allocates its tables and scratch on the current device
- * (synchronously); *out is NULL on error (DBP_ERR_INVALID_ARG for a bad desc or
- * size). */
+ * n_out / 2 symbols).  Allocates its tables and all scratch of the later calls
+ * on the current device (synchronously; no later call allocates); *out is NULL
+ * on error (DBP_ERR_INVALID_ARG for a bad desc or size).  Calls on one dsp share
+ * its scratch: issue them in order on one stream. */
 dbp_status dbp_dsp_create(const dbp_dsp_desc* desc, int64_t n_in, dbp_dsp_t* out);
 
 /* Sizes: n_out samples per polarization after resampling, n_sym symbols.  Either

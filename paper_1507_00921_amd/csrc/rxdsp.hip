@@ -332,6 +332,8 @@ struct dbp_dsp_s {
     float* tot = nullptr;          // [2][n_blocks]
     double* offs = nullptr;        // [2][n_blocks]
     int* errs = nullptr;           // [2][n_blocks]
+    float2* gpart = nullptr;       // normal-equation chunk sums [ceil(n_sym / GRAM_CH)][E]
+    double2* gsum = nullptr;       // their FP64 totals [E]
     void* mem = nullptr;
 };
 
@@ -414,8 +416,11 @@ dbp_status dbp_dsp_create(const dbp_dsp_desc* desc, int64_t n_in, dbp_dsp_t* out
     const size_t table_b = (size_t)up * K * sizeof(float);
     const size_t nb = (size_t)s->n_blocks;
     auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const int M = 2 * desc->eq_taps, E = M * M + 2 * M;
+    const size_t gpart_b = (size_t)grid_of(s->n_sym, GRAM_CH) * E * sizeof(float2);
     const size_t bytes = al(table_b) + 2 * al(2 * sizeof(float)) + al(2 * s->n_sym * sizeof(float)) +
-                         al(2 * nb * sizeof(float)) + al(2 * nb * sizeof(double)) + al(2 * nb * sizeof(int));
+                         al(2 * nb * sizeof(float)) + al(2 * nb * sizeof(double)) + al(2 * nb * sizeof(int)) +
+                         al(gpart_b) + al((size_t)E * sizeof(double2));
     if (hipMalloc(&s->mem, bytes) != hipSuccess) {
         delete s;
         return DBP_ERR_OOM;
@@ -434,6 +439,10 @@ dbp_status dbp_dsp_create(const dbp_dsp_desc* desc, int64_t n_in, dbp_dsp_t* out
     s->offs = (double*)m;
     m += al(2 * nb * sizeof(double));
     s->errs = (int*)m;
+    m += al(2 * nb * sizeof(int));
+    s->gpart = (float2*)m;
+    m += al(gpart_b);
+    s->gsum = (double2*)m;
     // windowed sinc of every output phase ph / up, taps k = -K/2 + 1 .. K/2
     std::vector<float> tab((size_t)up * K);
     for (int ph = 0; ph < up; ++ph)
@@ -471,13 +480,8 @@ dbp_status dbp_dsp_train(dbp_dsp_t s, const void* x2, const void* sym, int64_t n
     const int N = s->d.eq_taps, M = 2 * N, E = M * M + 2 * M;
     const int n_chunks = grid_of(n_train, GRAM_CH);
     hipStream_t st = (hipStream_t)stream;
-    float2* part = nullptr;
-    double2* sum = nullptr;
-    if (hipMalloc((void**)&part, (size_t)n_chunks * E * sizeof(float2)) != hipSuccess) return DBP_ERR_OOM;
-    if (hipMalloc((void**)&sum, (size_t)E * sizeof(double2)) != hipSuccess) {
-        (void)hipFree(part);
-        return DBP_ERR_OOM;
-    }
+    float2* part = s->gpart;
+    double2* sum = s->gsum;
     const size_t smem = (size_t)(2 * (2 * GRAM_CH + N) + 2 * GRAM_CH) * sizeof(float2);
     hipLaunchKernelGGL(gram_kernel, dim3(n_chunks), dim3(THREADS), smem, st, (const float2*)x2, (long long)s->n_out,
                        (const float2*)sym, (long long)s->n_sym, (long long)n_train, N, part);
@@ -487,8 +491,6 @@ dbp_status dbp_dsp_train(dbp_dsp_t s, const void* x2, const void* sym, int64_t n
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipMemcpyAsync(h.data(), sum, (size_t)E * sizeof(double2), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
-    (void)hipFree(part);
-    (void)hipFree(sum);
     if (e != hipSuccess) return DBP_ERR_HIP;
     std::vector<std::complex<double>> A((size_t)M * M), B((size_t)M * 2);
     for (int i = 0; i < M * M; ++i) A[i] = {h[i].x, h[i].y};
