@@ -182,3 +182,25 @@ def test_backpropagation_at_the_scope_rate_then_dsp_matches_oracle(dbp):
           f"EVM {20 * np.log10(siggen.evm(zh, s)):.3f} / {20 * np.log10(siggen.evm(z_ref, s)):.3f} dB")
     assert abs(nerr - D.bit_errors(z_ref, s)) <= amb
     assert abs(20 * np.log10(siggen.evm(zh, s)) - 20 * np.log10(siggen.evm(z_ref, s))) <= 0.01
+
+
+def test_degenerate_settings_match_oracle(dbp):
+    # ratio 1 (identity resampling), one-tap butterfly (the even samples only), a one-symbol
+    # phase window: every stage still equals the oracle's
+    x, s = capture(5, 2800)
+    n = x.shape[-1]
+    d = dbp.receiver_dsp(n, up=25, down=25, resample_taps=2, kaiser_beta=0.0, eq_taps=1, cpr_half_window=0)
+    assert (d.n_out, d.n_sym) == (n, n // 2)
+    x2 = d.resample(dev(x))
+    assert float(np.max(np.abs(host(x2) - x.astype(np.complex128)))) <= 1e-6
+    ref2 = D.resample(x.astype(np.complex128), 25, 25, 2, 0.0)
+    assert rel(host(x2), ref2) <= 1e-7
+    sym2 = s[:, : n // 2].astype(np.complex64)                  # any known sequence of the right length
+    taps = d.train(x2, dev(sym2), 1000)
+    W_ref = D.equalizer_ls(host(x2), sym2.astype(np.complex128), 1, 1000)
+    assert rel(host(taps), W_ref) <= 1e-4
+    y = d.equalize(x2, taps)
+    assert rel(host(y), D.equalizer_apply(host(x2), host(taps))) <= 1e-6
+    z, _ = d.cpr(y)
+    z_ref = D.cpr(host(y), 0)
+    assert float(np.max(np.abs(host(z) - z_ref))) <= 1e-4
