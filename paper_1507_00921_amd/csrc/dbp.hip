@@ -194,7 +194,7 @@ dbp_status choose_geometry(const dbp_desc* d, const std::vector<double>& b, Geom
         // time-domain steps: one launch per step on tiles whose halo covers the
         // FIR and tap spans, so tiling is exact for any signal length
         if (nc > FT_MAXC || (d->n_fir - 1) / 2 > FT_MAXH) return DBP_ERR_UNSUPPORTED;
-        g.block = FT_TS;
+        g.block = fir_fwd_tile(d->n_fir, 2 * nc + 1);
         g.overlap = 2 * ((d->n_fir - 1) / 2 + nc);
         g.k = 1;
         g.e = 0;
@@ -724,15 +724,24 @@ namespace dbp {
 
 static constexpr int kCheckpointEvery = 8;
 
-// Time-domain geometry of a FIR-mode plan.
+// Time-domain geometry of a FIR-mode plan: tiles of the forward step and, of
+// another length, of its adjoint (the per-tile partials follow the adjoint's).
 struct FirGeo {
-    int n_tiles, n_wg, nw, width, n_ckpt, seg;
+    int ts, n_tiles, n_wg;              // adjoint tiles
+    int ts_fwd, n_tiles_fwd, n_wg_fwd;  // forward tiles
+    int nw, width, n_ckpt, seg;
 };
 
 static FirGeo fir_geo(const Plan* p) {
     FirGeo f;
-    f.n_tiles = (int)((p->desc.n_samples + FT_TS - 1) / FT_TS);
+    const long long L = p->desc.n_samples;
+    const int ntaps = p->desc.method == DBP_ESSFM ? p->desc.n_taps : 1;
+    f.ts = fir_adj_tile(p->desc.n_fir, ntaps);
+    f.n_tiles = (int)((L + f.ts - 1) / f.ts);
     f.n_wg = f.n_tiles * p->desc.batch;
+    f.ts_fwd = fir_fwd_tile(p->desc.n_fir, ntaps);
+    f.n_tiles_fwd = (int)((L + f.ts_fwd - 1) / f.ts_fwd);
+    f.n_wg_fwd = f.n_tiles_fwd * p->desc.batch;
     f.nw = p->desc.method == DBP_ESSFM ? p->desc.n_taps : 0;
     f.width = f.nw + 2 * p->desc.n_fir;
     f.seg = kCheckpointEvery;
@@ -785,12 +794,13 @@ static size_t fft_grad_ws_bytes(const Plan* p) {
     return (size_t)(f.n_passes - 1) * f.state + f.xs + 2 * f.window + f.part;
 }
 
-static FirArgs fir_args(const Plan* p, int s, const float* taps, const void* fir) {
+static FirArgs fir_args(const Plan* p, int s, const float* taps, const void* fir, bool adjoint = false) {
     FirArgs a{};
     const FirGeo f = fir_geo(p);
     a.L = p->desc.n_samples;
-    a.n_tiles = f.n_tiles;
-    a.n_wg = f.n_wg;
+    a.ts = adjoint ? f.ts : f.ts_fwd;
+    a.n_tiles = adjoint ? f.n_tiles : f.n_tiles_fwd;
+    a.n_wg = adjoint ? f.n_wg : f.n_wg_fwd;
     a.nfir = p->desc.n_fir;
     a.h = (fir ? (const float2*)fir : p->d_fir) + (size_t)s * a.nfir;
     a.ntaps = p->desc.method == DBP_ESSFM ? p->desc.n_taps : 1;
@@ -1025,7 +1035,7 @@ dbp_status dbp_backprop_grad(dbp_plan_t p, const void* in, const float* taps, co
             if (launch_fir_step(npol, a, s) != hipSuccess) return DBP_ERR_HIP;
         }
         for (int j = len - 1; j >= 0; --j, ++r) {
-            FirArgs a = fir_args(p, s0 + j, taps, fir);
+            FirArgs a = fir_args(p, s0 + j, taps, fir, true);
             a.x = j == 0 ? ckpt(c) : buf(b_seg + j - 1);
             a.gz = gcur;
             float2* gdst = ((ns - 1 - r) % 2 == 0) ? gfinal : buf(b_grad + (gfinal == buf(b_grad + 1) ? 0 : 1));

@@ -3,10 +3,12 @@
 // centre taps of the impulse response of Eq. (1), or learned values) instead
 // of the FFT filter, followed by the (E)SSFM nonlinear substep of Eqs. (2)-(3).
 //
-// Both kernels work on tiles of FT_TS consecutive samples of every
-// polarization, circular over the signal.  A tile loads its input with the
-// halo the step needs (h spans +-HF samples, the tap filter w +-NC), so tiled
-// results equal the whole-signal step up to rounding.
+// Both kernels work on tiles of consecutive samples of every polarization,
+// circular over the signal.  A tile loads its input with the halo the step
+// needs (h spans +-HF samples, the tap filter w +-NC), so tiled results equal
+// the whole-signal step up to rounding.  The tile length is chosen per kernel
+// so that the widest range it filters (the FIR output with its halo) is
+// exactly FT_SPAN positions: FR per thread, the same work in every wave.
 //
 // Conventions: u[n] = sum_m h[m] x[n - (m - HF)], J[n] = sum_m w[m] I[n - (m - NC)],
 // z = u exp(-j phi J).  Gradients: g = dL/dRe + j dL/dIm.
@@ -19,16 +21,23 @@
 namespace dbp {
 
 constexpr int FT_THREADS = 256;
-constexpr int FT_TS = 1024;       // output samples per tile
+constexpr int FT_SPAN = 1024;     // FIR outputs per tile (the tile's samples and their halo)
 constexpr int FT_MAXH = 64;       // largest FIR half-width
 constexpr int FT_MAXC = 64;       // largest tap half-width
 constexpr int FR = 4;             // consecutive outputs per thread in the compile-time-tap FIR loops
+static_assert(FT_SPAN == FT_THREADS * FR, "one group of FR outputs per thread");
+
+// Output samples per tile of the forward step (FIR outputs on the tile +-NC) and of
+// the adjoint (recomputed FIR outputs on the tile +-(HF + 2 NC)); ntaps = 1 for SSFM.
+__host__ __device__ constexpr int fir_fwd_tile(int nfir, int ntaps) { return FT_SPAN - (ntaps - 1); }
+__host__ __device__ constexpr int fir_adj_tile(int nfir, int ntaps) { return FT_SPAN - (nfir - 1) - 2 * (ntaps - 1); }
 
 struct FirArgs {
     const float2* x;        // step input [n_sig][NPOL][L]
     float2* z;              // step output (forward) or input gradient (adjoint)
     const float2* gz;       // adjoint: gradient at the step output
     long long L;
+    int ts;                 // output samples per tile
     int n_tiles;            // tiles per signal
     int n_wg;               // n_tiles * n_sig
     const float2* h;        // this step's FIR taps [nfir]
@@ -140,7 +149,7 @@ __device__ __forceinline__ void tap_filter(float* js, const float* is, int n_out
     }
 }
 
-// Forward step on one tile: out[a + o] for o < FT_TS.  NF, NW: compile-time
+// Forward step on one tile: out[a0 + o] for o < ts.  NF, NW: compile-time
 // FIR and intensity tap counts (0 / -1: taken from the arguments; NW = 0: SSFM).
 template <int NPOL, int NF, int NW>
 __global__ __launch_bounds__(FT_THREADS) void fir_step_kernel(FirArgs a) {
@@ -150,8 +159,10 @@ __global__ __launch_bounds__(FT_THREADS) void fir_step_kernel(FirArgs a) {
     const int ntaps = NW > 0 ? NW : (NW == 0 ? 1 : a.ntaps);
     const int HF = (nfir - 1) / 2;
     const int NC = (ntaps - 1) / 2;
-    const int nx = FT_TS + 2 * (HF + NC);     // x on [a0 - HF - NC, a0 + TS + HF + NC)
-    const int nu = FT_TS + 2 * NC;            // u, I on [a0 - NC, a0 + TS + NC)
+    // compile-time tile when both tap counts are (ranges, addresses and trip counts fold)
+    const int TS = NF > 0 && NW >= 0 ? fir_fwd_tile(NF, NW == 0 ? 1 : NW) : a.ts;
+    const int nx = TS + 2 * (HF + NC);        // x on [a0 - HF - NC, a0 + TS + HF + NC)
+    const int nu = TS + 2 * NC;               // u, I on [a0 - NC, a0 + TS + NC)
     float2* hs = reinterpret_cast<float2*>(smem);
     float* wsm = reinterpret_cast<float*>(hs + 2 * FT_MAXH + 1);
     float2* xs = reinterpret_cast<float2*>(wsm + 2 * FT_MAXC + 2);
@@ -162,7 +173,7 @@ __global__ __launch_bounds__(FT_THREADS) void fir_step_kernel(FirArgs a) {
     const int sig = wg / a.n_tiles;
     const int tile = wg - sig * a.n_tiles;
     const long long L = a.L;
-    const long long a0 = (long long)tile * FT_TS;
+    const long long a0 = (long long)tile * TS;
     const float2* __restrict__ x = a.x + (long long)sig * NPOL * L;
     float2* __restrict__ z = a.z + (long long)sig * NPOL * L;
 
@@ -173,7 +184,7 @@ __global__ __launch_bounds__(FT_THREADS) void fir_step_kernel(FirArgs a) {
     __syncthreads();
     fir_u<NPOL, NF>(us, is, xs, nx, nu, hs, nfir);
     __syncthreads();
-    for (int o = threadIdx.x; o < FT_TS; o += FT_THREADS) {
+    for (int o = threadIdx.x; o < TS; o += FT_THREADS) {
         if (a0 + o >= L) break;
         float j = 0.f;
         if constexpr (NW != 0) {
@@ -188,7 +199,7 @@ __global__ __launch_bounds__(FT_THREADS) void fir_step_kernel(FirArgs a) {
     }
 }
 
-// Adjoint of one step on one tile: g_x[a0 + o] for o < FT_TS, plus this tile's
+// Adjoint of one step on one tile: g_x[a0 + o] for o < ts, plus this tile's
 // partial sums of dL/dw (owned outputs n in [a0, a0 + TS)) and dL/dh.
 template <int NPOL, int NF, int NW>
 __global__ __launch_bounds__(FT_THREADS) void fir_adjoint_kernel(FirArgs a) {
@@ -198,10 +209,11 @@ __global__ __launch_bounds__(FT_THREADS) void fir_adjoint_kernel(FirArgs a) {
     const int ntaps = NW > 0 ? NW : (NW == 0 ? 1 : a.ntaps);
     const int HF = (nfir - 1) / 2;
     const int NC = (ntaps - 1) / 2;
-    const int nx = FT_TS + 4 * HF + 4 * NC;   // x on [a0 - 2HF - 2NC, ...)
-    const int nu = FT_TS + 2 * HF + 4 * NC;   // u, I on [a0 - HF - 2NC, ...)
-    const int nz = FT_TS + 2 * HF + 2 * NC;   // J, g_z, Jbar on [a0 - HF - NC, ...)
-    const int ng = FT_TS + 2 * HF;            // g_u on [a0 - HF, ...)
+    const int TS = NF > 0 && NW >= 0 ? fir_adj_tile(NF, NW == 0 ? 1 : NW) : a.ts;
+    const int nx = TS + 4 * HF + 4 * NC;      // x on [a0 - 2HF - 2NC, ...)
+    const int nu = TS + 2 * HF + 4 * NC;      // u, I on [a0 - HF - 2NC, ...)
+    const int nz = TS + 2 * HF + 2 * NC;      // J, g_z, Jbar on [a0 - HF - NC, ...)
+    const int ng = TS + 2 * HF;               // g_u on [a0 - HF, ...)
     float2* hs = reinterpret_cast<float2*>(smem);
     float* wsm = reinterpret_cast<float*>(hs + 2 * FT_MAXH + 1);
     float2* xs = reinterpret_cast<float2*>(wsm + 2 * FT_MAXC + 2);
@@ -217,7 +229,7 @@ __global__ __launch_bounds__(FT_THREADS) void fir_adjoint_kernel(FirArgs a) {
     const int sig = wg / a.n_tiles;
     const int tile = wg - sig * a.n_tiles;
     const long long L = a.L;
-    const long long a0 = (long long)tile * FT_TS;
+    const long long a0 = (long long)tile * TS;
     const float2* __restrict__ x = a.x + (long long)sig * NPOL * L;
     const float2* __restrict__ gz = a.gz + (long long)sig * NPOL * L;
     float2* __restrict__ gx = a.z + (long long)sig * NPOL * L;
@@ -275,7 +287,7 @@ __global__ __launch_bounds__(FT_THREADS) void fir_adjoint_kernel(FirArgs a) {
     if constexpr (NF > 0) {
         // FR consecutive outputs per thread, window j = r + m of g_u in registers
         constexpr int W = FR + NF - 1;
-        for (int base = t * FR; base < FT_TS; base += FT_THREADS * FR) {
+        for (int base = t * FR; base < TS; base += FT_THREADS * FR) {
 #pragma unroll
             for (int p = 0; p < NPOL; ++p) {
                 const float2* gr = gzs + p * nz + NC + base;     // g_u at base - HF
@@ -301,7 +313,7 @@ __global__ __launch_bounds__(FT_THREADS) void fir_adjoint_kernel(FirArgs a) {
             }
         }
     } else
-    for (int o = t; o < FT_TS; o += FT_THREADS) {
+    for (int o = t; o < TS; o += FT_THREADS) {
         if (a0 + o >= L) break;
 #pragma unroll
         for (int p = 0; p < NPOL; ++p) {
@@ -317,7 +329,7 @@ __global__ __launch_bounds__(FT_THREADS) void fir_adjoint_kernel(FirArgs a) {
             gx[p * L + a0 + o] = acc;
         }
     }
-    const int n_own = (int)min((long long)FT_TS, L - a0);
+    const int n_own = (int)min((long long)TS, L - a0);
     const int nw = NW != 0 ? ntaps : 0;
     // partials parameter-major ([parameter][tile]) so that the reduction reads them contiguously
     float* part = a.part + wg;
@@ -325,8 +337,8 @@ __global__ __launch_bounds__(FT_THREADS) void fir_adjoint_kernel(FirArgs a) {
     if constexpr (NF > 0 && NW >= 0) {
         // Parameter partials over the owned outputs n = a0 + o, o < n_own:
         //   dL/dh[l] = sum g_u[n] conj(x[n - (l - HF)]),  dL/dw[m] = sum Jbar[n] I[n - (m - NC)].
-        // Every thread accumulates all parameters over its outputs o = t + 256 q, then
-        // the 256 sums of each parameter are added through LDS in a fixed order.
+        // Every thread accumulates all parameters over its FR outputs, then the 256
+        // sums of each parameter are added through LDS in a fixed order.
         constexpr int NWC = NW;
         constexpr int W = NWC + 2 * NF;
         float acc[W];
@@ -368,21 +380,24 @@ __global__ __launch_bounds__(FT_THREADS) void fir_adjoint_kernel(FirArgs a) {
             }
         }
         // x, u and g_z are no longer read: their LDS holds the reduction, 16 parameters
-        // at a time ([16][256] per-thread sums, then [16][16] partial sums)
+        // at a time ([16][256] per-thread sums in rows of RS floats, then [16][16] partial
+        // sums).  Thread (k, seg) adds the sums of threads seg + 16 i: the 64 lanes of a
+        // wave then read 64 different banks.
+        constexpr int RS = FT_THREADS + 16;
         float* rb = reinterpret_cast<float*>(xs);
-        float* rb2 = rb + 16 * FT_THREADS;
+        float* rb2 = rb + 16 * RS;
 #pragma unroll
         for (int c0 = 0; c0 < W; c0 += 16) {
             __syncthreads();                   // previous readers of this LDS are done
 #pragma unroll
             for (int k = 0; k < 16; ++k)
-                if (c0 + k < W) rb[k * FT_THREADS + t] = acc[c0 + k];
+                if (c0 + k < W) rb[k * RS + t] = acc[c0 + k];
             __syncthreads();
             {
                 const int k = t >> 4, seg = t & 15;
                 float sum = 0.f;
 #pragma unroll
-                for (int i = 0; i < 16; ++i) sum += rb[k * FT_THREADS + seg * 16 + i];
+                for (int i = 0; i < 16; ++i) sum += rb[k * RS + seg + 16 * i];
                 rb2[k * 16 + seg] = sum;
             }
             __syncthreads();
@@ -438,16 +453,16 @@ __global__ __launch_bounds__(FT_THREADS) void fir_adjoint_kernel(FirArgs a) {
     }
 }
 
-inline size_t fir_fwd_smem(int npol, int nfir, int ntaps_or_0) {
+inline size_t fir_fwd_smem(int npol, int nfir, int ntaps_or_0, int ts) {
     const int HF = (nfir - 1) / 2, NC = ntaps_or_0 ? (ntaps_or_0 - 1) / 2 : 0;
-    const int nx = FT_TS + 2 * (HF + NC), nu = FT_TS + 2 * NC;
+    const int nx = ts + 2 * (HF + NC), nu = ts + 2 * NC;
     return (2 * FT_MAXH + 1) * 8 + (2 * FT_MAXC + 2) * 4 + (size_t)npol * nx * 8 + (size_t)npol * nu * 8 +
            (size_t)nu * 4;
 }
 
-inline size_t fir_adj_smem(int npol, int nfir, int ntaps_or_0) {
+inline size_t fir_adj_smem(int npol, int nfir, int ntaps_or_0, int ts) {
     const int HF = (nfir - 1) / 2, NC = ntaps_or_0 ? (ntaps_or_0 - 1) / 2 : 0;
-    const int nx = FT_TS + 4 * HF + 4 * NC, nu = FT_TS + 2 * HF + 4 * NC, nz = FT_TS + 2 * HF + 2 * NC;
+    const int nx = ts + 4 * HF + 4 * NC, nu = ts + 2 * HF + 4 * NC, nz = ts + 2 * HF + 2 * NC;
     return (2 * FT_MAXH + 1) * 8 + (2 * FT_MAXC + 2) * 4 + (size_t)npol * (nx + nu + nz) * 8 +
            (size_t)(nu + 2 * nz) * 4 + 4 * 64 * 2 * 4;
 }

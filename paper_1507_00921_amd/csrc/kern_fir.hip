@@ -71,12 +71,12 @@ static hipError_t launch_nf(bool adjoint, const FirArgs& a, size_t sm, hipStream
 }
 
 hipError_t launch_fir_step(int npol, const FirArgs& a, hipStream_t s) {
-    const size_t sm = fir_fwd_smem(npol, a.nfir, a.w ? a.ntaps : 0);
+    const size_t sm = fir_fwd_smem(npol, a.nfir, a.w ? a.ntaps : 0, a.ts);
     return npol == 1 ? launch_nf<1>(false, a, sm, s) : launch_nf<2>(false, a, sm, s);
 }
 
 hipError_t launch_fir_adjoint(int npol, const FirArgs& a, hipStream_t s) {
-    const size_t sm = fir_adj_smem(npol, a.nfir, a.w ? a.ntaps : 0);
+    const size_t sm = fir_adj_smem(npol, a.nfir, a.w ? a.ntaps : 0, a.ts);
     return npol == 1 ? launch_nf<1>(true, a, sm, s) : launch_nf<2>(true, a, sm, s);
 }
 
