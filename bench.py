@@ -306,7 +306,7 @@ def grad_workload(dbp, torch, reps=5):
     """Differentiation workload: 64 PM signals x 32768 samples at 3200 km, ESSFM 40 steps with
     per-step 9-tap c_k and 33-tap complex dispersion FIRs (least-squares fit of Eq. (1) over
     the signal band), loss = symbol MSE after the matched filter.  One training step =
-    forward + loss + backward through the autograd wrapper (checkpoint every 8 steps)."""
+    forward + loss + backward through the autograd wrapper (every step's input stored: 40 states, 1.25 GiB)."""
     batch, n, spans = 64, 32768, 40
     b2 = siggen.beta2_ps2_km()
     xs = np.stack([siggen.transmitted_field(3, i, 2, n, 0.0)[0] for i in range(batch)])
@@ -357,7 +357,7 @@ def grad_workload(dbp, torch, reps=5):
     torch.cuda.synchronize()
     ms_b = e0.elapsed_time(e1) / reps
     return {"workload": f"{batch}x2x{n}, 3200 km, ESSFM 40 steps, 9 taps + 33-tap FIR per step, "
-                        "checkpoint every 8 steps, symbol-MSE loss",
+                        "every step's input stored, symbol-MSE loss",
             "fwd_bwd_ms": round(ms_step, 3), "dbp_forward_ms": round(ms_f, 3),
             "dbp_backward_ms": round(ms_b, 3), "loss": round(float(loss.detach()), 5)}
 

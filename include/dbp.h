@@ -86,6 +86,7 @@ typedef enum dbp_precision {
 
 #define DBP_FLAG_FORWARD 0x1u   /* physical direction (forward propagation) */
 #define DBP_FLAG_WHOLE   0x2u   /* one circular block of the whole signal */
+#define DBP_FLAG_GRAD_SPARSE 0x4u  /* FIR gradient: checkpoint every 8th step only */
 
 typedef struct dbp_desc {
     int32_t n_pol;            /* 1 or 2 */
@@ -196,9 +197,12 @@ dbp_status dbp_backprop(dbp_plan_t plan, const void* in, void* out, const float*
  * and grad_fir (device complex64 [N_s][n_fir], FIR plans; may be NULL; must
  * be NULL for FFT-step plans, which have no FIR taps).  taps and fir
  * override the plan's parameters as in dbp_backprop.
- *   FIR plans: the forward pass runs once storing the state every 8 steps;
- *     each 8-step segment is then recomputed from its checkpoint and its
- *     adjoint steps run in reverse.
+ *   FIR plans: the forward pass runs once storing the input of every step,
+ *     then the adjoint steps run in reverse.  With DBP_FLAG_GRAD_SPARSE, or
+ *     when those N_s states would take more than 4 GiB, it stores every 8th
+ *     step's input instead and recomputes each 8-step segment from its
+ *     checkpoint before the segment's adjoint steps (less workspace, about
+ *     one more forward pass of time).
  *   FFT-step plans (overlap-and-save, Sec. III): the derivative of exactly the
  *     blocked cascade dbp_backprop computes (same Nb, O, k).  The passes run
  *     forward once storing every pass input; then each pass, in reverse,

@@ -118,7 +118,7 @@ dbp_status validate(const dbp_desc* d) {
         if (!finite(d->fir_band_thz) || d->fir_band_thz < 0) return DBP_ERR_INVALID_ARG;
     }
     if (d->precision < DBP_FP32 || d->precision > DBP_BF16X3) return DBP_ERR_INVALID_ARG;
-    if (d->flags & ~(DBP_FLAG_FORWARD | DBP_FLAG_WHOLE)) return DBP_ERR_INVALID_ARG;
+    if (d->flags & ~(DBP_FLAG_FORWARD | DBP_FLAG_WHOLE | DBP_FLAG_GRAD_SPARSE)) return DBP_ERR_INVALID_ARG;
     if (d->steps_per_pass < 0) return DBP_ERR_INVALID_ARG;
     if (d->spans_per_step < 0) return DBP_ERR_INVALID_ARG;
     if (d->spans_per_step > 1 && (d->steps_per_span != 1 || d->n_spans % d->spans_per_step != 0))
@@ -722,7 +722,11 @@ dbp_status dbp_plan_geometry(dbp_plan_t p, int32_t* block, int32_t* overlap, int
 
 namespace dbp {
 
+// FIR-plan gradients keep every step's input when those states fit in
+// kDenseCheckpointBytes (a small part of the device's HBM), else every
+// kCheckpointEvery-th and recompute the segments between them.
 static constexpr int kCheckpointEvery = 8;
+static constexpr size_t kDenseCheckpointBytes = size_t(4) << 30;
 
 // Time-domain geometry of a FIR-mode plan: tiles of the forward step and, of
 // another length, of its adjoint (the per-tile partials follow the adjoint's).
@@ -744,7 +748,9 @@ static FirGeo fir_geo(const Plan* p) {
     f.n_wg_fwd = f.n_tiles_fwd * p->desc.batch;
     f.nw = p->desc.method == DBP_ESSFM ? p->desc.n_taps : 0;
     f.width = f.nw + 2 * p->desc.n_fir;
-    f.seg = kCheckpointEvery;
+    const bool dense = !(p->desc.flags & DBP_FLAG_GRAD_SPARSE) &&
+                       (size_t)p->geo.n_steps * p->state_bytes() <= kDenseCheckpointBytes;
+    f.seg = dense ? 1 : kCheckpointEvery;
     f.n_ckpt = (p->geo.n_steps + f.seg - 1) / f.seg;
     return f;
 }
@@ -1009,7 +1015,8 @@ dbp_status dbp_backprop_grad(dbp_plan_t p, const void* in, const float* taps, co
     float* part = (float*)(w + (size_t)(b_grad + 2) * state);
     auto ckpt = [&](int c) { return c == 0 ? (const float2*)in : (const float2*)buf(c - 1); };
 
-    // forward with a checkpoint every f.seg steps (the state after the last step is not needed)
+    // forward with a checkpoint every f.seg steps (1: every step's input; the state after the
+    // last step is not needed)
     {
         const float2* src = (const float2*)in;
         int tog = 0;

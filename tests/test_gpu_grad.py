@@ -52,9 +52,9 @@ def setup(seed, batch, n_pol, n, n_spans, essfm=True, n_fir=33, perturb=0.02):
     return xs, fir, taps, steps
 
 
-def make_plan(dbp, n, n_spans, batch, n_pol, taps, fir):
+def make_plan(dbp, n, n_spans, batch, n_pol, taps, fir, **kw):
     return dbp.plan(n, n_spans, 1, batch=batch, n_pol=n_pol, taps=None if taps is None else taps[0],
-                    linear=dbp.LINEAR_FIR, fir=fir[0], beta2_ps2_km=B2)
+                    linear=dbp.LINEAR_FIR, fir=fir[0], beta2_ps2_km=B2, **kw)
 
 
 def dev(a, dtype=None):
@@ -86,13 +86,16 @@ def test_planner_designed_fir_matches_oracle(dbp):
     assert rel_l2(a.backprop(x).cpu().numpy(), b.backprop(x).cpu().numpy()) <= 1e-6
 
 
-@pytest.mark.parametrize("essfm,n_spans,n", [(True, 20, 3000), (False, 9, 2100), (True, 1, 1500)])
-def test_fir_gradient_parity(dbp, essfm, n_spans, n):
+@pytest.mark.parametrize("essfm,n_spans,n,sparse", [(True, 20, 3000, False), (False, 9, 2100, False),
+                                                    (True, 1, 1500, False), (True, 20, 3000, True),
+                                                    (False, 9, 2100, True)])
+def test_fir_gradient_parity(dbp, essfm, n_spans, n, sparse):
+    # sparse: checkpoints every 8 steps and recomputed segments (20 steps: 8 + 8 + 4)
     batch = 2
     xs, fir, taps, steps = setup(3, batch, 2, n, n_spans, essfm)
     g = np.random.default_rng(7)
     gout = (g.standard_normal(xs.shape) + 1j * g.standard_normal(xs.shape)).astype(np.complex64)
-    p = make_plan(dbp, n, n_spans, batch, 2, taps, fir)
+    p = make_plan(dbp, n, n_spans, batch, 2, taps, fir, grad_sparse=sparse)
     gx, gt, gf = p.backprop_grad(dev(xs, np.complex64), dev(gout), taps=None if taps is None else dev(taps),
                                  fir=dev(fir))
     gx = gx.cpu().numpy().astype(np.complex128)
@@ -116,6 +119,25 @@ def test_fir_gradient_parity(dbp, essfm, n_spans, n):
         assert ew <= 1e-4
     else:
         assert gt is None
+
+
+def test_dense_and_sparse_checkpoints_give_identical_gradients(dbp):
+    # the recomputed segment states are the stored ones bit for bit, so both schedules
+    # return the same gradients exactly; the dense one needs more workspace
+    n, n_spans, batch = 2500, 19, 2
+    xs, fir, taps, _ = setup(5, batch, 2, n, n_spans, True)
+    g = np.random.default_rng(8)
+    gout = dev((g.standard_normal(xs.shape) + 1j * g.standard_normal(xs.shape)).astype(np.complex64))
+    x = dev(xs, np.complex64)
+    out = []
+    for sparse in (False, True):
+        p = make_plan(dbp, n, n_spans, batch, 2, taps, fir, grad_sparse=sparse)
+        out.append((p.workspace_size(grad=True),
+                    [t.cpu() for t in p.backprop_grad(x, gout, taps=dev(taps), fir=dev(fir))]))
+    (ws_dense, gd), (ws_sparse, gs) = out
+    assert ws_dense > ws_sparse
+    for a, b in zip(gd, gs):
+        assert torch.equal(a, b)
 
 
 def test_autograd_function_with_symbol_loss(dbp):
