@@ -516,6 +516,50 @@ def cpu_baseline_all_cores(rx_np, taps, k, budget_s=10.0):
                       f"{reps} DBPs in {wall:.1f} s wall"}
 
 
+def cpu_oracle_context(rx_np):
+    """The FP64 oracle (one core) on bounded samples of the other workloads, each scaled to
+    its whole job: SSFM-20 on the headline field (40 of its 800 steps), the 1x16384 whole-signal
+    case, the differentiation workload (the FP64 adjoint of 1 of its 64 signals) and the
+    precision workload (2 of its 800 SSFM steps on 2x4194304).  Context beside the GPU
+    figures, about 8 s of host work."""
+    from oracle import adjoint as A
+    from oracle import dbp_ref as R
+    b2, fs = siggen.beta2_ps2_km(), siggen.FS_THZ
+    out = {}
+    ssfm = R.schedule(SPANS, 80.0, 20, b2, siggen.GAMMA_W_KM, siggen.ALPHA_DB_KM)
+    t0 = time.perf_counter()
+    R.run_blocked(rx_np, ssfm[:40], fs, BLOCK, OVERLAP, 40)
+    el = (time.perf_counter() - t0) * len(ssfm) / 40
+    out["ssfm20_headline"] = {"msamples_per_s": round(N / el / 1e6, 5), "s_per_dbp": round(el, 1),
+                              "sample": "40 of 800 steps on the full 2x262144 field, scaled"}
+    x0 = siggen.transmitted_field(4, 0, 1, 16384, 0.0)[0]
+    st0 = R.schedule(4, 80.0, 1, b2, siggen.GAMMA_W_KM, siggen.ALPHA_DB_KM)
+    t0 = time.perf_counter()
+    for _ in range(20):
+        R.run_whole(x0, st0, fs)
+    out["whole_1x16384_ssfm4"] = {"us_per_dbp": round((time.perf_counter() - t0) / 20 * 1e6, 1), "sample": "20 runs"}
+    base = R.schedule(SPANS, 80.0, 1, b2, siggen.GAMMA_W_KM, siggen.ALPHA_DB_KM)
+    h0 = R.ls_fir_taps(33, base[0].b, fs, 0.0154)
+    w = np.zeros(9)
+    w[4] = 1.0
+    steps = [R.Step(b=st.b, phi=st.phi, w=w, h=h0) for st in base]
+    x3 = siggen.transmitted_field(3, 0, 2, 32768, 0.0)[0]
+    g3 = np.random.default_rng(2).standard_normal(x3.shape) + 0j
+    t0 = time.perf_counter()
+    A.grad_whole(x3, steps, fs, g3)
+    el = (time.perf_counter() - t0) * 64
+    out["differentiation_64x2x32768"] = {"fwd_bwd_ms": round(el * 1e3, 0),
+                                         "sample": "FP64 adjoint (forward + reverse) of 1 of the 64 signals, x64"}
+    x4 = np.random.default_rng(3).standard_normal((2, 4194304)) * 0.03 + 0j
+    t0 = time.perf_counter()
+    R.run_blocked(x4, ssfm[:2], fs, BLOCK, OVERLAP, 2)
+    el = (time.perf_counter() - t0) * len(ssfm) / 2
+    out["precision_2x4194304_ssfm800"] = {"msamples_per_s": round(4194304 / el / 1e6, 5), "s_per_dbp": round(el, 0),
+                                          "sample": "2 of 800 steps on the full field, scaled"}
+    out["cores"] = 1
+    return out
+
+
 KERNEL_SOURCES = ["fft.hpp", "wave_fft.hpp", "phase.hpp", "step_kernel.hpp", "registry.hpp", "kern_1024.hip"]
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "pass_kernel_1024_essfm_2x262144_traffic.md")
 
@@ -876,6 +920,9 @@ def main():
         allc = cpu_baseline_all_cores(rx.cpu().numpy().reshape(2, N).astype(np.complex128), taps, essfm.steps_per_pass)
         log("oracle on all host cores " + json.dumps(allc))
         res["config"]["cpu_oracle_all_cores"] = allc
+        ctx = cpu_oracle_context(rx.cpu().numpy().reshape(2, N).astype(np.complex128))
+        log("oracle on the other workloads " + json.dumps(ctx))
+        res["config"]["cpu_oracle_other_workloads"] = ctx
     print(json.dumps(res), flush=True)
 
 
