@@ -233,3 +233,57 @@ def test_polarization_split_blocks(dbp, monkeypatch, force, nb, taps):
     err = rel_l2(y, ref)
     print(f"{p.kernel}: rel L2 {err:.3e}")
     assert err <= 1e-5
+
+
+@pytest.mark.parametrize("essfm,n_pol", [(True, 2), (False, 2), (False, 1)])
+def test_dispersion_free_cascade_has_the_closed_form(dbp, essfm, n_pol):
+    # beta2 = 0: the linear substep is the identity and the phase rotation keeps the total
+    # intensity I, so the 40 steps together multiply each polarization by exp(-j Phi J), Phi the
+    # sum of the steps' phi (Eqs. (2)-(3)) and J = w (*) I of the input, circular: a closed
+    # form independent of the oracle.  Headline geometry, 11.7 blocks (ragged last block).
+    n = 9000
+    r = np.random.default_rng(11)
+    x = ((r.standard_normal((n_pol, n)) + 1j * r.standard_normal((n_pol, n))) * 0.03).astype(np.complex64)
+    kw = dict(taps=TAPS9) if essfm else {}
+    p = dbp.plan(n, 40, 1, n_pol=n_pol, beta2_ps2_km=0.0, block=1024, overlap=256, steps_per_pass=5, **kw)
+    y = _from_gpu(p.backprop(_to_gpu(x)), (n_pol, n))
+    _, phi = dbp.schedule(dbp.make_desc(n, 40, 1, n_pol=n_pol, beta2_ps2_km=0.0, **kw))
+    xi = x.astype(np.complex128)
+    inten = np.sum(xi.real ** 2 + xi.imag ** 2, axis=0)
+    if essfm:
+        w = np.asarray(TAPS9, dtype=np.float32).astype(np.float64)
+        nc = len(w) // 2
+        j = sum(w[m] * np.roll(inten, m - nc) for m in range(len(w)))
+    else:
+        j = inten
+    total = float(np.sum(phi) * np.max(j))
+    ref = xi * np.exp(-1j * np.sum(phi) * j)
+    err = rel_l2(y, ref)
+    # tolerance from the arithmetic: 40 FP32 FFT round trips let the intensity drift by about
+    # 1e-6 (numpy's complex64 FFT: 1.3e-6 over 40 round trips of these blocks), and the
+    # accumulated phase multiplies that drift by Phi J (up to 28 rad here, about 0.7 rad per
+    # step, past the pi/4 of the quadrant reduction)
+    tol = 2e-6 * (1.0 + abs(total))
+    print(f"beta2 = 0, essfm={essfm}, n_pol={n_pol}: peak total phase {total:.2f} rad, rel L2 {err:.2e} "
+          f"(tolerance {tol:.1e})")
+    assert 1.0 < abs(total) < 50.0
+    assert err <= tol
+
+
+def test_linear_cascade_is_the_whole_link_dispersion(dbp):
+    # gamma = 0, one circular block: the 10 linear substeps compose to the single all-pass
+    # response of Eq. (1) for the summed b, applied with numpy's FFT (a closed form; the
+    # oracle is not involved), and the summed b is the link's beta2 L
+    n, spans, sps = 8192, 5, 2
+    x = siggen.transmitted_field(1, 61, 2, n, 0.0)[0].astype(np.complex64)
+    p = dbp.plan(n, spans, sps, whole=True, gamma_w_km=0.0, beta2_ps2_km=B2)
+    y = _from_gpu(p.backprop(_to_gpu(x)), (2, n))
+    b, _ = dbp.schedule(dbp.make_desc(n, spans, sps, whole=True, gamma_w_km=0.0, beta2_ps2_km=B2))
+    assert len(b) == spans * sps
+    assert abs(abs(np.sum(b)) - abs(B2) * spans * 80.0) <= 1e-9 * abs(B2) * spans * 80.0
+    f = np.fft.fftfreq(n, d=1.0 / FS)
+    ref = np.fft.ifft(np.fft.fft(x.astype(np.complex128), axis=-1) * np.exp(-2j * np.pi ** 2 * np.sum(b) * f * f),
+                      axis=-1)
+    err = rel_l2(y, ref)
+    print(f"gamma = 0 whole-link dispersion: rel L2 {err:.2e}")
+    assert err <= 1e-5
