@@ -315,7 +315,8 @@ typedef struct {
  * n_out / 2 symbols).  Allocates its tables and all scratch of the later calls
  * on the current device (synchronously; no later call allocates); *out is NULL
  * on error (DBP_ERR_INVALID_ARG for a bad desc or size).  Calls on one dsp share
- * its scratch: issue them in order on one stream. */
+ * its scratch: issue them in order on one stream, with the device current that
+ * was current at create (else DBP_ERR_INVALID_ARG, no device work). */
 dbp_status dbp_dsp_create(const dbp_dsp_desc* desc, int64_t n_in, dbp_dsp_t* out);
 
 /* Sizes: n_out samples per polarization after resampling, n_sym symbols.  Either

@@ -335,6 +335,7 @@ struct dbp_dsp_s {
     float2* gpart = nullptr;       // normal-equation chunk sums [ceil(n_sym / GRAM_CH)][E]
     double2* gsum = nullptr;       // their FP64 totals [E]
     void* mem = nullptr;
+    int device = -1;               // the device current at create, which owns mem
 };
 
 namespace {
@@ -397,6 +398,12 @@ bool solve(std::vector<std::complex<double>>& A, std::vector<std::complex<double
 
 int grid_of(long long n, int per) { return (int)((n + per - 1) / per); }
 
+// The handle's memory belongs to the device current at create; calls need it current.
+bool on_device(const dbp_dsp_s* s) {
+    int dev = -1;
+    return hipGetDevice(&dev) == hipSuccess && dev == s->device;
+}
+
 }  // namespace
 
 extern "C" {
@@ -405,8 +412,11 @@ dbp_status dbp_dsp_create(const dbp_dsp_desc* desc, int64_t n_in, dbp_dsp_t* out
     if (!out) return DBP_ERR_INVALID_ARG;
     *out = nullptr;
     if (!valid(desc, n_in)) return DBP_ERR_INVALID_ARG;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return DBP_ERR_HIP;
     dbp_dsp_s* s = new (std::nothrow) dbp_dsp_s();
     if (!s) return DBP_ERR_OOM;
+    s->device = dev;
     s->d = *desc;
     s->n_in = n_in;
     s->n_out = n_in * desc->up / desc->down;
@@ -465,6 +475,7 @@ dbp_status dbp_dsp_info(dbp_dsp_t s, int64_t* n_out, int64_t* n_sym) {
 
 dbp_status dbp_dsp_resample(dbp_dsp_t s, const void* in, void* out, void* stream) {
     if (!s || !in || !out) return DBP_ERR_INVALID_ARG;
+    if (!on_device(s)) return DBP_ERR_INVALID_ARG;
     const char* a = (const char*)in;
     const char* b = (const char*)out;
     if (a < b + 2 * s->n_out * sizeof(float2) && b < a + 2 * s->n_in * sizeof(float2)) return DBP_ERR_INVALID_ARG;
@@ -477,6 +488,7 @@ dbp_status dbp_dsp_resample(dbp_dsp_t s, const void* in, void* out, void* stream
 
 dbp_status dbp_dsp_train(dbp_dsp_t s, const void* x2, const void* sym, int64_t n_train, void* taps, void* stream) {
     if (!s || !x2 || !sym || !taps || n_train < 1 || n_train > s->n_sym) return DBP_ERR_INVALID_ARG;
+    if (!on_device(s)) return DBP_ERR_INVALID_ARG;
     const int N = s->d.eq_taps, M = 2 * N, E = M * M + 2 * M;
     const int n_chunks = grid_of(n_train, GRAM_CH);
     hipStream_t st = (hipStream_t)stream;
@@ -508,6 +520,7 @@ dbp_status dbp_dsp_train(dbp_dsp_t s, const void* x2, const void* sym, int64_t n
 
 dbp_status dbp_dsp_equalize(dbp_dsp_t s, const void* x2, const void* taps, void* y, void* stream) {
     if (!s || !x2 || !taps || !y) return DBP_ERR_INVALID_ARG;
+    if (!on_device(s)) return DBP_ERR_INVALID_ARG;
     const char* a = (const char*)x2;
     const char* b = (const char*)y;
     if (a < b + 2 * s->n_sym * sizeof(float2) && b < a + 2 * s->n_out * sizeof(float2)) return DBP_ERR_INVALID_ARG;
@@ -520,6 +533,7 @@ dbp_status dbp_dsp_equalize(dbp_dsp_t s, const void* x2, const void* taps, void*
 dbp_status dbp_dsp_cpr(dbp_dsp_t s, const void* y, const void* sym, int64_t n_ref, void* z, int64_t* bit_errors,
                        void* stream) {
     if (!s || !y || !z || n_ref < 0 || n_ref > s->n_sym || (n_ref > 0 && !sym)) return DBP_ERR_INVALID_ARG;
+    if (!on_device(s)) return DBP_ERR_INVALID_ARG;
     const char* a = (const char*)y;
     const char* b = (const char*)z;
     const size_t bytes = 2 * s->n_sym * sizeof(float2);
