@@ -287,3 +287,37 @@ def test_linear_cascade_is_the_whole_link_dispersion(dbp):
     err = rel_l2(y, ref)
     print(f"gamma = 0 whole-link dispersion: rel L2 {err:.2e}")
     assert err <= 1e-5
+
+
+def test_essfm_with_a_unit_filter_is_ssfm(dbp):
+    # w = e_Nc makes J = I exactly (Eq. (3) reduces to Eq. (2)), so the ESSFM kernel must give
+    # the SSFM kernel's output: the filter's centre index and every other tap are pinned (a tap
+    # off by one sample moves the result by ~1e-2).  Not bitwise: at 26 blocks SSFM runs on the
+    # polarization-split kernel, whose roundings differ, and the cascade amplifies them.
+    n = 20000
+    x, _ = received(1, 70, 2, n, 2.0, 40, 1)
+    w = np.zeros(9, np.float32)
+    w[4] = 1.0
+    geo = dict(block=1024, overlap=256, steps_per_pass=5, beta2_ps2_km=B2)
+    ye = _from_gpu(dbp.plan(n, 40, 1, taps=w, **geo).backprop(_to_gpu(x)), (2, n))
+    ys = _from_gpu(dbp.plan(n, 40, 1, **geo).backprop(_to_gpu(x)), (2, n))
+    err = rel_l2(ye, ys)
+    print(f"ESSFM with w = e_4 against SSFM: rel L2 {err:.2e}")
+    assert err <= 1e-5
+
+
+def test_essfm_with_a_one_sample_shift_filter_matches_oracle(dbp):
+    # asymmetric taps (w = e_{Nc+1}: J[n] = I[n - 1]) pin the filter's direction on the GPU
+    # against the oracle's Eq. (3) convention; symmetric taps cannot tell the two apart
+    n = 20000
+    x, _ = received(1, 71, 2, n, 2.0, 40, 1)
+    w = np.zeros(9, np.float32)
+    w[5] = 1.0
+    p = dbp.plan(n, 40, 1, taps=w, block=1024, overlap=256, steps_per_pass=5, beta2_ps2_km=B2)
+    y = _from_gpu(p.backprop(_to_gpu(x)), (2, n))
+    ref = _oracle(x, p, 40, 1, taps=w)
+    err = rel_l2(y, ref)
+    mirrored = _oracle(x, p, 40, 1, taps=w[::-1].copy())
+    print(f"one-sample-shift taps: rel L2 {err:.2e} (against the mirrored filter {rel_l2(y, mirrored):.2e})")
+    assert err <= 1e-5
+    assert rel_l2(y, mirrored) > 100 * err
