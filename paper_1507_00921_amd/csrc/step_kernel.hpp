@@ -294,8 +294,23 @@ __device__ __forceinline__ void run_steps(float2 (&v)[NPOL][E], const BlockJob& 
     }
 }
 
+// Block outputs of a launch per pass are stored with the non-temporal hint: the
+// output is read again only by the next launch, after every block of this one,
+// so there is nothing to gain from keeping it in the caches.  The persistent
+// batch kernel (NTS = false) reads a block's output back as soon as the next
+// pass's items that need it are dequeued, and keeps the ordinary policy.
+template <bool NTS = true>
+__device__ __forceinline__ void store_out(float2* p, float2 v) {
+    if constexpr (NTS) {
+        typedef float f2v __attribute__((ext_vector_type(2)));
+        __builtin_nontemporal_store(f2v{v.x, v.y}, reinterpret_cast<f2v*>(p));
+    } else {
+        *p = v;
+    }
+}
+
 // Keep the centre V samples of the block.
-template <int NB, int E, int NPOL>
+template <int NB, int E, int NPOL, bool NTS = true>
 __device__ __forceinline__ void store_block(const float2 (&v)[NPOL][E], const BlockJob& a, int t) {
     constexpr int T = NB / E;
     const long long L = a.L;
@@ -305,7 +320,7 @@ __device__ __forceinline__ void store_block(const float2 (&v)[NPOL][E], const Bl
         const long long o = (long long)a.blk * a.V + pos - a.halo;
         if (pos >= a.halo && pos < a.halo + a.V && o < L) {
 #pragma unroll
-            for (int p = 0; p < NPOL; ++p) a.dst[p * L + o] = v[p][q];
+            for (int p = 0; p < NPOL; ++p) store_out<NTS>(a.dst + p * L + o, v[p][q]);
         }
     }
 }
@@ -313,7 +328,8 @@ __device__ __forceinline__ void store_block(const float2 (&v)[NPOL][E], const Bl
 // The same through a buffer resource spanning the signal (NPOL * L * 8 bytes
 // < 2^31): lanes outside the centre get an offset past the resource, which
 // the hardware's range check discards, so every lane issues the same stores
-// and the count of outstanding memory operations is the same on every path.
+// and the count of outstanding memory operations is the same on every path
+// (non-temporal, as store_out: cache-policy bit 1).
 template <int NB, int E, int NPOL>
 __device__ __forceinline__ void store_block_rsrc(const float2 (&v)[NPOL][E], const BlockJob& a, int t) {
     typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
@@ -330,18 +346,18 @@ __device__ __forceinline__ void store_block_rsrc(const float2 (&v)[NPOL][E], con
 #pragma unroll
         for (int p = 0; p < NPOL; ++p)
             __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v[p][q]), r,
-                                                  off + (unsigned)(p * L * (long long)sizeof(float2)), 0, 0);
+                                                  off + (unsigned)(p * L * (long long)sizeof(float2)), 0, 2);
     }
 }
 
-template <int NB, int E, int NPOL, bool PHASE64, int NT>
+template <int NB, int E, int NPOL, bool PHASE64, int NT, bool NTS = true>
 __device__ __forceinline__ void process_block(const BlockJob& a, const TwReg<NB, E>& twr,
                                               BlockSmem<NB, E, NPOL, NT>& sm) {
     const int t = threadIdx.x;
     float2 v[NPOL][E];
     load_block<NB, E, NPOL>(v, a.src, a.L, (long long)a.blk * a.V - a.halo, t);
     run_steps<NB, E, NPOL, PHASE64, NT>(v, a, twr, sm, nullptr);
-    store_block<NB, E, NPOL>(v, a, t);
+    store_block<NB, E, NPOL, NTS>(v, a, t);
     // before the LDS is reused by a following job, every wave is done with it
     if constexpr (NB / E > 64) __syncthreads();
 }
@@ -456,7 +472,7 @@ __device__ __forceinline__ void process_block_split(const BlockJob& a, const TwR
     for (int q = 0; q < E; ++q) {
         const int pos = t + T * q;
         const long long o = (long long)a.blk * a.V + pos - a.halo;
-        if (pos >= a.halo && pos < a.halo + a.V && o < L) a.dst[grp * L + o] = v[0][q];
+        if (pos >= a.halo && pos < a.halo + a.V && o < L) store_out(a.dst + grp * L + o, v[0][q]);
     }
 }
 
