@@ -143,7 +143,7 @@ __global__ __launch_bounds__(NB / E) void dbp_batch_kernel(BatchArgs a) {
             const int b1 = min(sg.n_blk, (grp + 1) * sg.grp);
             for (int b = grp * sg.grp; b < b1; ++b) {
                 j.blk = b;
-                process_block<NB, E, NPOL, PHASE64, NT, false>(j, twr, sm);
+                process_block<NB, E, NPOL, PHASE64, NT>(j, twr, sm);
             }
         }
         // every thread's stores are released at agent scope (one L2 writeback) before

@@ -726,6 +726,8 @@ namespace dbp {
 // kDenseCheckpointBytes (a small part of the device's HBM), else every
 // kCheckpointEvery-th and recompute the segments between them.
 static constexpr int kCheckpointEvery = 8;
+// States above this size are written with the non-temporal hint by the pass kernels.
+static constexpr size_t kStreamStoreBytes = size_t(128) << 20;
 static constexpr size_t kDenseCheckpointBytes = size_t(4) << 30;
 
 // Time-domain geometry of a FIR-mode plan: tiles of the forward step and, of
@@ -960,6 +962,9 @@ dbp_status dbp_backprop(dbp_plan_t p, const void* in, void* out, const float* ta
     a.taps = p->desc.method == DBP_ESSFM ? (taps ? taps : p->d_taps) : nullptr;
     a.ntaps = p->desc.method == DBP_ESSFM ? p->desc.n_taps : 1;
     a.frag = p->d_frag;
+    // a pass reads one state and writes another: beyond half the 256 MB Infinity Cache per
+    // state the output cannot stay cached until the next pass reads it, and is streamed out
+    a.nt_store = state > kStreamStoreBytes ? 1 : 0;
     const int grid = p->launch_stream ? p->stream_grid
                    : p->grid_cap > 0  ? std::min(p->grid_cap, a.n_wg)
                                       : a.n_wg;

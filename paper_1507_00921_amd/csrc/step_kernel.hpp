@@ -34,6 +34,7 @@ struct PassArgs {
     const float* taps;      // [N_s][ntaps] or nullptr (SSFM: J = I)
     int ntaps;              // odd
     const void* frag;       // split-precision variant: BF16 DFT constant fragments
+    int nt_store;           // 1: store block outputs with the non-temporal hint
 };
 
 // Workgroups are dealt round-robin to the 8 XCDs; give each XCD a contiguous
@@ -134,6 +135,7 @@ struct BlockJob {
     const float2* H;
     const float* taps;      // [N_s][ntaps] of this signal, nullptr for SSFM
     int ntaps;
+    bool nt = false;        // outputs stored with the non-temporal hint
 };
 
 // Shared-memory footprint of the block routine.
@@ -294,14 +296,13 @@ __device__ __forceinline__ void run_steps(float2 (&v)[NPOL][E], const BlockJob& 
     }
 }
 
-// Block outputs of a launch per pass are stored with the non-temporal hint: the
-// output is read again only by the next launch, after every block of this one,
-// so there is nothing to gain from keeping it in the caches.  The persistent
-// batch kernel (NTS = false) reads a block's output back as soon as the next
-// pass's items that need it are dequeued, and keeps the ordinary policy.
-template <bool NTS = true>
-__device__ __forceinline__ void store_out(float2* p, float2 v) {
-    if constexpr (NTS) {
+// Block outputs are stored with the non-temporal hint when the host asks for it
+// (states larger than half the Infinity Cache, where a pass's output cannot stay
+// cached until the next launch reads it); otherwise with the ordinary policy,
+// which lets the next launch, or the persistent batch kernel's next-pass items,
+// read them from the caches.  The flag is uniform across the launch.
+__device__ __forceinline__ void store_out(float2* p, float2 v, bool nt) {
+    if (nt) {
         typedef float f2v __attribute__((ext_vector_type(2)));
         __builtin_nontemporal_store(f2v{v.x, v.y}, reinterpret_cast<f2v*>(p));
     } else {
@@ -310,7 +311,7 @@ __device__ __forceinline__ void store_out(float2* p, float2 v) {
 }
 
 // Keep the centre V samples of the block.
-template <int NB, int E, int NPOL, bool NTS = true>
+template <int NB, int E, int NPOL>
 __device__ __forceinline__ void store_block(const float2 (&v)[NPOL][E], const BlockJob& a, int t) {
     constexpr int T = NB / E;
     const long long L = a.L;
@@ -320,7 +321,7 @@ __device__ __forceinline__ void store_block(const float2 (&v)[NPOL][E], const Bl
         const long long o = (long long)a.blk * a.V + pos - a.halo;
         if (pos >= a.halo && pos < a.halo + a.V && o < L) {
 #pragma unroll
-            for (int p = 0; p < NPOL; ++p) store_out<NTS>(a.dst + p * L + o, v[p][q]);
+            for (int p = 0; p < NPOL; ++p) store_out(a.dst + p * L + o, v[p][q], a.nt);
         }
     }
 }
@@ -329,7 +330,7 @@ __device__ __forceinline__ void store_block(const float2 (&v)[NPOL][E], const Bl
 // < 2^31): lanes outside the centre get an offset past the resource, which
 // the hardware's range check discards, so every lane issues the same stores
 // and the count of outstanding memory operations is the same on every path
-// (non-temporal, as store_out: cache-policy bit 1).
+// (with the cache policy store_out picks: bit 1 is non-temporal).
 template <int NB, int E, int NPOL>
 __device__ __forceinline__ void store_block_rsrc(const float2 (&v)[NPOL][E], const BlockJob& a, int t) {
     typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
@@ -344,20 +345,24 @@ __device__ __forceinline__ void store_block_rsrc(const float2 (&v)[NPOL][E], con
         const bool ok = pos >= a.halo && pos < a.halo + a.V && o < L;
         const unsigned off = ok ? (unsigned)o * (unsigned)sizeof(float2) : 0x80000000u;
 #pragma unroll
-        for (int p = 0; p < NPOL; ++p)
-            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v[p][q]), r,
-                                                  off + (unsigned)(p * L * (long long)sizeof(float2)), 0, 2);
+        for (int p = 0; p < NPOL; ++p) {
+            const unsigned at = off + (unsigned)(p * L * (long long)sizeof(float2));
+            if (a.nt)
+                __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v[p][q]), r, at, 0, 2);
+            else
+                __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v[p][q]), r, at, 0, 0);
+        }
     }
 }
 
-template <int NB, int E, int NPOL, bool PHASE64, int NT, bool NTS = true>
+template <int NB, int E, int NPOL, bool PHASE64, int NT>
 __device__ __forceinline__ void process_block(const BlockJob& a, const TwReg<NB, E>& twr,
                                               BlockSmem<NB, E, NPOL, NT>& sm) {
     const int t = threadIdx.x;
     float2 v[NPOL][E];
     load_block<NB, E, NPOL>(v, a.src, a.L, (long long)a.blk * a.V - a.halo, t);
     run_steps<NB, E, NPOL, PHASE64, NT>(v, a, twr, sm, nullptr);
-    store_block<NB, E, NPOL, NTS>(v, a, t);
+    store_block<NB, E, NPOL>(v, a, t);
     // before the LDS is reused by a following job, every wave is done with it
     if constexpr (NB / E > 64) __syncthreads();
 }
@@ -472,7 +477,7 @@ __device__ __forceinline__ void process_block_split(const BlockJob& a, const TwR
     for (int q = 0; q < E; ++q) {
         const int pos = t + T * q;
         const long long o = (long long)a.blk * a.V + pos - a.halo;
-        if (pos >= a.halo && pos < a.halo + a.V && o < L) store_out(a.dst + grp * L + o, v[0][q]);
+        if (pos >= a.halo && pos < a.halo + a.V && o < L) store_out(a.dst + grp * L + o, v[0][q], a.nt);
     }
 }
 
@@ -496,6 +501,7 @@ __global__ __launch_bounds__(2 * NB / E) void dbp_pass_kernel_split(PassArgs a) 
     j.H = a.H;
     j.taps = a.taps;
     j.ntaps = a.ntaps;
+    j.nt = a.nt_store != 0;
     process_block_split<NB, E, PHASE64, NT>(j, twr, sm);
 }
 
@@ -519,6 +525,7 @@ __global__ __launch_bounds__(NB / E) void dbp_pass_kernel(PassArgs a) {
     j.H = a.H;
     j.taps = a.taps;
     j.ntaps = a.ntaps;
+    j.nt = a.nt_store != 0;
     process_block<NB, E, NPOL, PHASE64, NT>(j, twr, sm);
 }
 
@@ -579,6 +586,7 @@ __global__ __launch_bounds__(NB / E) void dbp_stream_kernel(PassArgs a) {
         j.H = a.H;
         j.taps = a.taps;
         j.ntaps = a.ntaps;
+        j.nt = a.nt_store != 0;
         run_steps<NB, E, NPOL, PHASE64, NT, true>(v, j, twr, sm.b, sm.h);
         store_block_rsrc<NB, E, NPOL>(v, j, t);
         // the next block's exchanges reuse the LDS: every wave is done with it
