@@ -444,17 +444,18 @@ using namespace dbp;
 
 namespace dbp {
 
-// Streaming twin of the plan's pass kernel: used when the launch has at least
-// two blocks per resident workgroup slot (so that prefetching the next block
-// has something to overlap), every step uses one dispersion table and a
-// signal fits one buffer resource.
-// DBP_STREAM=0 disables it, DBP_STREAM=1 uses it whenever a twin exists;
-// DBP_STREAM_GRID=n (a multiple of 8) sets its grid.
+// Streaming twin of the plan's pass kernel (resident grid, next block
+// prefetched), used on request: DBP_STREAM=1 selects it whenever a twin exists,
+// every step uses one dispersion table and a signal fits one buffer resource;
+// DBP_STREAM_GRID=n (a multiple of 8) sets its grid.  With the non-temporal
+// output stores of large states, the per-block kernel is the faster of the two
+// at one step per pass on the 64-signal field (by 3-7 %; before those stores the
+// two were within noise there and the twin was the default for k = 1).
 static dbp_status choose_stream(Plan* p, const KernelEntry* ke, int n_tables) {
     if (!ke || !ke->sfn || !ke->socc || n_tables != 1) return DBP_OK;
     if ((long long)p->desc.n_pol * p->desc.n_samples * (long long)sizeof(float2) >= (1LL << 31)) return DBP_OK;
     const char* on = std::getenv("DBP_STREAM");
-    if (on && std::atoi(on) == 0) return DBP_OK;
+    if (!(on && std::atoi(on) == 1)) return DBP_OK;
     int cu = 0;
     if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess || cu < 1)
         return DBP_ERR_HIP;
@@ -466,11 +467,6 @@ static dbp_status choose_stream(Plan* p, const KernelEntry* ke, int n_tables) {
         if (n >= 8 && n % 8 == 0) grid = n;
     }
     if (grid < 8) return DBP_OK;
-    const long long v = p->geo.block - p->geo.overlap;
-    const long long n_wg = (p->desc.n_samples + v - 1) / v * p->desc.batch;
-    // measured on the 64-signal field: the streaming kernel is within noise of the per-block
-    // kernel at one step per pass and 4-7 % slower at two, so it is chosen for k = 1 only
-    if (!(on && std::atoi(on) == 1) && (n_wg < 2LL * grid || p->geo.k > 1)) return DBP_OK;
     p->launch_stream = (void*)ke->sfn;
     p->stream_grid = grid;
     std::snprintf(p->kernel_name, sizeof(p->kernel_name), "dbp_stream_kernel<%d, %d, %d, %s, %d>", ke->nb, ke->e,

@@ -84,23 +84,23 @@ def test_stream_matches_block_kernel_and_oracle(dbp, monkeypatch, block, overlap
         assert err <= 1e-5
 
 
-def test_stream_chosen_for_large_working_set(dbp):
+def test_stream_kernel_on_request_for_large_working_set(dbp):
     # the headline field replicated 64 times (256 MiB per state) on 512-point blocks: the
-    # planner picks the streaming kernel by itself; its output equals the per-block kernel's
-    # bit for bit
+    # planner's default is the per-block kernel, DBP_STREAM=1 selects the streaming twin, and
+    # the twin's output equals the per-block kernel's bit for bit
     import os
     n, batch = 262144, 64
     kw = dict(n_samples=n, n_spans=40, steps_per_span=1, batch=batch, taps=TAPS9, block=512, overlap=128,
               steps_per_pass=1, beta2_ps2_km=B2)
     assert "DBP_STREAM" not in os.environ
-    p = dbp.plan(**kw)
-    assert p.kernel == "dbp_stream_kernel<512, 8, 2, true, 9>", p.kernel
-    os.environ["DBP_STREAM"] = "0"
+    q = dbp.plan(**kw)
+    assert q.kernel == "dbp_pass_kernel<512, 8, 2, true, 9>", q.kernel
+    os.environ["DBP_STREAM"] = "1"
     try:
-        q = dbp.plan(**kw)
+        p = dbp.plan(**kw)
     finally:
         del os.environ["DBP_STREAM"]
-    assert q.kernel == "dbp_pass_kernel<512, 8, 2, true, 9>"
+    assert p.kernel == "dbp_stream_kernel<512, 8, 2, true, 9>"
     rx, _ = received(1, 0, 2, n, 0.0, 40, 2)
     x = torch.from_numpy(rx.astype(np.complex64)).to("cuda").reshape(1, 2, n).expand(batch, 2, n).contiguous()
     # distinct signals: rotate each copy in time so no two are equal
