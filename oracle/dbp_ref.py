@@ -248,11 +248,6 @@ def passes(n_steps: int, k: int) -> int:
 
 # --------------------------------------------------------------------------- link helpers
 
-def channel_memory_samples(beta2_ps2_km: float, length_km: float, bandwidth_thz: float) -> float:
-    """Sec. III: overall channel memory M ~ 2 pi |beta2| L B^2 samples (B = sampling rate)."""
-    return 2.0 * math.pi * abs(beta2_ps2_km) * length_km * bandwidth_thz ** 2
-
-
 def ideal_fir_taps(n_taps: int, b: float, fs_thz: float, n_fft: int = 1 << 16) -> np.ndarray:
     """Centre n_taps samples of the impulse response of Eq. (1)'s all-pass filter.
 
