@@ -263,7 +263,9 @@ typedef struct dbp_rx_s* dbp_rx_t;
 /* Create a receiver for desc's link, method and geometry (batch 1, FFT linear
  * step, not BF16X3, not DBP_FLAG_WHOLE; desc->n_samples is ignored: the planner
  * sees the chunk length).  chunk: samples per polarization per push, >= Nb and a
- * multiple of V = Nb - O (DBP_ERR_INVALID_ARG otherwise).  Block sizes
+ * multiple of V = Nb - O (DBP_ERR_INVALID_ARG otherwise), at most 2^29
+ * (DBP_ERR_UNSUPPORTED above, checked before any device work: the rings hold at
+ * most 2^31 samples).  Block sizes
  * 256..4096 (DBP_ERR_UNSUPPORTED otherwise).  The receiver owns its device
  * state (one ring per pass, allocated and cleared here, synchronously, on the
  * current device); *out is NULL on error. */

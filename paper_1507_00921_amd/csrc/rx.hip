@@ -83,6 +83,11 @@ static hipError_t rx_zero_all(dbp_rx_s* r, hipStream_t s) {
     return launch_rx_zero((float2*)r->mem, n, s);
 }
 
+// Ring capacities are powers of two up to kMaxRing samples, so that the masks of
+// RingArgs (int) stay non-negative; a chunk takes at most a quarter of that.
+constexpr long long kMaxRing = 1LL << 31;
+constexpr long long kMaxChunk = 1LL << 29;
+
 }  // namespace dbp
 
 using namespace dbp;
@@ -94,6 +99,8 @@ dbp_status dbp_rx_create(const dbp_desc* desc, int64_t chunk, dbp_rx_t* out) {
     *out = nullptr;
     if (!desc || chunk <= 0 || desc->batch != 1 || (desc->flags & DBP_FLAG_WHOLE)) return DBP_ERR_INVALID_ARG;
     if (desc->linear != DBP_LINEAR_FFT || desc->precision == DBP_BF16X3) return DBP_ERR_UNSUPPORTED;
+    // ring positions are masked with 32-bit masks: rings hold at most 2^31 samples
+    if (chunk > kMaxChunk) return DBP_ERR_UNSUPPORTED;
     dbp_desc d = *desc;
     d.n_samples = chunk;
     dbp_plan_t plan = nullptr;
@@ -126,6 +133,10 @@ dbp_status dbp_rx_create(const dbp_desc* desc, int64_t chunk, dbp_rx_t* out) {
     }
     r->cap = pow2_at_least(chunk + (long long)(r->P + 1) * r->c * r->V + 2LL * r->nb);
     r->fifo_cap = pow2_at_least(r->latency + 2 * chunk + r->nb);
+    if (r->cap > kMaxRing || r->fifo_cap > kMaxRing) {
+        dbp_rx_destroy(r);
+        return DBP_ERR_UNSUPPORTED;
+    }
     const size_t bytes = ((size_t)r->P * r->cap + r->fifo_cap) * r->npol * sizeof(float2);
     hipError_t e = hipMalloc(&r->mem, bytes);
     if (e != hipSuccess) {

@@ -162,6 +162,18 @@ def test_null_arguments():
     lib.dbp_destroy(None)
 
 
+def test_receiver_rejects_chunks_beyond_its_ring_masks():
+    # rings are indexed with 32-bit masks: a chunk above 2^29 samples is refused before
+    # the planner or the device is touched
+    import ctypes
+    dbp = _lib_or_skip()
+    d = dbp.make_desc(1 << 20, 40, 1, block=1024, overlap=256)
+    h = ctypes.c_void_p()
+    assert dbp.lib().dbp_rx_create(ctypes.byref(d), (1 << 29) + 768, ctypes.byref(h)) == 2
+    assert h.value is None
+    assert dbp.lib().dbp_rx_create(ctypes.byref(d), 0, ctypes.byref(h)) == 1
+
+
 @pytest.mark.parametrize("steps_per_span,forward,m", [(1, False, 1), (20, False, 1), (7, True, 1),
                                                       (1, False, 2), (1, True, 8), (1, False, 40)])
 def test_planner_schedule_matches_oracle(steps_per_span, forward, m):
