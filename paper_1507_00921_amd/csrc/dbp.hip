@@ -321,8 +321,49 @@ void twiddle_table(int nb, std::vector<float2>& tw) {
     }
 }
 
-// exp(-j 2 pi^2 b f_k^2) / nb in natural bin order, f_k = fftfreq(nb, 1/fs)
+// Splits c into three FP32 parts with c = c0 + c1 + c2 to FP64 rounding, c0 and c1
+// holding at most 11 significant bits each (so that their product with an integer of
+// magnitude <= 2^13 is exact in FP32).
+static void split11(double c, float (&parts)[3]) {
+    double rest = c;
+    for (int j = 0; j < 2; ++j) {
+        if (rest == 0.0) { parts[j] = 0.0f; continue; }
+        int ex;
+        std::frexp(rest, &ex);                       // rest = m 2^ex, 0.5 <= |m| < 1
+        const double q = std::ldexp(1.0, ex - 11);
+        parts[j] = (float)(std::nearbyint(rest / q) * q);
+        rest -= (double)parts[j];
+    }
+    parts[2] = (float)rest;
+}
+
+// The fractional part of c kk^2 turns in FP32 arithmetic, |kk| <= 2^13: each part of c
+// times kk is exact, the product with kk again is split into its rounded value and its
+// exact error (fma), and fractions are taken of the exact values, so the only roundings
+// are those of adding fractions in [-1/2, 1/2] (about 2^-25 turns each).
+static float turns_fp32(const float (&c)[3], int kk) {
+    const float s = (float)kk;                       // exact
+    float t = 0.0f;
+    for (int j = 0; j < 3; ++j) {
+        const float a = c[j] * s;                    // exact for j < 2
+        const float p = a * s;
+        const float e = std::fma(a, s, -p);          // a s = p + e exactly
+        t += p - std::rint(p);                       // exact fraction of p
+        t -= std::rint(t);
+        t += e;
+        t -= std::rint(t);
+    }
+    return t;
+}
+
+// exp(-j 2 pi^2 b f_k^2) / nb in natural bin order, f_k = fftfreq(nb, 1/fs).
+// fp64: the phase and its reduction in FP64.  Otherwise FP32 arithmetic: the phase in
+// turns is c kk^2 with c = -pi b fs^2 / nb^2 (its three FP32 parts from the descriptor),
+// reduced exactly to a fraction u of a turn, then to a quarter turn q and a remainder
+// r = (4u - q) pi/2 with |r| <= pi/4, whose FP32 sine and cosine are rotated by q.
 void dispersion_table(int nb, double b, double fs, bool fp64, float2* out) {
+    float c[3];
+    split11(-M_PI * b * fs * fs / ((double)nb * (double)nb), c);
     for (int k = 0; k < nb; ++k) {
         const int kk = k < (nb + 1) / 2 ? k : k - nb;
         if (fp64) {
@@ -331,9 +372,14 @@ void dispersion_table(int nb, double b, double fs, bool fp64, float2* out) {
             th = std::remainder(th, 2.0 * M_PI);
             out[k] = make_float2((float)(std::cos(th) / nb), (float)(std::sin(th) / nb));
         } else {
-            const float f = (float)kk * (float)fs / (float)nb;
-            const float th = -2.0f * (float)(M_PI * M_PI) * (float)b * f * f;
-            out[k] = make_float2(std::cos(th) / (float)nb, std::sin(th) / (float)nb);
+            const float u = 4.0f * turns_fp32(c, kk);           // quarter turns, |u| <= 2
+            const float q = std::rint(u);
+            const float r = (u - q) * 1.57079637f;              // u - q exact
+            const float cs = std::cos(r), sn = std::sin(r);
+            const int qi = ((int)q) & 3;
+            float re = qi == 0 ? cs : qi == 1 ? -sn : qi == 2 ? -cs : sn;
+            float im = qi == 0 ? sn : qi == 1 ? cs : qi == 2 ? -sn : -cs;
+            out[k] = make_float2(re / (float)nb, im / (float)nb);
         }
     }
 }

@@ -14,7 +14,7 @@ import siggen
 from oracle import adjoint as A
 from oracle import dbp_ref as R
 
-from gpu_inputs import B2, FS, received, rel_l2
+from gpu_inputs import B2, FS, received, field_err, rel_l2
 
 pytestmark = pytest.mark.gpu
 
@@ -66,14 +66,14 @@ def test_fft_grad_matches_oracle(dbp, nb, o, k, n_pol, nc, n_spans, n, batch):
     wsum = np.zeros((n_spans, 2 * nc + 1)) if taps is not None else None
     for i in range(batch):
         ref = A.grad_blocked(xs[i], steps, FS, nb, o, k, gout[i].astype(np.complex128))
-        err = rel_l2(gx[i], ref.x)
+        err = field_err(gx[i], ref.x)
         print(f"Nb={nb} O={o} k={k} pol={n_pol} signal {i}: grad_in rel L2 {err:.3e}")
         assert err <= 1e-5
         if taps is not None:
             wsum += np.stack(ref.w)
     if taps is not None:
         got = gt.cpu().numpy().astype(np.float64)
-        err = rel_l2(got, wsum)
+        err = field_err(got, wsum)
         print(f"  grad_taps rel L2 {err:.3e}")
         assert err <= 1e-4
     else:

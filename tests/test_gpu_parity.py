@@ -16,7 +16,7 @@ import pytest
 import siggen
 from oracle import dbp_ref as R
 
-from gpu_inputs import B2, FS, received, rel_l2
+from gpu_inputs import B2, FS, received, field_err, rel_l2
 
 pytestmark = pytest.mark.gpu
 
@@ -65,7 +65,7 @@ def test_cfg0_whole_signal_single_polarization(dbp):
     assert (p.block, p.overlap, p.steps_per_pass) == (16384, 0, 4)
     y = _from_gpu(p.backprop(_to_gpu(rx)), (1, 16384))
     ref = _oracle(rx, p, 4, 1)
-    err = rel_l2(y, ref)
+    err = field_err(y, ref)
     print(f"cfg0 rel L2 {err:.3e}")
     assert err <= 1e-5
     assert abs(siggen.evm_db(y, sym) - siggen.evm_db(ref, sym)) <= 0.01
@@ -90,7 +90,7 @@ def test_blocked_parity(dbp, block, overlap, n_pol, essfm, n_spans, sps, k, n):
                  steps_per_pass=k, beta2_ps2_km=B2)
     y = _from_gpu(p.backprop(_to_gpu(rx)), (n_pol, n))
     ref = _oracle(rx, p, n_spans, sps, taps=taps)
-    err = rel_l2(y, ref)
+    err = field_err(y, ref)
     print(f"Nb={p.block} O={p.overlap} k={p.steps_per_pass} steps={p.n_steps}: rel L2 {err:.3e}")
     assert err <= (1e-5 if p.n_steps <= 40 else 2e-4)
 
@@ -107,7 +107,7 @@ def test_cfg1_full_size(dbp, method):
         p = dbp.plan(n, 40, 20, block=1024, overlap=256, beta2_ps2_km=B2)
         ref = _oracle(rx, p, 40, 20)
     y = _from_gpu(p.backprop(_to_gpu(rx)), (2, n))
-    err = rel_l2(y, ref)
+    err = field_err(y, ref)
     devm = siggen.evm_db(y, sym) - siggen.evm_db(ref, sym)
     print(f"cfg1 {method}: k={p.steps_per_pass} passes={p.n_passes} rel L2 {err:.3e} dEVM {devm:+.4f} dB")
     assert err <= (1e-5 if p.n_steps <= 40 else 2e-4)
@@ -128,7 +128,7 @@ def test_sampled_outputs_at_full_size_are_per_block_exact(dbp):
         lo = b * v
         hi = min(lo + v, n)
         want = g[:, p.overlap // 2: p.overlap // 2 + hi - lo]
-        assert rel_l2(y[:, lo:hi], want) <= 1e-5
+        assert field_err(y[:, lo:hi], want) <= 1e-5
 
 
 def test_in_place_and_workspace_rules(dbp):
@@ -164,7 +164,7 @@ def test_per_step_device_taps(dbp):
     p = dbp.plan(n, 6, 1, taps=per_step[0], block=512, overlap=128, steps_per_pass=2, beta2_ps2_km=B2)
     y = _from_gpu(p.backprop(_to_gpu(rx), taps=torch.from_numpy(per_step).cuda()), (2, n))
     ref = _oracle(rx, p, 6, 1, taps_per_step=per_step)
-    assert rel_l2(y, ref) <= 1e-5
+    assert field_err(y, ref) <= 1e-5
 
 
 def test_forward_direction_and_batch(dbp):
@@ -175,7 +175,7 @@ def test_forward_direction_and_batch(dbp):
     y = _from_gpu(p.backprop(_to_gpu(xb, batch=3)), (3, 2, n))
     for i in range(3):
         ref = _oracle(xb[i], p, 3, 4, backward=False)
-        assert rel_l2(y[i], ref) <= 1e-5
+        assert field_err(y[i], ref) <= 1e-5
 
 
 def test_fp32_phase_variant(dbp):
@@ -184,11 +184,13 @@ def test_fp32_phase_variant(dbp):
     p = dbp.plan(n, 40, 1, taps=TAPS9, block=1024, overlap=256, precision=dbp.FP32, beta2_ps2_km=B2)
     y = _from_gpu(p.backprop(_to_gpu(rx)), (2, n))
     ref = _oracle(rx, p, 40, 1, taps=TAPS9)
-    err = rel_l2(y, ref)
+    err = field_err(y, ref)
     print(f"FP32 tables and phase: rel L2 {err:.3e}")
-    # dispersion phases of up to 27 rad per 80 km step formed in FP32 carry ~2e-6 rad of
-    # systematic error per bin, repeated every step: this variant is reported, held to 5e-5
-    assert err <= 5e-5
+    # the dispersion phase (up to 27 rad per 80 km step) is formed in FP32 as an exactly
+    # reduced fraction of a turn (about 2e-7 rad per bin at most; a direct FP32 product of
+    # the constants leaves 4e-6 rad, repeated every step), so the variant meets the FP32
+    # budget of the other variants
+    assert err <= 1e-5
 
 
 def test_gamma_zero_round_trip_on_gpu(dbp):
@@ -198,7 +200,7 @@ def test_gamma_zero_round_trip_on_gpu(dbp):
     f = dbp.plan(n, 5, 2, whole=True, forward=True, gamma_w_km=0.0, beta2_ps2_km=B2)
     b = dbp.plan(n, 5, 2, whole=True, gamma_w_km=0.0, beta2_ps2_km=B2)
     y = _from_gpu(b.backprop(f.backprop(_to_gpu(x))), (2, n))
-    assert rel_l2(y, x) <= 1e-5
+    assert field_err(y, x) <= 1e-5
 
 
 @pytest.mark.parametrize("m,taps_nc,n", [(8, 32, 20000), (4, 4, 12288), (2, None, 9000)])
@@ -212,7 +214,7 @@ def test_multi_span_steps_parity(dbp, m, taps_nc, n):
     t = None if taps is None else np.asarray(taps, np.float32).astype(np.float64)
     steps = R.schedule(8, 80.0, 1, B2, siggen.GAMMA_W_KM, siggen.ALPHA_DB_KM, taps=t, spans_per_step=m)
     ref = R.run_blocked(x, steps, FS, p.block, p.overlap, p.steps_per_pass)
-    err = rel_l2(y, ref)
+    err = field_err(y, ref)
     print(f"multi-span m={m} steps={len(steps)} Nb={p.block} O={p.overlap} k={p.steps_per_pass}: rel L2 {err:.3e}")
     assert len(steps) == p.n_steps == 8 // m
     assert err <= 1e-5
@@ -230,7 +232,7 @@ def test_polarization_split_blocks(dbp, monkeypatch, force, nb, taps):
     assert ("split" in p.kernel) == (force == "1"), p.kernel
     y = _from_gpu(p.backprop(_to_gpu(x)), x.shape)
     ref = _oracle(x, p, 6, 1, taps=taps)
-    err = rel_l2(y, ref)
+    err = field_err(y, ref)
     print(f"{p.kernel}: rel L2 {err:.3e}")
     assert err <= 1e-5
 
@@ -258,7 +260,7 @@ def test_dispersion_free_cascade_has_the_closed_form(dbp, essfm, n_pol):
         j = inten
     total = float(np.sum(phi) * np.max(j))
     ref = xi * np.exp(-1j * np.sum(phi) * j)
-    err = rel_l2(y, ref)
+    err = field_err(y, ref)
     # tolerance from the arithmetic: 40 FP32 FFT round trips let the intensity drift by about
     # 1e-6 (numpy's complex64 FFT: 1.3e-6 over 40 round trips of these blocks), and the
     # accumulated phase multiplies that drift by Phi J (up to 28 rad here, about 0.7 rad per
@@ -284,7 +286,7 @@ def test_linear_cascade_is_the_whole_link_dispersion(dbp):
     f = np.fft.fftfreq(n, d=1.0 / FS)
     ref = np.fft.ifft(np.fft.fft(x.astype(np.complex128), axis=-1) * np.exp(-2j * np.pi ** 2 * np.sum(b) * f * f),
                       axis=-1)
-    err = rel_l2(y, ref)
+    err = field_err(y, ref)
     print(f"gamma = 0 whole-link dispersion: rel L2 {err:.2e}")
     assert err <= 1e-5
 
@@ -301,7 +303,7 @@ def test_essfm_with_a_unit_filter_is_ssfm(dbp):
     geo = dict(block=1024, overlap=256, steps_per_pass=5, beta2_ps2_km=B2)
     ye = _from_gpu(dbp.plan(n, 40, 1, taps=w, **geo).backprop(_to_gpu(x)), (2, n))
     ys = _from_gpu(dbp.plan(n, 40, 1, **geo).backprop(_to_gpu(x)), (2, n))
-    err = rel_l2(ye, ys)
+    err = field_err(ye, ys)
     print(f"ESSFM with w = e_4 against SSFM: rel L2 {err:.2e}")
     assert err <= 1e-5
 
@@ -316,7 +318,7 @@ def test_essfm_with_a_one_sample_shift_filter_matches_oracle(dbp):
     p = dbp.plan(n, 40, 1, taps=w, block=1024, overlap=256, steps_per_pass=5, beta2_ps2_km=B2)
     y = _from_gpu(p.backprop(_to_gpu(x)), (2, n))
     ref = _oracle(x, p, 40, 1, taps=w)
-    err = rel_l2(y, ref)
+    err = field_err(y, ref)
     mirrored = _oracle(x, p, 40, 1, taps=w[::-1].copy())
     print(f"one-sample-shift taps: rel L2 {err:.2e} (against the mirrored filter {rel_l2(y, mirrored):.2e})")
     assert err <= 1e-5

@@ -14,7 +14,7 @@ import pytest
 import siggen
 from oracle import dbp_ref as R
 
-from gpu_inputs import B2, FS, received, rel_l2
+from gpu_inputs import B2, FS, received, field_err, rel_l2
 
 pytestmark = pytest.mark.gpu
 
@@ -79,7 +79,7 @@ def test_stream_matches_block_kernel_and_oracle(dbp, monkeypatch, block, overlap
     steps = R.schedule(n_spans, 80.0, sps, B2, siggen.GAMMA_W_KM, siggen.ALPHA_DB_KM, taps=t64)
     for i in range(batch):
         o = R.run_blocked(fields[i], steps, FS, st_plan.block, st_plan.overlap, st_plan.steps_per_pass)
-        err = rel_l2(y_st[i].astype(np.complex128), o)
+        err = field_err(y_st[i].astype(np.complex128), o)
         print(f"  signal {i}: rel L2 vs oracle {err:.3e}")
         assert err <= 1e-5
 
@@ -115,6 +115,6 @@ def test_stream_kernel_on_request_for_large_working_set(dbp):
     steps = R.schedule(40, 80.0, 1, B2, siggen.GAMMA_W_KM, siggen.ALPHA_DB_KM,
                        taps=np.asarray(TAPS9, np.float32).astype(np.float64))
     o = R.run_blocked(np.roll(rx, 97 * b, axis=-1), steps, FS, 512, 128, 1)
-    err = rel_l2(a[b].cpu().numpy().astype(np.complex128), o)
+    err = field_err(a[b].cpu().numpy().astype(np.complex128), o)
     print(f"x64 field, signal {b}: rel L2 vs oracle {err:.3e}")
     assert err <= 1e-5
