@@ -190,6 +190,26 @@ size_t dbp_workspace_size(dbp_plan_t plan, int32_t grad);
 dbp_status dbp_backprop(dbp_plan_t plan, const void* in, void* out, const float* taps,
                         const void* fir, void* ws, size_t ws_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): dbp_backprop
+ * with its workspace taken from a fixed device array of
+ * DBP_NOALLOC_SCRATCH_BYTES that the library holds on every device it runs on
+ * until the process ends.  Arguments as dbp_backprop (the caller still owns in,
+ * out, taps and fir); the call allocates and frees nothing.
+ *   DBP_ERR_WORKSPACE     dbp_workspace_size(plan, 0) > DBP_NOALLOC_SCRATCH_BYTES
+ *                         (two states of at most 16 MiB, e.g. 2 x 1048576
+ *                         samples, or one state of 32 MiB for single-pass plans)
+ *   DBP_ERR_INVALID_ARG   as dbp_backprop (batch plans, overlap, wrong device)
+ *   DBP_ERR_HIP           the array's device address could not be found
+ * Every call on a device shares that device's array, which keeps the last
+ * call's contents (nothing in it has to start at zero: each pass writes its
+ * whole output state before the next reads it).  Calls that overlap in time on
+ * one device (other streams, other host threads) race on it and must be
+ * serialized by the caller. */
+#define DBP_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+dbp_status dbp_backprop_noalloc(dbp_plan_t plan, const void* in, void* out, const float* taps,
+                                const void* fir, void* stream);
+
 /* Gradient of a real loss through dbp_backprop (reverse mode).  Given
  * grad_out = dL/dRe(out) + j dL/dIm(out) (device complex64, same shape as
  * in), writes grad_in (same convention; may be NULL; must not overlap

@@ -23,6 +23,7 @@ LINEAR_FFT, LINEAR_FIR = 0, 1
 FP32, FP32_FP64PHASE, BF16X3 = 0, 1, 2
 FLAG_FORWARD, FLAG_WHOLE, FLAG_GRAD_SPARSE = 0x1, 0x2, 0x4
 MAX_TAPS = 129
+NOALLOC_SCRATCH_BYTES = 32 << 20    # DBP_NOALLOC_SCRATCH_BYTES
 MAX_FIR = 129
 
 STATUS = {0: "ok", 1: "invalid argument", 2: "unsupported configuration",
@@ -77,6 +78,8 @@ def lib():
         L.dbp_backprop.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                    c_size_t, c_void_p]
         L.dbp_backprop.restype = c_int32
+        L.dbp_backprop_noalloc.argtypes = [c_void_p] * 6
+        L.dbp_backprop_noalloc.restype = c_int32
         L.dbp_backprop_grad.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                         c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]
         L.dbp_backprop_grad.restype = c_int32
@@ -270,6 +273,18 @@ class Plan:
         st = lib().dbp_backprop(self._h, _ptr(x), _ptr(out), _ptr(taps), _ptr(fir), _ptr(workspace),
                                 workspace.numel(), _stream_ptr(stream))
         _check(st, "dbp_backprop")
+        return out
+
+    def backprop_noalloc(self, x, out, taps=None, fir=None, stream=None):
+        """Run the plan on x into the caller's out with the library's fixed device scratch as
+        workspace (dbp_backprop_noalloc: no device allocation in the call).  Calls that
+        overlap in time on one device share that scratch and must be serialized."""
+        self._check_field(x, "input")
+        self._check_field(out, "output")
+        self._check_params(taps, fir)
+        st = lib().dbp_backprop_noalloc(self._h, _ptr(x), _ptr(out), _ptr(taps), _ptr(fir),
+                                        _stream_ptr(stream))
+        _check(st, "dbp_backprop_noalloc")
         return out
 
     def _check_params(self, taps, fir):

@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -21,6 +22,32 @@
 #include "mfma_kernel.hpp"
 
 namespace dbp {
+
+// ------------------------------------------------------------------ fixed device scratch
+
+// Workspace of dbp_backprop_noalloc, for callers that cannot allocate: every
+// device the library runs on holds its own copy for the life of the process.
+// In host code `scratch` names a host-side stand-in, never the device memory:
+// kernels and copies receive the address hipGetSymbolAddress returns for the
+// current device, looked up once per device when a plan is created there.
+static __device__ __align__(256) unsigned char scratch[DBP_NOALLOC_SCRATCH_BYTES];
+
+static constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on device `dev`, which must be the current
+// device; nullptr when the lookup fails.
+void* scratch_address(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+        g_scratch_ptr[dev] = ptr;
+    }
+    return g_scratch_ptr[dev];
+}
 
 // ------------------------------------------------------------------ kernel registry
 
@@ -695,6 +722,9 @@ dbp_status dbp_plan(const dbp_desc* desc, dbp_plan_t* out) {
         delete p;
         return DBP_ERR_HIP;
     }
+    // set-up of the allocation-free entry point on this device (once per device; a failed
+    // lookup is retried, and reported, by that entry point)
+    (void)scratch_address(p->device);
     if (!fir_mode && desc->precision != DBP_BF16X3 &&
         (st = choose_stream(p,
                             find_entry(nb, p->geo.e, desc->n_pol, fp64, tap_variant(desc->method, desc->n_taps),
@@ -952,19 +982,16 @@ size_t dbp_workspace_size(dbp_plan_t p, int32_t grad) {
     return p->geo.n_passes == 1 ? state : 2 * state;
 }
 
-dbp_status dbp_backprop(dbp_plan_t p, const void* in, void* out, const float* taps, const void* fir,
-                        void* ws, size_t ws_bytes, void* stream) {
-    if (!p || !in || !out || p->is_batch) return DBP_ERR_INVALID_ARG;
-    (void)fir;
+}  // extern "C"
+
+// The passes of dbp_backprop on a workspace the caller has checked to be at
+// least dbp_workspace_size(p, 0) bytes (or NULL when that size is 0).
+static dbp_status backprop_passes(Plan* p, const void* in, void* out, const float* taps, const void* fir,
+                                  void* ws, void* stream) {
     const size_t state = p->state_bytes();
     const char* ib = (const char*)in;
     const char* ob = (const char*)out;
     if (in != out && ib < ob + state && ob < ib + state) return DBP_ERR_INVALID_ARG;
-    const size_t need = dbp_workspace_size(p, 0);
-    if (ws_bytes < need || (need > 0 && !ws)) return DBP_ERR_WORKSPACE;
-    int dev = -1;
-    if (hipGetDevice(&dev) != hipSuccess) return DBP_ERR_HIP;
-    if (dev != p->device) return DBP_ERR_INVALID_ARG;
     hipStream_t s = (hipStream_t)stream;
     const Geometry& g = p->geo;
     float2* w0 = (float2*)ws;
@@ -1033,6 +1060,31 @@ dbp_status dbp_backprop(dbp_plan_t p, const void* in, void* out, const float* ta
         if (hipMemcpyAsync(out, w0, state, hipMemcpyDeviceToDevice, s) != hipSuccess) return DBP_ERR_HIP;
     }
     return DBP_OK;
+}
+
+extern "C" {
+
+dbp_status dbp_backprop(dbp_plan_t p, const void* in, void* out, const float* taps, const void* fir,
+                        void* ws, size_t ws_bytes, void* stream) {
+    if (!p || !in || !out || p->is_batch) return DBP_ERR_INVALID_ARG;
+    const size_t need = dbp_workspace_size(p, 0);
+    if (ws_bytes < need || (need > 0 && !ws)) return DBP_ERR_WORKSPACE;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return DBP_ERR_HIP;
+    if (dev != p->device) return DBP_ERR_INVALID_ARG;
+    return backprop_passes(p, in, out, taps, fir, ws, stream);
+}
+
+dbp_status dbp_backprop_noalloc(dbp_plan_t p, const void* in, void* out, const float* taps, const void* fir,
+                                void* stream) {
+    if (!p || !in || !out || p->is_batch) return DBP_ERR_INVALID_ARG;
+    if (dbp_workspace_size(p, 0) > DBP_NOALLOC_SCRATCH_BYTES) return DBP_ERR_WORKSPACE;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return DBP_ERR_HIP;
+    if (dev != p->device) return DBP_ERR_INVALID_ARG;
+    void* ws = scratch_address(dev);
+    if (!ws) return DBP_ERR_HIP;
+    return backprop_passes(p, in, out, taps, fir, ws, stream);
 }
 
 dbp_status dbp_backprop_grad(dbp_plan_t p, const void* in, const float* taps, const void* fir,
