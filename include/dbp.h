@@ -375,6 +375,46 @@ dbp_status dbp_dsp_cpr(dbp_dsp_t dsp, const void* y, const void* sym, int64_t n_
 /* Release (NULL is a no-op); no call on it may still be running. */
 void dbp_dsp_destroy(dbp_dsp_t dsp);
 
+/* Loss head of the differentiation workload (Sec. IV footnote: the ESSFM
+ * coefficients can be optimized for the mean squared error between the detected
+ * symbols and the transmitted ones), and its reverse mode, so that a training
+ * step runs entirely in this library:
+ *   loss = (1 / (batch n_pol L/2)) sum |y[2m] / amp - s[m]|^2,
+ *   y = IDFT_L(DFT_L(z) mf) per signal and polarization (circular over L),
+ * i.e. the receive filter mf (real, on the length-L DFT grid, hence
+ * self-adjoint) followed by one sample per symbol at two samples per symbol;
+ * amp is the symbol amplitude of the field.  The reverse mode is
+ *   grad_z = g IDFT_L(DFT_L(up) mf),  up[2m] = 2 (y[2m] / amp - s[m]) / (amp N),
+ *   up[2m + 1] = 0,  N = batch n_pol L/2,  g = dL/dloss,
+ * with complex gradients dL/dRe + j dL/dIm.  No length-L transform is run: the
+ * even and odd bins are two L/2-point transforms and the decimated output two
+ * L/4-point ones.  L = n_samples, a power of two from 2048 to 32768; z and
+ * grad_z device complex64 [batch][n_pol][L], symbols device complex64
+ * [batch][n_pol][L/2].  Allocates its tables and every scratch of the later
+ * calls on the current device at create (mf: host float64 [L], copied). */
+typedef struct dbp_mse_s* dbp_mse_t;
+
+/* DBP_ERR_INVALID_ARG for a bad size, count, amplitude or non-finite mf;
+ * DBP_ERR_UNSUPPORTED for L outside 2048..32768.  *out is NULL on error. */
+dbp_status dbp_mse_create(int64_t n_samples, int32_t n_pol, int32_t batch, const double* mf,
+                          double amplitude, dbp_mse_t* out);
+
+/* loss (device float32, one value) of the field z against the symbols.  Keeps
+ * the residual y[2m] / amp - s[m] in the handle for dbp_mse_backward.
+ * Asynchronous on stream; the per-signal sums are added in FP64 in a fixed
+ * order (bitwise reproducible). */
+dbp_status dbp_mse_forward(dbp_mse_t mse, const void* z, const void* symbols, float* loss,
+                           void* stream);
+
+/* grad_z for the residual of the last dbp_mse_forward on this handle, scaled by
+ * the device float32 *grad_loss (NULL: 1).  Asynchronous on stream; calls on one
+ * handle share its scratch and must be issued in order on one stream, with
+ * the device current that was current at create (else DBP_ERR_INVALID_ARG). */
+dbp_status dbp_mse_backward(dbp_mse_t mse, const float* grad_loss, void* grad_z, void* stream);
+
+/* Release (NULL is a no-op); no call on it may still be running. */
+void dbp_mse_destroy(dbp_mse_t mse);
+
 /* Short static description of a status code. */
 const char* dbp_status_string(dbp_status s);
 

@@ -119,6 +119,14 @@ def lib():
         L.dbp_dsp_cpr.restype = c_int32
         L.dbp_dsp_destroy.argtypes = [c_void_p]
         L.dbp_dsp_destroy.restype = None
+        L.dbp_mse_create.argtypes = [c_int64, c_int32, c_int32, POINTER(c_double), c_double, POINTER(c_void_p)]
+        L.dbp_mse_create.restype = c_int32
+        L.dbp_mse_forward.argtypes = [c_void_p] * 5
+        L.dbp_mse_forward.restype = c_int32
+        L.dbp_mse_backward.argtypes = [c_void_p] * 4
+        L.dbp_mse_backward.restype = c_int32
+        L.dbp_mse_destroy.argtypes = [c_void_p]
+        L.dbp_mse_destroy.restype = None
         L.dbp_status_string.argtypes = [c_int32]
         L.dbp_status_string.restype = ctypes.c_char_p
         L.dbp_version.argtypes = []
@@ -530,6 +538,99 @@ class ReceiverDsp:
 
 def receiver_dsp(n_in: int, **kw) -> ReceiverDsp:
     return ReceiverDsp(n_in, **kw)
+
+
+class SymbolMse:
+    """A dbp_mse: the loss head of the differentiation workload, mean |MF(z)[::2] / amp - s|^2
+    over every symbol, with its reverse mode (Sec. IV footnote).  mf: the real receive filter on
+    the length-n DFT grid (numpy); fields complex64 CUDA tensors [batch][n_pol][n], symbols
+    [batch][n_pol][n / 2]."""
+
+    def __init__(self, n_samples: int, n_pol: int, batch: int, mf, amplitude: float):
+        mf = np.ascontiguousarray(mf, dtype=np.float64)
+        if mf.shape != (n_samples,):
+            raise ValueError(f"mf must have {n_samples} values")
+        h = c_void_p()
+        _check(lib().dbp_mse_create(n_samples, n_pol, batch, mf.ctypes.data_as(POINTER(c_double)), amplitude,
+                                    ctypes.byref(h)), "dbp_mse_create")
+        self._h = h
+        self.n, self.n_pol, self.batch = n_samples, n_pol, batch
+        self.generation = 0          # forward calls so far (the reverse mode uses the last one's residual)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().dbp_mse_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, t, n, what, dtype=None):
+        import torch
+        want = (self.batch, self.n_pol, n)
+        if t.dtype != (dtype or torch.complex64) or not t.is_cuda or not t.is_contiguous() or t.numel() != np.prod(want):
+            raise ValueError(f"{what} must be a contiguous complex64 CUDA tensor {list(want)}")
+
+    def forward(self, z, symbols, loss=None, stream=None):
+        """Loss (float32 CUDA tensor [1]); keeps the residual for backward()."""
+        import torch
+        self._check(z, self.n, "z")
+        self._check(symbols, self.n // 2, "symbols")
+        if loss is None:
+            loss = torch.empty(1, dtype=torch.float32, device=z.device)
+        _check(lib().dbp_mse_forward(self._h, _ptr(z), _ptr(symbols), _ptr(loss), _stream_ptr(stream)),
+               "dbp_mse_forward")
+        self.generation += 1
+        return loss
+
+    def backward(self, grad_loss=None, grad_z=None, stream=None):
+        """dloss/dz (times the device scalar grad_loss) for the last forward()."""
+        import torch
+        if grad_z is None:
+            grad_z = torch.empty(self.batch, self.n_pol, self.n, dtype=torch.complex64, device="cuda")
+        self._check(grad_z, self.n, "grad_z")
+        if grad_loss is not None and (grad_loss.dtype != torch.float32 or not grad_loss.is_cuda
+                                      or grad_loss.numel() != 1):
+            raise ValueError("grad_loss must be a float32 CUDA tensor of one value")
+        g = grad_loss.contiguous() if grad_loss is not None else None
+        _check(lib().dbp_mse_backward(self._h, _ptr(g), _ptr(grad_z), _stream_ptr(stream)), "dbp_mse_backward")
+        return grad_z
+
+
+def _mse_function():
+    import torch
+
+    class MseFunction(torch.autograd.Function):
+        """loss = head.forward(z, symbols) with the library's reverse mode of the loss head."""
+
+        @staticmethod
+        def forward(ctx, z, symbols, head):
+            loss = head.forward(z.contiguous(), symbols)
+            ctx.head = head
+            ctx.generation = head.generation
+            return loss.reshape(())
+
+        @staticmethod
+        def backward(ctx, g):
+            if ctx.head.generation != ctx.generation:
+                raise RuntimeError("SymbolMse: another forward ran after this loss; its residual is gone")
+            return ctx.head.backward(g.reshape(1).to(torch.float32)), None, None
+
+    return MseFunction
+
+
+_MseFunction = None
+
+
+def mse_function():
+    """The torch.autograd.Function wrapping SymbolMse.forward / backward."""
+    global _MseFunction
+    if _MseFunction is None:
+        _MseFunction = _mse_function()
+    return _MseFunction
 
 
 def _autograd_function():

@@ -238,3 +238,29 @@ def test_split_precision_geometry_rules():
     arr = (dbp.Desc * 2)(_desc(n_samples=4096, precision=dbp.BF16X3), _desc(n_samples=4096))
     assert lib.dbp_plan_batch(arr, 2, ctypes.byref(h)) == 2
 
+
+
+def test_loss_head_validation_on_host():
+    # dbp_mse_create rejects bad sizes and arguments before touching the GPU
+    dbp = _lib_or_skip()
+    lib = dbp.lib()
+    h = ctypes.c_void_p()
+
+    def create(n, n_pol=2, batch=1, amp=1.0, mf=None):
+        m = np.ones(max(n, 1)) if mf is None else mf
+        return lib.dbp_mse_create(n, n_pol, batch, m.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), amp,
+                                  ctypes.byref(h))
+
+    assert create(3000) == 1                   # not a power of two
+    assert create(1024) == 2                   # below 2048
+    assert create(65536) == 2                  # above 32768
+    assert create(4096, n_pol=3) == 1
+    assert create(4096, batch=0) == 1
+    assert create(4096, amp=0.0) == 1
+    bad = np.ones(4096)
+    bad[7] = np.nan
+    assert create(4096, mf=bad) == 1
+    assert h.value is None
+    assert lib.dbp_mse_forward(None, None, None, None, None) == 1
+    assert lib.dbp_mse_backward(None, None, None, None) == 1
+    lib.dbp_mse_destroy(None)
