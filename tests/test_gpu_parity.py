@@ -10,6 +10,9 @@ perturbations): an independent FP32 cascade (numpy's complex64 FFT) on the
 800-step, 1024-point workload reaches 2.2e-4, so those are held to 2e-4
 relative L2 and, above all, to the 0.01 dB EVM bound.
 """
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -95,14 +98,25 @@ def test_blocked_parity(dbp, block, overlap, n_pol, essfm, n_spans, sps, k, n):
     assert err <= (1e-5 if p.n_steps <= 40 else 2e-4)
 
 
-@pytest.mark.parametrize("method", ["essfm", "ssfm"])
+def _fitted_taps():
+    """ESSFM taps fitted by the oracle at +4 dBm (tests/golden/make_fitted_taps.py)."""
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "fitted_taps_headline.json")) as f:
+        g = json.load(f)
+    assert g["p_dbm"] == 4.0 and len(g["taps"]) == 9
+    return np.asarray(g["taps"], dtype=np.float32)
+
+
+@pytest.mark.parametrize("method", ["essfm", "ssfm", "essfm_fitted_p4"])
 def test_cfg1_full_size(dbp, method):
-    # 2 x 262144 at 3200 km, Nb=1024, O=256: ESSFM 40 steps (9 taps) or SSFM 800 steps
+    # 2 x 262144 at 3200 km, Nb=1024, O=256: ESSFM 40 steps (9 taps) or SSFM 800 steps; the
+    # bench's operating point: +4 dBm with taps fitted as Sec. IV prescribes
     n = 262144
-    rx, sym = received(1, 0, 2, n, 0.0, 40, 2)
-    if method == "essfm":
-        p = dbp.plan(n, 40, 1, taps=TAPS9, block=1024, overlap=256, beta2_ps2_km=B2)
-        ref = _oracle(rx, p, 40, 1, taps=TAPS9)
+    rx, sym = received(1, 0, 2, n, 4.0 if method == "essfm_fitted_p4" else 0.0, 40, 2)
+    if method.startswith("essfm"):
+        taps = _fitted_taps() if method == "essfm_fitted_p4" else TAPS9
+        p = dbp.plan(n, 40, 1, taps=taps, block=1024, overlap=256, beta2_ps2_km=B2)
+        assert (p.block, p.overlap, p.steps_per_pass) == (1024, 256, 5)
+        ref = _oracle(rx, p, 40, 1, taps=taps)
     else:
         p = dbp.plan(n, 40, 20, block=1024, overlap=256, beta2_ps2_km=B2)
         ref = _oracle(rx, p, 40, 20)
