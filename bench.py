@@ -212,7 +212,7 @@ def time_dbp_settled(torch, p, x, out, ws, reps=10, batches=5, warm_s=0.5):
     return float(np.median([time_dbp(torch, p, x, out, ws, 0, reps)[0] for _ in range(batches)]))
 
 
-def hbm_working_set(dbp, torch, rx, taps, batch=64, reps=10, only=None):
+def hbm_working_set(dbp, torch, rx, taps, batch=64, reps=10, only=None, only_variant="per_block"):
     """The ESSFM pass kernel on the field replicated `batch` times (256 MiB per state,
     beyond the 256 MB Infinity Cache), one launch per pass: k = 1 (one HBM round trip per
     step) and k = 2 on the smallest valid block, Nb=512 O=128 (and SSFM at k = 1, and ESSFM
@@ -233,7 +233,7 @@ def hbm_working_set(dbp, torch, rx, taps, batch=64, reps=10, only=None):
         if only is not None and name != only:
             continue
         for variant in ("stream", "per_block"):
-            if only is not None and variant != "stream":
+            if only is not None and variant != only_variant:
                 continue
             # the planner's default is the per-block kernel; the streaming twin is timed
             # beside it (under the case's own name) at one step per pass
@@ -247,7 +247,7 @@ def hbm_working_set(dbp, torch, rx, taps, batch=64, reps=10, only=None):
             finally:
                 os.environ.pop("DBP_STREAM", None)
             assert p.n_passes == 1
-            if variant == "per_block" and f"{name}_per_block" not in res and "stream" not in res[name]["kernel"]:
+            if variant == "per_block" and only is None and "stream" not in res[name]["kernel"]:
                 p.close()
                 continue
             ws = p.workspace()
@@ -865,8 +865,11 @@ def main():
     ap.add_argument("--hbm-only", action="store_true",
                     help="only the large-working-set pass-kernel measurement")
     ap.add_argument("--hbm-case", default=None,
-                    help="with --hbm-only: one case (e.g. k1_nb512), streaming kernel, 2 + 10 launches "
-                         "(for counter runs)")
+                    help="with --hbm-only: one case (e.g. k1_nb512), 2 + 10 launches (for counter runs)")
+    ap.add_argument("--hbm-variant", default="per_block", choices=("per_block", "stream"),
+                    help="with --hbm-case: the per-block kernel (the planner's default) or the streaming twin")
+    ap.add_argument("--only", default=None, choices=("precision", "gradient", "batch"),
+                    help="run one secondary workload alone and print its JSON (for profiler runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a plain 1 GiB device copy three times and exit (counter calibration)")
     args = ap.parse_args()
@@ -887,7 +890,12 @@ def main():
     if args.hbm_only:
         rx, _ = gpu_field(dbp, torch, P_DBM)
         taps = siggen.symmetric_taps(siggen.rng(1, 0, 7), NC)
-        print(json.dumps(hbm_working_set(dbp, torch, rx, taps, only=args.hbm_case)), flush=True)
+        print(json.dumps(hbm_working_set(dbp, torch, rx, taps, only=args.hbm_case,
+                                         only_variant=args.hbm_variant)), flush=True)
+        return
+    if args.only:
+        fn = {"precision": precision_workload, "gradient": grad_workload, "batch": batch_workload}[args.only]
+        print(json.dumps(fn(dbp, torch, reps=2)), flush=True)
         return
 
     sweep = None
