@@ -247,6 +247,7 @@ struct BatchGroup {
     BatchLaunchFn fn;
     int grid;
     int item0, n_items;
+    double work = 0;          // sample-steps of its signals (launch order: most work first)
     float2* d_tw = nullptr;
 };
 
@@ -265,6 +266,9 @@ struct BatchState {
     int n_progress = 0;
     long long total = 0;                 // complex elements of the packed buffer
     hipStream_t cap = nullptr;           // private capture stream
+    std::vector<hipStream_t> side;       // one more capture stream per further group
+    hipEvent_t ev_fork = nullptr;        // the groups' launches fork after the reset ...
+    std::vector<hipEvent_t> ev_join;     // ... and join before the graph ends
     hipGraphExec_t exec = nullptr;
     const void* g_in = nullptr;
     void* g_out = nullptr;
@@ -276,6 +280,11 @@ void destroy_batch(Plan* p) {
     BatchState* b = (BatchState*)p->batch;
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->cap) (void)hipStreamDestroy(b->cap);
+    for (hipStream_t q : b->side)
+        if (q) (void)hipStreamDestroy(q);
+    if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
+    for (hipEvent_t e : b->ev_join)
+        if (e) (void)hipEventDestroy(e);
     std::map<float2*, int> tws;
     for (auto& g : b->groups) tws[g.d_tw] = 1;
     for (auto& kv : tws)
@@ -438,6 +447,7 @@ dbp_status dbp_plan_batch(const dbp_desc* descs, int32_t n, dbp_plan_t* out) {
         int max_pass = 0;
         for (int i : sig) max_pass = std::max(max_pass, B->sigs[i].n_pass);
         G.item0 = (int)items.size();
+        for (int i : sig) G.work += (double)B->sigs[i].L * B->sigs[i].n_steps;
         for (int lv = 0; lv < max_pass; ++lv)
             for (int i : sig)
                 if (B->sigs[i].n_pass > lv)
@@ -480,6 +490,19 @@ dbp_status dbp_plan_batch(const dbp_desc* descs, int32_t n, dbp_plan_t* out) {
     }
     if (st == DBP_OK && hipMemset(B->d_err, 0, sizeof(int)) != hipSuccess) st = DBP_ERR_HIP;
     if (st == DBP_OK && hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking) != hipSuccess) st = DBP_ERR_HIP;
+    // groups run concurrently in the graph: the persistent launches of the other kernel
+    // variants fill the CUs that one variant's drained queue leaves idle
+    std::stable_sort(B->groups.begin(), B->groups.end(),
+                     [](const BatchGroup& x, const BatchGroup& y) { return x.work > y.work; });
+    if (st == DBP_OK && hipEventCreateWithFlags(&B->ev_fork, hipEventDisableTiming) != hipSuccess) st = DBP_ERR_HIP;
+    for (size_t gi = 1; gi < B->groups.size() && st == DBP_OK; ++gi) {
+        hipStream_t q = nullptr;
+        hipEvent_t e = nullptr;
+        if (hipStreamCreateWithFlags(&q, hipStreamNonBlocking) != hipSuccess) st = DBP_ERR_HIP;
+        else B->side.push_back(q);
+        if (st == DBP_OK && hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) st = DBP_ERR_HIP;
+        else if (st == DBP_OK) B->ev_join.push_back(e);
+    }
     if (st != DBP_OK) {
         dbp_destroy(p);
         return st;
@@ -540,7 +563,14 @@ dbp_status dbp_backprop_batch(dbp_plan_t p, const void* in_packed, void* out_pac
                                      B->cap) == hipSuccess;
         // in place: every pass-0 block must read the untouched input, so stage it first
         if (ok && inplace) ok = launch_copy(ws1, (const float2*)in_packed, B->total, B->cap) == hipSuccess;
+        // DBP_BATCH_SERIAL=1: the groups one after another on one stream (for comparison)
+        const char* ser = std::getenv("DBP_BATCH_SERIAL");
+        const bool serial = ser && ser[0] == '1';
+        if (ok && !serial && B->groups.size() > 1) ok = hipEventRecord(B->ev_fork, B->cap) == hipSuccess;
         for (size_t gi = 0; gi < B->groups.size() && ok; ++gi) {
+            hipStream_t q = (serial || gi == 0) ? B->cap : B->side[gi - 1];
+            if (q != B->cap) ok = hipStreamWaitEvent(q, B->ev_fork, 0) == hipSuccess;
+            if (!ok) break;
             const BatchGroup& G = B->groups[gi];
             BatchArgs a{};
             a.in = inplace ? ws1 : (const float2*)in_packed;
@@ -558,7 +588,10 @@ dbp_status dbp_backprop_batch(dbp_plan_t p, const void* in_packed, void* out_pac
             a.tw = G.d_tw;
             a.taps = B->d_taps;
             a.spin_limit = 1LL << 18;          // about 0.25 s per wait at ~1 us per poll
-            ok = G.fn(a, G.grid, B->cap) == hipSuccess;
+            ok = G.fn(a, G.grid, q) == hipSuccess;
+            if (ok && q != B->cap)
+                ok = hipEventRecord(B->ev_join[gi - 1], q) == hipSuccess &&
+                     hipStreamWaitEvent(B->cap, B->ev_join[gi - 1], 0) == hipSuccess;
         }
         const hipError_t ec = hipStreamEndCapture(B->cap, &graph);
         if (!ok || ec != hipSuccess || !graph) {

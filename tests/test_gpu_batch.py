@@ -160,3 +160,19 @@ def test_batch_kernel_reproduces_the_pass_kernel_on_1024_point_blocks(dbp):
         assert np.array_equal(y[i].view(np.float32), yp.view(np.float32))
         ref, ns = oracle_one(xs[i], w, (1024, 256, 3))
         assert field_err(y[i].astype(np.complex128), ref) <= 1e-5
+
+
+def test_concurrent_groups_equal_serial_groups(dbp, monkeypatch):
+    # the kernel-variant groups (SSFM, ESSFM with 9 and with other tap counts) run as parallel
+    # branches of the graph; run one after another instead they give the same bits
+    work = small_work(3, 12)
+    outs = []
+    for serial in ("1", "0"):
+        monkeypatch.setenv("DBP_BATCH_SERIAL", serial)
+        bp = dbp.plan_batch(descs_for(dbp, work))
+        y = bp.backprop(bp.pack(fields_for(work, 3)))
+        torch.cuda.synchronize()
+        assert bp.status() == 0
+        outs.append(y.clone())
+        bp.close()
+    assert torch.equal(torch.view_as_real(outs[0]), torch.view_as_real(outs[1]))
