@@ -21,10 +21,10 @@
 namespace dbp {
 
 constexpr int FT_THREADS = 256;
-constexpr int FT_SPAN = 1024;     // FIR outputs per tile (the tile's samples and their halo)
+constexpr int FT_SPAN = 768;      // FIR outputs per tile (the tile's samples and their halo)
 constexpr int FT_MAXH = 64;       // largest FIR half-width
 constexpr int FT_MAXC = 64;       // largest tap half-width
-constexpr int FR = 4;             // consecutive outputs per thread in the compile-time-tap FIR loops
+constexpr int FR = 3;             // consecutive outputs per thread in the compile-time-tap FIR loops
 static_assert(FT_SPAN == FT_THREADS * FR, "one group of FR outputs per thread");
 
 // Output samples per tile of the forward step (FIR outputs on the tile +-NC) and of
@@ -309,7 +309,7 @@ __global__ __launch_bounds__(FT_THREADS) void fir_adjoint_kernel(FirArgs a) {
                 }
 #pragma unroll
                 for (int r = 0; r < FR; ++r)
-                    if (a0 + base + r < L) gx[p * L + a0 + base + r] = acc[r];
+                    if (base + r < TS && a0 + base + r < L) gx[p * L + a0 + base + r] = acc[r];
             }
         }
     } else
