@@ -142,7 +142,7 @@ def fit_taps(dbp, torch, rx, target, n_fit=100000, iters=8, nc=NC, plan_kw=None,
     return G.symmetric_full(c), info
 
 
-def paper_arrangement(dbp, torch, rx, sym, target, sweep, reps=20):
+def paper_arrangement(dbp, torch, rx, sym, target, sweep, reps=20, taps9=None):
     """The experiment's own arrangement (Sec. IV): ESSFM with one step for the whole 40-span
     link and Nc = 32 (65 taps, fitted like the 9-tap case) against SSFM with steps over two
     spans (20 steps for the link) and over one span; geometry from the planner.  Times on
@@ -162,6 +162,39 @@ def paper_arrangement(dbp, torch, rx, sym, target, sweep, reps=20):
                      "evm_db_by_launch_dbm": {f"{pw:+.0f}": round(e[name], 3) for pw, e in sweep.items()}}
     best = {k: max(sweep, key=lambda pw: -sweep[pw][k]) for k in ("essfm_1_step_link_nc32", "ssfm_1_per_2_spans")}
     res["best_launch_dbm"] = {k: v for k, v in best.items()}
+    res["measured_geometry"] = measured_geometry(dbp, torch, rx, taps, taps9, reps=reps)
+    return res
+
+
+def measured_geometry(dbp, torch, rx, taps_link, taps9=None, reps=20):
+    """Single-plan geometry from timing (DBP_FLAG_TUNE) against the analytic model, for the
+    experiment's arrangements (Sec. III-IV: N = 8M and overlap >= M lets one pass cover the
+    whole link): SSFM with one step per two spans -- the model's choice, the planner's timed
+    choice, and the whole link in one 8192-point pass -- and the one-step ESSFM (N_c = 32)."""
+    b2 = siggen.beta2_ps2_km()
+    out = torch.empty_like(rx)
+    res = {}
+
+    def timed(name, **kw):
+        t0 = time.perf_counter()
+        p = dbp.plan(N, SPANS, 1, beta2_ps2_km=b2, **kw)
+        plan_s = time.perf_counter() - t0
+        ms, _ = time_dbp(torch, p, rx, out, p.workspace(), 3, reps)
+        res[name] = {"geometry": [p.block, p.overlap, p.steps_per_pass], "passes": p.n_passes,
+                     "ms": round(ms, 4), "plan_s": round(plan_s, 3)}
+        p.close()
+
+    timed("ssfm_1_per_2_spans_model", spans_per_step=2)
+    timed("ssfm_1_per_2_spans_tuned", spans_per_step=2, tune=True)
+    sm = np.pi * abs(b2) * 160.0 * siggen.FS_THZ ** 2         # spread per side of one 160 km step
+    o1 = 2 * int(np.ceil(20 * sm + 16))
+    timed("ssfm_1_per_2_spans_single_pass", spans_per_step=2, block=8192, overlap=o1, steps_per_pass=20)
+    timed("essfm_1_step_link_nc32_model", spans_per_step=SPANS, taps=taps_link)
+    timed("essfm_1_step_link_nc32_tuned", spans_per_step=SPANS, taps=taps_link, tune=True)
+    if taps9 is not None:
+        timed("essfm_1_per_span_model", taps=taps9)
+        timed("essfm_1_per_span_tuned", taps=taps9, tune=True)
+    log("measured geometry " + json.dumps(res))
     return res
 
 
@@ -868,7 +901,7 @@ def main():
                     help="with --hbm-only: one case (e.g. k1_nb512), 2 + 10 launches (for counter runs)")
     ap.add_argument("--hbm-variant", default="per_block", choices=("per_block", "stream"),
                     help="with --hbm-case: the per-block kernel (the planner's default) or the streaming twin")
-    ap.add_argument("--only", default=None, choices=("precision", "gradient", "batch"),
+    ap.add_argument("--only", default=None, choices=("precision", "gradient", "batch", "geometry"),
                     help="run one secondary workload alone and print its JSON (for profiler runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a plain 1 GiB device copy three times and exit (counter calibration)")
@@ -892,6 +925,14 @@ def main():
         taps = siggen.symmetric_taps(siggen.rng(1, 0, 7), NC)
         print(json.dumps(hbm_working_set(dbp, torch, rx, taps, only=args.hbm_case,
                                          only_variant=args.hbm_variant)), flush=True)
+        return
+    if args.only == "geometry":
+        rx, _ = gpu_field(dbp, torch, P_DBM)
+        target = dbp.plan(N, SPANS, 20, block=BLOCK, overlap=OVERLAP, beta2_ps2_km=b2).backprop(rx)
+        link, _ = fit_taps(dbp, torch, rx, target, nc=32, plan_kw=dict(n_spans=SPANS, steps_per_span=1,
+                                                                     spans_per_step=SPANS))
+        taps9, _ = fit_taps(dbp, torch, rx, target)
+        print(json.dumps(measured_geometry(dbp, torch, rx, link, taps9)), flush=True)
         return
     if args.only:
         fn = {"precision": precision_workload, "gradient": grad_workload, "batch": batch_workload}[args.only]
@@ -958,7 +999,7 @@ def main():
         extras["receiver"] = {f"chunk_{cb}_blocks": receiver_workload(dbp, torch, rx, taps, chunk_blocks=cb)
                               for cb in (64, 336)}
         log("receiver mode " + json.dumps(extras["receiver"]))
-        extras["paper_arrangement"] = paper_arrangement(dbp, torch, rx, sym, target, sweep)
+        extras["paper_arrangement"] = paper_arrangement(dbp, torch, rx, sym, target, sweep, taps9=taps)
         log("paper arrangement " + json.dumps(extras["paper_arrangement"]))
         extras["paper_context"] = paper_context(extras["paper_arrangement"], ms_e, ms_s)
         extras["evm_vs_launch_power_db"] = {

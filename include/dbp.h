@@ -87,6 +87,7 @@ typedef enum dbp_precision {
 #define DBP_FLAG_FORWARD 0x1u   /* physical direction (forward propagation) */
 #define DBP_FLAG_WHOLE   0x2u   /* one circular block of the whole signal */
 #define DBP_FLAG_GRAD_SPARSE 0x4u  /* FIR gradient: checkpoint every 8th step only */
+#define DBP_FLAG_TUNE    0x8u   /* measured geometry: time candidates at plan creation */
 
 typedef struct dbp_desc {
     int32_t n_pol;            /* 1 or 2 */
@@ -136,7 +137,18 @@ void dbp_desc_init(dbp_desc* d);
 
 /* Create a plan: validate, build the step schedule in FP64, choose the
  * geometry, build the dispersion and twiddle tables and copy them to the
- * current HIP device.  The plan owns its device tables.  Returns
+ * current HIP device.  The plan owns its device tables.  With block = 0 the
+ * geometry comes from an analytic cost per sample (overlap inflation times
+ * FFT depth and per-pass cost; O the smallest overlap covering k steps, Sec. III);
+ * with DBP_FLAG_TUNE (FFT steps, block = 0, not DBP_FLAG_WHOLE or BF16X3) the
+ * planner instead times candidate geometries on a zero signal of the plan's
+ * own size and batch -- for every block size the model's best step count per
+ * pass and the largest one that fits (fewest passes; at large blocks the
+ * whole link in one pass, the paper's arrangement) -- each as a full
+ * backpropagation (one warm-up and three timed runs on a private stream,
+ * synchronously, with temporary buffers of three states), and keeps the
+ * fastest; DBP_AUTOTUNE_LOG names a file that receives one JSON line per
+ * candidate.  dbp_plan_geometry reports the choice.  Returns
  * DBP_ERR_INVALID_ARG for an invalid descriptor (no device work done),
  * DBP_ERR_UNSUPPORTED for a geometry without a kernel, DBP_ERR_HIP or
  * DBP_ERR_OOM if the device upload fails.  *out is NULL on error. */

@@ -145,7 +145,8 @@ dbp_status validate(const dbp_desc* d) {
         if (!finite(d->fir_band_thz) || d->fir_band_thz < 0) return DBP_ERR_INVALID_ARG;
     }
     if (d->precision < DBP_FP32 || d->precision > DBP_BF16X3) return DBP_ERR_INVALID_ARG;
-    if (d->flags & ~(DBP_FLAG_FORWARD | DBP_FLAG_WHOLE | DBP_FLAG_GRAD_SPARSE)) return DBP_ERR_INVALID_ARG;
+    if (d->flags & ~(DBP_FLAG_FORWARD | DBP_FLAG_WHOLE | DBP_FLAG_GRAD_SPARSE | DBP_FLAG_TUNE))
+        return DBP_ERR_INVALID_ARG;
     if (d->steps_per_pass < 0) return DBP_ERR_INVALID_ARG;
     if (d->spans_per_step < 0) return DBP_ERR_INVALID_ARG;
     if (d->spans_per_step > 1 && (d->steps_per_span != 1 || d->n_spans % d->spans_per_step != 0))
@@ -209,6 +210,27 @@ static int max_k(const std::vector<double>& b, double fs, int nc, int halo) {
     return (int)std::max<long long>(1, std::min<long long>(k, (long long)b.size()));
 }
 
+// Modelled chip time per output sample and step of a k-step pass on Nb-point
+// blocks with overlap O: Nb/(Nb-O) * (a + p/k), where a (per step) and p (per
+// pass) are picoseconds per block sample, fitted to full-chip timings of the
+// pass kernels on MI355X (2^22-sample signals, ESSFM and SSFM): the 512-point
+// one-wave kernels are the cheapest per step; beyond 2048 points the blocks
+// need 8-16 values per thread and far more time per sample (8192: ~25 ps per
+// step against ~3-5 ps), which the FFT's log2 Nb alone does not capture.
+double model_cost(int nb, int o, int k) {
+    double a, p;
+    switch (nb) {
+        case 256: a = 3.0; p = 2.7; break;
+        case 512: a = 2.7; p = 2.5; break;
+        case 1024: a = 4.0; p = 3.3; break;
+        case 2048: a = 5.3; p = 6.0; break;
+        case 4096: a = 6.4; p = 14.0; break;
+        case 8192: a = 25.0; p = 40.0; break;
+        default: a = 60.0; p = 90.0; break;
+    }
+    return (double)nb / (nb - o) * (a + p / k);
+}
+
 int balance_k(int ns, int kmax) {
     const int passes = (ns + kmax - 1) / kmax;
     return (ns + passes - 1) / passes;
@@ -244,8 +266,7 @@ dbp_status choose_geometry(const dbp_desc* d, const std::vector<double>& b, Geom
         g.k = d->steps_per_pass > 0 ? std::min(d->steps_per_pass, ns)
                                     : balance_k(ns, max_k(b, d->fs_thz, nc, d->overlap / 2));
     } else {
-        // cost per sample and step ~ Nb/(Nb-O) * (log2 Nb + 6 + 12/k), O the smallest
-        // overlap covering k steps
+        // measured cost per sample and step (model_cost), O the smallest overlap covering k steps
         double best = 1e300;
         double smax = 0;
         for (double v : b) smax = std::max(smax, spread_per_side(v, d->fs_thz, nc));
@@ -255,7 +276,7 @@ dbp_status choose_geometry(const dbp_desc* d, const std::vector<double>& b, Geom
                 int o = 2 * (int)std::ceil(k * smax + kMargin);
                 if (o > nb / 2) break;
                 int kb = balance_k(ns, k);
-                double cost = (double)nb / (nb - o) * (std::log2((double)nb) + 6.0 + 12.0 / kb);
+                double cost = model_cost(nb, o, kb);
                 if (cost < best - 1e-12) {
                     best = cost;
                     g.block = nb;
@@ -547,6 +568,119 @@ static dbp_status choose_stream(Plan* p, const KernelEntry* ke, int n_tables) {
     return DBP_OK;
 }
 
+// ------------------------------------------------------------------ measured geometry
+
+// Plans whose geometry the planner may choose by timing (DBP_FLAG_TUNE).
+static bool tunable(const dbp_desc* d) {
+    return d->block == 0 && !(d->flags & DBP_FLAG_WHOLE) && d->linear == DBP_LINEAR_FFT &&
+           d->precision != DBP_BF16X3;
+}
+
+struct TuneCand {
+    int nb, o, k;
+};
+
+// The model's own pick, then for every block size the k with the least modelled
+// cost and the largest k that fits (fewest passes), each with the smallest
+// overlap covering its k steps.
+static std::vector<TuneCand> tune_candidates(const dbp_desc* d, const std::vector<double>& b, const Geometry& gm) {
+    const int ns = (int)b.size();
+    const int nc = d->method == DBP_ESSFM ? (d->n_taps - 1) / 2 : 0;
+    double smax = 0;
+    for (double v : b) smax = std::max(smax, spread_per_side(v, d->fs_thz, nc));
+    std::vector<TuneCand> out{{gm.block, gm.overlap, gm.k}};
+    auto add = [&](TuneCand c) {
+        for (const TuneCand& e : out)
+            if (e.nb == c.nb && e.o == c.o && e.k == c.k) return;
+        out.push_back(c);
+    };
+    for (int nb = 256; nb <= std::min<long long>(max_block(d->n_pol), d->n_samples); nb *= 2) {
+        TuneCand best{0, 0, 0}, most{0, 0, 0};
+        double best_cost = 1e300;
+        for (int k = 1; k <= ns; ++k) {
+            if (2 * (int)std::ceil(k * smax + kMargin) > nb / 2) break;
+            const int kb = balance_k(ns, k);
+            const int o = 2 * (int)std::ceil(kb * smax + kMargin);
+            const double cost = model_cost(nb, o, kb);
+            if (cost < best_cost - 1e-12) {
+                best_cost = cost;
+                best = {nb, o, kb};
+            }
+            most = {nb, o, kb};
+        }
+        if (best.nb) add(best);
+        if (most.nb) add(most);
+    }
+    return out;
+}
+
+// Time every candidate as a full backpropagation of a zero signal of the plan's
+// size (one warm-up, three timed runs) and return the fastest as an explicit
+// geometry (DBP_FLAG_TUNE cleared).
+static dbp_status tune_geometry(const dbp_desc* d, dbp_desc* chosen) {
+    std::vector<double> b, phi;
+    build_schedule(d, b, phi);
+    Geometry gm;
+    dbp_status st = choose_geometry(d, b, gm);
+    if (st != DBP_OK) return st;
+    const std::vector<TuneCand> cands = tune_candidates(d, b, gm);
+    *chosen = *d;
+    chosen->flags &= ~DBP_FLAG_TUNE;
+    chosen->block = gm.block;
+    chosen->overlap = gm.overlap;
+    chosen->steps_per_pass = gm.k;
+    const size_t state = (size_t)d->batch * d->n_pol * (size_t)d->n_samples * sizeof(float2);
+    void *in = nullptr, *outb = nullptr, *ws = nullptr;
+    hipStream_t s = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    st = DBP_ERR_HIP;
+    if (hipMalloc(&in, state) == hipSuccess && hipMalloc(&outb, state) == hipSuccess &&
+        hipMalloc(&ws, 2 * state) == hipSuccess && hipMemset(in, 0, state) == hipSuccess &&
+        hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess && hipEventCreate(&e0) == hipSuccess &&
+        hipEventCreate(&e1) == hipSuccess) {
+        st = DBP_OK;
+        float best = 1e30f;
+        const char* log = std::getenv("DBP_AUTOTUNE_LOG");
+        for (const TuneCand& c : cands) {
+            dbp_desc cd = *chosen;
+            cd.block = c.nb;
+            cd.overlap = c.o;
+            cd.steps_per_pass = c.k;
+            dbp_plan_t p = nullptr;
+            if (dbp_plan(&cd, &p) != DBP_OK) continue;
+            float ms = -1.f;
+            bool ok = dbp_backprop(p, in, outb, nullptr, nullptr, ws, 2 * state, s) == DBP_OK &&
+                      hipEventRecord(e0, s) == hipSuccess;
+            for (int r = 0; r < 3 && ok; ++r) ok = dbp_backprop(p, in, outb, nullptr, nullptr, ws, 2 * state, s) == DBP_OK;
+            if (ok && hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess)
+                (void)hipEventElapsedTime(&ms, e0, e1);
+            int passes = 0;
+            (void)dbp_plan_geometry(p, nullptr, nullptr, nullptr, nullptr, &passes);
+            dbp_destroy(p);
+            if (ms <= 0.f) continue;
+            ms /= 3.f;
+            if (log) {
+                if (FILE* f = std::fopen(log, "a")) {
+                    std::fprintf(f, "{\"tune\": 1, \"block\": %d, \"overlap\": %d, \"k\": %d, \"passes\": %d, "
+                                    "\"ms\": %.6g, \"model_pick\": %d}\n",
+                                 c.nb, c.o, c.k, passes, ms, (int)(&c == &cands[0]));
+                    std::fclose(f);
+                }
+            }
+            if (ms < best) {
+                best = ms;
+                *chosen = cd;
+            }
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (s) (void)hipStreamDestroy(s);
+    for (void* ptr : {in, outb, ws})
+        if (ptr) (void)hipFree(ptr);
+    return st;
+}
+
 }  // namespace dbp
 
 extern "C" {
@@ -631,6 +765,11 @@ dbp_status dbp_plan(const dbp_desc* desc, dbp_plan_t* out) {
     *out = nullptr;
     dbp_status st = validate(desc);
     if (st != DBP_OK) return st;
+    if ((desc->flags & DBP_FLAG_TUNE) && tunable(desc)) {
+        dbp_desc chosen;
+        if ((st = tune_geometry(desc, &chosen)) != DBP_OK) return st;
+        return dbp_plan(&chosen, out);
+    }
     if (desc->precision == DBP_BF16X3 && desc->linear == DBP_LINEAR_FIR) return DBP_ERR_UNSUPPORTED;
     Plan* p = new (std::nothrow) Plan();
     if (!p) return DBP_ERR_OOM;

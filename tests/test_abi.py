@@ -264,3 +264,18 @@ def test_loss_head_validation_on_host():
     assert lib.dbp_mse_forward(None, None, None, None, None) == 1
     assert lib.dbp_mse_backward(None, None, None, None) == 1
     lib.dbp_mse_destroy(None)
+
+
+def test_tune_flag_is_accepted_and_host_view_is_the_model():
+    # DBP_FLAG_TUNE is a valid flag; the host-only view reports the analytic model's choice
+    dbp = _lib_or_skip()
+    b2 = siggen.beta2_ps2_km()
+    for kw in [dict(), dict(spans_per_step=2)]:
+        plain = dbp.choose_geometry(dbp.make_desc(262144, 40, 1, beta2_ps2_km=b2, **kw))
+        tuned = dbp.choose_geometry(dbp.make_desc(262144, 40, 1, beta2_ps2_km=b2, tune=True, **kw))
+        assert plain == tuned
+    # the measured cost model keeps 8192-point blocks (several times slower per sample on this
+    # chip) for steps that need them: one step per two spans fits 512-1024-point blocks
+    assert dbp.choose_geometry(dbp.make_desc(262144, 40, 1, beta2_ps2_km=b2, spans_per_step=2))[0] <= 1024
+    assert dbp.choose_geometry(dbp.make_desc(262144, 40, 1, beta2_ps2_km=b2, spans_per_step=40,
+                                             taps=np.ones(65, np.float32)))[0] == 4096

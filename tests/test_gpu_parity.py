@@ -337,3 +337,29 @@ def test_essfm_with_a_one_sample_shift_filter_matches_oracle(dbp):
     print(f"one-sample-shift taps: rel L2 {err:.2e} (against the mirrored filter {rel_l2(y, mirrored):.2e})")
     assert err <= 1e-5
     assert rel_l2(y, mirrored) > 100 * err
+
+
+@pytest.mark.parametrize("m,taps_nc", [(1, 4), (2, None)])
+def test_tuned_geometry_is_the_fastest_candidate_and_matches_oracle(dbp, tmp_path, monkeypatch, m, taps_nc):
+    """DBP_FLAG_TUNE: every candidate geometry is timed (one JSON line each); the plan keeps
+    the fastest, and its output is the oracle's cascade in that geometry."""
+    log = tmp_path / "tune.jsonl"
+    monkeypatch.setenv("DBP_AUTOTUNE_LOG", str(log))
+    n = 65536
+    taps = None if taps_nc is None else siggen.symmetric_taps(siggen.rng(1, 60 + m, 9), taps_nc)
+    x, _ = received(1, 60 + m, 2, n, 2.0, 16, 4)
+    p = dbp.plan(n, 16, 1, spans_per_step=m, taps=taps, beta2_ps2_km=B2, tune=True)
+    cands = [json.loads(line) for line in open(log) if '"tune"' in line]
+    assert len(cands) >= 2 and sum(c["model_pick"] for c in cands) == 1
+    best = min(cands, key=lambda c: c["ms"])
+    assert (p.block, p.overlap, p.steps_per_pass) == (best["block"], best["overlap"], best["k"])
+    y = _from_gpu(p.backprop(_to_gpu(x)), x.shape)
+    t = None if taps is None else np.asarray(taps, np.float32).astype(np.float64)
+    steps = R.schedule(16, 80.0, 1, B2, siggen.GAMMA_W_KM, siggen.ALPHA_DB_KM, taps=t, spans_per_step=m)
+    ref = R.run_blocked(x, steps, FS, p.block, p.overlap, p.steps_per_pass)
+    err = field_err(y, ref)
+    print(f"tuned m={m}: {len(cands)} candidates, chose Nb={p.block} O={p.overlap} k={p.steps_per_pass} "
+          f"({best['ms']:.4f} ms; model pick "
+          f"{[(c['block'], c['overlap'], c['k'], round(c['ms'], 4)) for c in cands if c['model_pick']]}): rel L2 {err:.3e}")
+    assert err <= 1e-5
+    p.close()
