@@ -49,6 +49,10 @@
  *            DBP_FORCE_SPLIT=0|1 polarization-split blocks off / on;
  *            DBP_STREAM=0|1 the streaming (resident-grid) pass kernel off / on
  *            where one is built, DBP_STREAM_GRID=n its grid (a multiple of 8).
+ *   Faults   DBP_FAULT_INJECT="<tag>:<n>" (tests of the cleanup paths): the
+ *            library's n-th device allocation counted since the tag last
+ *            changed fails as out of memory; the call then returns
+ *            DBP_ERR_OOM (or DBP_ERR_HIP) having released what it allocated.
  */
 #ifndef DBP_H
 #define DBP_H
@@ -427,8 +431,9 @@ dbp_status dbp_mse_backward(dbp_mse_t mse, const float* grad_loss, void* grad_z,
 /* Release (NULL is a no-op); no call on it may still be running. */
 void dbp_mse_destroy(dbp_mse_t mse);
 
-/* Short static description of a status code. */
-const char* dbp_status_string(dbp_status s);
+/* Short static description of a status code; any value is accepted ("unknown
+ * status" for values that are not a dbp_status). */
+const char* dbp_status_string(int32_t s);
 
 /* Library version, e.g. 0x000100 for 0.1.0. */
 int32_t dbp_version(void);

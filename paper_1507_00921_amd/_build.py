@@ -62,5 +62,64 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
     return LIB
 
 
+# Host code (planner, schedule, geometry, FIR design, handles and their error paths) checked
+# by AddressSanitizer and UndefinedBehaviorSanitizer: these translation units get the
+# sanitizers on their host pass only (-Xarch_host before every host-only flag; the GPU code is
+# compiled as usual), the kernel-only units are taken from the regular build.
+SANITIZED = ["dbp.hip", "batch.hip", "rx.hip", "rxdsp.hip", "mse.hip"]
+SAN_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+             "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer",
+             "-Xarch_host", "-g"]
+SANDIR = os.path.join(LIBDIR, "san")
+DRIVER_SRC = os.path.join(ROOT, "tests", "sanitize", "host_driver.cpp")
+
+
+def _sources_hash(extra=()):
+    import hashlib
+    h = hashlib.sha256()
+    names = sorted(os.listdir(CSRC))
+    for n in names:
+        with open(os.path.join(CSRC, n), "rb") as f:
+            h.update(n.encode() + f.read())
+    for path in [os.path.join(INCLUDE, "dbp.h"), DRIVER_SRC, *extra]:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    h.update(" ".join(HIPCC_FLAGS + SAN_FLAGS).encode())
+    return h.hexdigest()
+
+
+def build_sanitized(verbose: bool = False, jobs: int = 8) -> str:
+    """Build lib/san/libdbp_san.so (host code sanitized) and the host driver that exercises it;
+    returns the driver's path.  Rebuilt only when a source changed."""
+    from concurrent.futures import ThreadPoolExecutor
+    os.makedirs(SANDIR, exist_ok=True)
+    driver = os.path.join(SANDIR, "host_driver")
+    stamp = os.path.join(SANDIR, "stamp")
+    digest = _sources_hash()
+    if os.path.exists(driver) and os.path.exists(stamp) and open(stamp).read() == digest:
+        return driver
+    cc = hipcc()
+    objdir = os.path.join(SANDIR, "obj")
+    os.makedirs(objdir, exist_ok=True)
+    jobs_list = []
+    for src in SOURCES:
+        obj = os.path.join(objdir, src.replace(".hip", ".o"))
+        flags = HIPCC_FLAGS + (SAN_FLAGS if src in SANITIZED else [])
+        jobs_list.append((obj, [cc, *flags, "-I", INCLUDE, "-I", CSRC, "-c", os.path.join(CSRC, src), "-o", obj]))
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        list(ex.map(lambda j: _run(j[1], verbose), jobs_list))
+    lib = os.path.join(SANDIR, "libdbp_san.so")
+    _run([cc, "--offload-arch=gfx950", "-shared", "-fPIC", *[o for o, _ in jobs_list], "-o", lib], verbose)
+    clangxx = os.path.join(os.path.dirname(cc), "..", "llvm", "bin", "clang++")
+    if not os.path.exists(clangxx):
+        clangxx = "/opt/rocm/llvm/bin/clang++"
+    _run([clangxx, "-std=c++17", "-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+          "-fno-omit-frame-pointer", "-I", INCLUDE, DRIVER_SRC, "-L", SANDIR, "-ldbp_san",
+          "-Wl,-rpath," + SANDIR, "-o", driver], verbose)
+    with open(stamp, "w") as f:
+        f.write(digest)
+    return driver
+
+
 if __name__ == "__main__":
     print(build(verbose=True))

@@ -12,6 +12,7 @@
 #include <tuple>
 #include <vector>
 
+#include "alloc.hpp"
 #include "batch_registry.hpp"
 #include "dbp.h"
 #include "plan.hpp"
@@ -76,10 +77,10 @@ static dbp_status measure_cost(int npol, int nt, bool p64, int nb, Cost& out) {
     const size_t bytes = (size_t)npol * L * sizeof(float2);
     dbp_status rc = DBP_ERR_HIP;
     hipStream_t s = nullptr;
-    if (hipMalloc(&d_in, bytes) == hipSuccess && hipMalloc(&d_out, bytes) == hipSuccess &&
-        hipMalloc(&d_h, nb * sizeof(float2)) == hipSuccess && hipMalloc(&d_tw, nb * sizeof(float2)) == hipSuccess &&
-        hipMalloc(&d_st, st.size() * sizeof(StepDev)) == hipSuccess &&
-        hipMalloc(&d_taps, taps.size() * sizeof(float)) == hipSuccess &&
+    if (device_alloc(&d_in, bytes) == hipSuccess && device_alloc(&d_out, bytes) == hipSuccess &&
+        device_alloc(&d_h, nb * sizeof(float2)) == hipSuccess && device_alloc(&d_tw, nb * sizeof(float2)) == hipSuccess &&
+        device_alloc(&d_st, st.size() * sizeof(StepDev)) == hipSuccess &&
+        device_alloc(&d_taps, taps.size() * sizeof(float)) == hipSuccess &&
         hipMemset(d_in, 0, bytes) == hipSuccess &&
         hipMemcpy(d_h, h.data(), nb * sizeof(float2), hipMemcpyHostToDevice) == hipSuccess &&
         hipMemcpy(d_tw, tw.data(), nb * sizeof(float2), hipMemcpyHostToDevice) == hipSuccess &&
@@ -460,7 +461,7 @@ dbp_status dbp_plan_batch(const dbp_desc* descs, int32_t n, dbp_plan_t* out) {
 
     auto upload = [&](void** dptr, const void* src, size_t bytes) -> dbp_status {
         if (bytes == 0) return DBP_OK;
-        hipError_t e = hipMalloc(dptr, bytes);
+        hipError_t e = device_alloc(dptr, bytes);
         if (e == hipErrorOutOfMemory) return DBP_ERR_OOM;
         if (e != hipSuccess) return DBP_ERR_HIP;
         if (src && hipMemcpy(*dptr, src, bytes, hipMemcpyHostToDevice) != hipSuccess) return DBP_ERR_HIP;

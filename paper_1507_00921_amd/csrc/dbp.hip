@@ -12,8 +12,10 @@
 #include <map>
 #include <mutex>
 #include <new>
+#include <string>
 #include <vector>
 
+#include "alloc.hpp"
 #include "dbp.h"
 #include "plan.hpp"
 #include "registry.hpp"
@@ -22,6 +24,30 @@
 #include "mfma_kernel.hpp"
 
 namespace dbp {
+
+// ------------------------------------------------------------------ device allocations
+
+hipError_t device_alloc_raw(void** p, size_t bytes) {
+    if (const char* f = std::getenv("DBP_FAULT_INJECT")) {
+        static std::mutex mu;
+        static std::string tag;
+        static long long count = 0;
+        if (const char* colon = std::strrchr(f, ':')) {
+            const long long n = std::atoll(colon + 1);
+            std::lock_guard<std::mutex> lock(mu);
+            const std::string t(f, (size_t)(colon - f));
+            if (t != tag) {
+                tag = t;
+                count = 0;
+            }
+            if (++count == n) {
+                *p = nullptr;
+                return hipErrorOutOfMemory;
+            }
+        }
+    }
+    return hipMalloc(p, bytes);
+}
 
 // ------------------------------------------------------------------ fixed device scratch
 
@@ -634,8 +660,8 @@ static dbp_status tune_geometry(const dbp_desc* d, dbp_desc* chosen) {
     hipStream_t s = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     st = DBP_ERR_HIP;
-    if (hipMalloc(&in, state) == hipSuccess && hipMalloc(&outb, state) == hipSuccess &&
-        hipMalloc(&ws, 2 * state) == hipSuccess && hipMemset(in, 0, state) == hipSuccess &&
+    if (device_alloc(&in, state) == hipSuccess && device_alloc(&outb, state) == hipSuccess &&
+        device_alloc(&ws, 2 * state) == hipSuccess && hipMemset(in, 0, state) == hipSuccess &&
         hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess && hipEventCreate(&e0) == hipSuccess &&
         hipEventCreate(&e1) == hipSuccess) {
         st = DBP_OK;
@@ -702,7 +728,7 @@ void dbp_desc_init(dbp_desc* d) {
     d->spans_per_step = 1;
 }
 
-const char* dbp_status_string(dbp_status s) {
+const char* dbp_status_string(int32_t s) {
     switch (s) {
         case DBP_OK: return "ok";
         case DBP_ERR_INVALID_ARG: return "invalid argument";
@@ -874,7 +900,7 @@ dbp_status dbp_plan(const dbp_desc* desc, dbp_plan_t* out) {
     }
     auto upload = [&](void** dptr, const void* src, size_t bytes) -> dbp_status {
         if (bytes == 0) return DBP_OK;
-        hipError_t e = hipMalloc(dptr, bytes);
+        hipError_t e = device_alloc(dptr, bytes);
         if (e == hipErrorOutOfMemory) return DBP_ERR_OOM;
         if (e != hipSuccess) return DBP_ERR_HIP;
         if (hipMemcpy(*dptr, src, bytes, hipMemcpyHostToDevice) != hipSuccess) return DBP_ERR_HIP;

@@ -37,6 +37,7 @@
 #include <new>
 #include <vector>
 
+#include "alloc.hpp"
 #include "dbp.h"
 #include "fft.hpp"
 
@@ -329,7 +330,7 @@ dbp_status dbp_mse_create(int64_t n_samples, int32_t n_pol, int32_t batch, const
     const size_t b_ab = al((size_t)ns * l2 * sizeof(float2)), b_res = b_ab;
     const size_t b_R = al((size_t)ns * L * sizeof(float2)), b_part = al((size_t)ns * sizeof(double));
     const size_t bytes = b_tw2 + b_tw4 + b_twl + b_mf + b_ab + b_res + b_R + b_part;
-    hipError_t e = hipMalloc(&m->mem, bytes);
+    hipError_t e = dbp::device_alloc(&m->mem, bytes);
     if (e != hipSuccess) {
         delete m;
         return e == hipErrorOutOfMemory ? DBP_ERR_OOM : DBP_ERR_HIP;

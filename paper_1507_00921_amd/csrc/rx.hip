@@ -18,6 +18,7 @@
 #include <new>
 #include <vector>
 
+#include "alloc.hpp"
 #include "dbp.h"
 #include "plan.hpp"
 #include "rx_launch.hpp"
@@ -138,7 +139,7 @@ dbp_status dbp_rx_create(const dbp_desc* desc, int64_t chunk, dbp_rx_t* out) {
         return DBP_ERR_UNSUPPORTED;
     }
     const size_t bytes = ((size_t)r->P * r->cap + r->fifo_cap) * r->npol * sizeof(float2);
-    hipError_t e = hipMalloc(&r->mem, bytes);
+    hipError_t e = device_alloc(&r->mem, bytes);
     if (e != hipSuccess) {
         dbp_rx_destroy(r);
         return e == hipErrorOutOfMemory ? DBP_ERR_OOM : DBP_ERR_HIP;

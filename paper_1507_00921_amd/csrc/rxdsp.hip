@@ -23,6 +23,7 @@
 #include <new>
 #include <vector>
 
+#include "alloc.hpp"
 #include "dbp.h"
 
 namespace dbp {
@@ -431,7 +432,7 @@ dbp_status dbp_dsp_create(const dbp_dsp_desc* desc, int64_t n_in, dbp_dsp_t* out
     const size_t bytes = al(table_b) + 2 * al(2 * sizeof(float)) + al(2 * s->n_sym * sizeof(float)) +
                          al(2 * nb * sizeof(float)) + al(2 * nb * sizeof(double)) + al(2 * nb * sizeof(int)) +
                          al(gpart_b) + al((size_t)E * sizeof(double2));
-    if (hipMalloc(&s->mem, bytes) != hipSuccess) {
+    if (dbp::device_alloc(&s->mem, bytes) != hipSuccess) {
         delete s;
         return DBP_ERR_OOM;
     }
