@@ -92,6 +92,7 @@ typedef enum dbp_precision {
 #define DBP_FLAG_WHOLE   0x2u   /* one circular block of the whole signal */
 #define DBP_FLAG_GRAD_SPARSE 0x4u  /* FIR gradient: checkpoint every 8th step only */
 #define DBP_FLAG_TUNE    0x8u   /* measured geometry: time candidates at plan creation */
+#define DBP_FLAG_PERSISTENT 0x10u  /* all passes in one resident launch, halos exchanged */
 
 typedef struct dbp_desc {
     int32_t n_pol;            /* 1 or 2 */
@@ -157,6 +158,19 @@ void dbp_desc_init(dbp_desc* d);
  * DBP_ERR_UNSUPPORTED for a geometry without a kernel, DBP_ERR_HIP or
  * DBP_ERR_OOM if the device upload fails.  *out is NULL on error. */
 dbp_status dbp_plan(const dbp_desc* desc, dbp_plan_t* out);
+
+/* DBP_FLAG_PERSISTENT (FFT steps, at least two passes): dbp_backprop runs every pass in
+ * one cooperative launch of one workgroup per block.  A block keeps its samples in
+ * registers from pass to pass and only the samples other windows read cross memory
+ * between passes (as 64-bit value-and-flag words in a plan-owned buffer of
+ * 3 x batch x n_pol x n_blocks x V x 16 bytes, zeroed at creation), instead of the whole
+ * state being written and re-read by one launch per pass.  Results equal the per-pass
+ * launches bit for bit.  Calls on one such plan share that buffer and must not overlap
+ * in time; in-place calls (in == out) use the per-pass launches.  The plan falls back to
+ * per-pass launches where no persistent variant is built (1024-point blocks with four
+ * values per thread are), the blocks cannot all be resident, the device has no
+ * cooperative launch, or a window reads a block more than two dependency hops from it
+ * (tiny signals); dbp_plan_kernel names the kernel used. */
 
 /* Release a plan and its device tables (NULL is a no-op).  The caller must
  * ensure no call using the plan is still running on any stream. */
@@ -279,7 +293,8 @@ dbp_status dbp_batch_geometry(dbp_plan_t plan, int32_t i, int32_t* block, int32_
 dbp_status dbp_backprop_batch(dbp_plan_t plan, const void* in_packed, void* out_packed,
                               void* ws, size_t ws_bytes, void* stream);
 
-/* Synchronous: error flags of the last completed batch run (0: none; bit 0:
+/* Synchronous: error flags of the last completed batch run, or of the last
+ * persistent run of a DBP_FLAG_PERSISTENT plan (0: none; bit 0:
  * a dependency wait exceeded its bound and the block was skipped). */
 dbp_status dbp_batch_status(dbp_plan_t plan, int32_t* flags);
 

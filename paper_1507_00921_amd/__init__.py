@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(_PKG, "lib", "libdbp.so")
 SSFM, ESSFM = 0, 1
 LINEAR_FFT, LINEAR_FIR = 0, 1
 FP32, FP32_FP64PHASE, BF16X3 = 0, 1, 2
-FLAG_FORWARD, FLAG_WHOLE, FLAG_GRAD_SPARSE, FLAG_TUNE = 0x1, 0x2, 0x4, 0x8
+FLAG_FORWARD, FLAG_WHOLE, FLAG_GRAD_SPARSE, FLAG_TUNE, FLAG_PERSISTENT = 0x1, 0x2, 0x4, 0x8, 0x10
 MAX_TAPS = 129
 NOALLOC_SCRATCH_BYTES = 32 << 20    # DBP_NOALLOC_SCRATCH_BYTES
 MAX_FIR = 129
@@ -147,9 +147,11 @@ def make_desc(n_samples: int, n_spans: int, steps_per_span: int = 1, *, n_pol: i
               n_fir: int = 0, fir_band_thz: float = 0.0, linear: int = LINEAR_FFT, block: int = 0,
               overlap: int = 0,
               steps_per_pass: int = 0, precision: int = FP32_FP64PHASE, forward: bool = False,
-              whole: bool = False, spans_per_step: int = 1, grad_sparse: bool = False, tune: bool = False):
+              whole: bool = False, spans_per_step: int = 1, grad_sparse: bool = False, tune: bool = False,
+              persistent: bool = False):
     """Build a Desc.  taps (ESSFM) and fir are host arrays kept alive on the returned object.
-    tune: the planner times candidate geometries on the plan's size and keeps the fastest."""
+    tune: the planner times candidate geometries on the plan's size and keeps the fastest.
+    persistent: all passes in one resident launch (calls on the plan must not overlap)."""
     d = Desc()
     lib().dbp_desc_init(ctypes.byref(d))
     d.n_pol, d.batch, d.n_samples, d.fs_thz = n_pol, batch, n_samples, fs_thz
@@ -180,7 +182,8 @@ def make_desc(n_samples: int, n_spans: int, steps_per_span: int = 1, *, n_pol: i
     d.block, d.overlap, d.steps_per_pass = block, overlap, steps_per_pass
     d.precision = precision
     d.flags = ((FLAG_FORWARD if forward else 0) | (FLAG_WHOLE if whole else 0) |
-               (FLAG_GRAD_SPARSE if grad_sparse else 0) | (FLAG_TUNE if tune else 0))
+               (FLAG_GRAD_SPARSE if grad_sparse else 0) | (FLAG_TUNE if tune else 0) |
+               (FLAG_PERSISTENT if persistent else 0))
     d.spans_per_step = spans_per_step
     d._keep = keep
     return d
@@ -283,6 +286,12 @@ class Plan:
                                 workspace.numel(), _stream_ptr(stream))
         _check(st, "dbp_backprop")
         return out
+
+    def persistent_status(self) -> int:
+        """Error flags of the last persistent run (DBP_FLAG_PERSISTENT plans; synchronous)."""
+        v = c_int32()
+        _check(lib().dbp_batch_status(self._h, ctypes.byref(v)), "dbp_batch_status")
+        return v.value
 
     def backprop_noalloc(self, x, out, taps=None, fir=None, stream=None):
         """Run the plan on x into the caller's out with the library's fixed device scratch as

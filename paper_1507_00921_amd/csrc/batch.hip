@@ -528,7 +528,14 @@ dbp_status dbp_batch_geometry(dbp_plan_t p, int32_t i, int32_t* block, int32_t* 
 }
 
 dbp_status dbp_batch_status(dbp_plan_t p, int32_t* flags) {
-    if (!p || !p->is_batch || !flags) return DBP_ERR_INVALID_ARG;
+    if (!p || !flags) return DBP_ERR_INVALID_ARG;
+    if (!p->is_batch) {
+        if (!p->d_err) return DBP_ERR_INVALID_ARG;
+        int v = 0;
+        if (hipMemcpy(&v, p->d_err, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return DBP_ERR_HIP;
+        *flags = v;
+        return DBP_OK;
+    }
     BatchState* B = (BatchState*)p->batch;
     int v = 0;
     if (hipMemcpy(&v, B->d_err, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return DBP_ERR_HIP;

@@ -22,6 +22,7 @@
 #include "adj_launch.hpp"
 #include "fir_launch.hpp"
 #include "mfma_kernel.hpp"
+#include "persist_launch.hpp"
 
 namespace dbp {
 
@@ -171,7 +172,7 @@ dbp_status validate(const dbp_desc* d) {
         if (!finite(d->fir_band_thz) || d->fir_band_thz < 0) return DBP_ERR_INVALID_ARG;
     }
     if (d->precision < DBP_FP32 || d->precision > DBP_BF16X3) return DBP_ERR_INVALID_ARG;
-    if (d->flags & ~(DBP_FLAG_FORWARD | DBP_FLAG_WHOLE | DBP_FLAG_GRAD_SPARSE | DBP_FLAG_TUNE))
+    if (d->flags & ~(DBP_FLAG_FORWARD | DBP_FLAG_WHOLE | DBP_FLAG_GRAD_SPARSE | DBP_FLAG_TUNE | DBP_FLAG_PERSISTENT))
         return DBP_ERR_INVALID_ARG;
     if (d->steps_per_pass < 0) return DBP_ERR_INVALID_ARG;
     if (d->spans_per_step < 0) return DBP_ERR_INVALID_ARG;
@@ -594,6 +595,90 @@ static dbp_status choose_stream(Plan* p, const KernelEntry* ke, int n_tables) {
     return DBP_OK;
 }
 
+// ------------------------------------------------------------------ persistent pass loop
+
+// Where the window of every block reads samples other blocks own, the published
+// prefix / suffix of each block's centre (pub) and whether every reader of a
+// block is at most two dependency hops from it (the condition under which three
+// exchange slots suffice).  One signal; the batch repeats it.
+static bool persist_geometry(long long L, int nb, int V, int halo, std::vector<int2>& pub) {
+    const int n = (int)((L + V - 1) / V);
+    if (n < 2) return false;
+    pub.assign(n, make_int2(0, 0));
+    std::vector<std::vector<int>> src(n);       // blocks each block reads
+    for (int b = 0; b < n; ++b) {
+        const long long start = (long long)b * V - halo;
+        const int vb = (int)std::min<long long>(V, L - (long long)b * V);
+        for (int pos = 0; pos < nb; ++pos) {
+            const int c = pos - halo;
+            if (c >= 0 && c < vb) continue;
+            long long i = start + pos;
+            i = ((i % L) + L) % L;
+            const int ob = (int)(i / V), oc = (int)(i - (long long)ob * V);
+            const int vo = (int)std::min<long long>(V, L - (long long)ob * V);
+            if (oc < vo / 2) pub[ob].x = std::max(pub[ob].x, oc + 1);
+            else pub[ob].y = std::max(pub[ob].y, vo - oc);
+            if (std::find(src[b].begin(), src[b].end(), ob) == src[b].end()) src[b].push_back(ob);
+        }
+    }
+    // a reader r of block b (b in src[r]) must be within two hops of b: r in src[b], or
+    // r in src[x] for some x in src[b]
+    for (int r = 0; r < n; ++r)
+        for (int b : src[r]) {
+            if (b == r) continue;
+            bool ok = std::find(src[b].begin(), src[b].end(), r) != src[b].end();
+            for (int x : src[b])
+                if (!ok && std::find(src[x].begin(), src[x].end(), r) != src[x].end()) ok = true;
+            if (!ok) return false;
+        }
+    return true;
+}
+
+// Enable the persistent pass loop for a plan that asks for it and qualifies
+// (otherwise the plan keeps its per-pass launches).
+static dbp_status setup_persist(Plan* p) {
+    const dbp_desc* d = &p->desc;
+    if (!(d->flags & DBP_FLAG_PERSISTENT) || d->linear != DBP_LINEAR_FFT || d->precision == DBP_BF16X3 ||
+        p->geo.n_passes < 2 || p->launch_stream)
+        return DBP_OK;
+    const bool fp64 = d->precision != DBP_FP32;
+    const int nt = tap_variant(d->method, d->n_taps);
+    const PersistEntry* pe = find_persist(p->geo.block, p->geo.e, d->n_pol, fp64, nt);
+    if (!pe) return DBP_OK;
+    // the persistent loop runs whole blocks per workgroup: a plan that chose polarization-split
+    // blocks keeps the plain per-block kernel for the calls that fall back (in place)
+    LaunchFn plain = p->geo.split ? find_kernel(p->geo.block, p->geo.e, d->n_pol, fp64, nt, false) : nullptr;
+    if (p->geo.split && !plain) return DBP_OK;
+    int coop = 0, cu = 0;
+    if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, p->device) != hipSuccess || !coop ||
+        hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess)
+        return DBP_OK;
+    const int V = p->geo.block - p->geo.overlap;
+    const long long n_blk = (d->n_samples + V - 1) / V;
+    const long long n_wg = n_blk * d->batch;
+    if ((long long)pe->occ() * cu < n_wg) return DBP_OK;
+    std::vector<int2> pub1;
+    if (!persist_geometry(d->n_samples, p->geo.block, V, p->geo.overlap / 2, pub1)) return DBP_OK;
+    std::vector<int2> pub;
+    for (int s = 0; s < d->batch; ++s) pub.insert(pub.end(), pub1.begin(), pub1.end());
+    const size_t xb_bytes = (size_t)3 * n_wg * d->n_pol * V * 2 * sizeof(unsigned long long);
+    hipError_t e;
+    if ((e = device_alloc(&p->d_xb, xb_bytes)) != hipSuccess || (e = device_alloc(&p->d_pub, pub.size() * sizeof(int2))) != hipSuccess ||
+        (e = device_alloc(&p->d_err, sizeof(int))) != hipSuccess)
+        return e == hipErrorOutOfMemory ? DBP_ERR_OOM : DBP_ERR_HIP;
+    if (hipMemset(p->d_xb, 0, xb_bytes) != hipSuccess || hipMemset(p->d_err, 0, sizeof(int)) != hipSuccess ||
+        hipMemcpy(p->d_pub, pub.data(), pub.size() * sizeof(int2), hipMemcpyHostToDevice) != hipSuccess)
+        return DBP_ERR_HIP;
+    p->launch_persist = (void*)pe->fn;
+    if (plain) {
+        p->geo.split = false;
+        p->launch = (void*)plain;
+    }
+    std::snprintf(p->kernel_name, sizeof(p->kernel_name), "dbp_persist_kernel<%d, %d, %d, %s, %d>", pe->nb, pe->e,
+                  pe->npol, fp64 ? "true" : "false", pe->nt);
+    return DBP_OK;
+}
+
 // ------------------------------------------------------------------ measured geometry
 
 // Plans whose geometry the planner may choose by timing (DBP_FLAG_TUNE).
@@ -926,6 +1011,10 @@ dbp_status dbp_plan(const dbp_desc* desc, dbp_plan_t* out) {
         return st;
     }
     p->h_taps = taps;
+    if ((st = setup_persist(p)) != DBP_OK) {
+        dbp_destroy(p);
+        return st;
+    }
     *out = p;
     return DBP_OK;
 }
@@ -938,6 +1027,9 @@ void dbp_destroy(dbp_plan_t p) {
     if (p->d_taps) (void)hipFree(p->d_taps);
     if (p->d_fir) (void)hipFree(p->d_fir);
     if (p->d_frag) (void)hipFree(p->d_frag);
+    if (p->d_xb) (void)hipFree(p->d_xb);
+    if (p->d_pub) (void)hipFree(p->d_pub);
+    if (p->d_err) (void)hipFree(p->d_err);
     destroy_batch(p);
     delete p;
 }
@@ -1204,6 +1296,22 @@ static dbp_status backprop_passes(Plan* p, const void* in, void* out, const floa
                                       : a.n_wg;
 
     const int P = g.n_passes;
+    if (p->launch_persist && !inplace) {
+        PersistArgs pa{};
+        pa.a = a;
+        pa.a.in = (const float2*)in;
+        pa.a.out = (float2*)out;
+        pa.xb = p->d_xb;
+        pa.pub = p->d_pub;
+        pa.k = g.k;
+        pa.n_steps = g.n_steps;
+        pa.n_passes = P;
+        pa.flag0 = p->flag_next.fetch_add((unsigned)P + 1u);
+        if (pa.flag0 == 0u) pa.flag0 = p->flag_next.fetch_add((unsigned)P + 1u);   // 0 marks unwritten words
+        pa.err = p->d_err;
+        pa.spin_limit = 1LL << 20;
+        return ((PersistLaunchFn)p->launch_persist)(pa, s) == hipSuccess ? DBP_OK : DBP_ERR_HIP;
+    }
     const float2* src = (const float2*)in;
     for (int pass = 0; pass < P; ++pass) {
         float2* dst;

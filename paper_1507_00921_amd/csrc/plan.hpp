@@ -2,6 +2,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <vector>
 
 #include "dbp.h"
@@ -38,6 +39,11 @@ struct dbp_plan_s {
     float2* d_fir = nullptr;         // FIR linear step: [N_s][n_fir]
     void* d_frag = nullptr;          // split-precision DFT constant fragments
     int grid_cap = 0;                // persistent launch width (split-precision kernel), 0: one workgroup per block
+    void* launch_persist = nullptr;  // persistent pass loop (DBP_FLAG_PERSISTENT), used when set
+    unsigned long long* d_xb = nullptr;  // its exchange words [3][n_wg][n_pol][V][2]
+    int2* d_pub = nullptr;           // per block: published prefix / suffix of its centre
+    int* d_err = nullptr;            // set when one of its waits gave up
+    std::atomic<unsigned> flag_next{1};  // flag of the next call's first pass
     char kernel_name[96] = {0};      // the pass-kernel variant, as the profiler names it
     std::vector<float> h_taps;
 
