@@ -381,12 +381,17 @@ dbp_status dbp_dsp_resample(dbp_dsp_t dsp, const void* in, void* out, void* stre
 
 /* Least-squares butterfly taps from the resampled field x2 [2][n_out] and the
  * transmitted symbols sym [2][n_sym] (device): the normal equations are summed
- * on the GPU (per-chunk FP32 sums added in FP64 in a fixed order) and solved on
- * the host in FP64 (LU with partial pivoting); taps [2][2][N] complex64 are
- * written to device memory.  1 <= n_train <= n_sym.  Synchronizes stream (the
- * solve needs the sums); DBP_ERR_UNSUPPORTED if the system is singular. */
+ * on the GPU (per-chunk FP32 sums added in FP64 in a fixed order) and solved
+ * there in FP64 (Gaussian elimination with partial pivoting in one workgroup);
+ * taps [2][2][N] complex64 are written to device memory.  1 <= n_train <= n_sym.
+ * Asynchronous on stream; a singular system leaves NaN taps and sets bit 0 of
+ * dbp_dsp_status. */
 dbp_status dbp_dsp_train(dbp_dsp_t dsp, const void* x2, const void* sym, int64_t n_train, void* taps,
                          void* stream);
+
+/* Synchronous: flags of the last completed training (0: none; bit 0: its system
+ * was singular). */
+dbp_status dbp_dsp_status(dbp_dsp_t dsp, int32_t* flags);
 
 /* y [2][n_sym] = the butterfly with device taps [2][2][N] applied to x2 [2][n_out].
  * Asynchronous on stream. */

@@ -113,6 +113,8 @@ def lib():
         L.dbp_dsp_resample.restype = c_int32
         L.dbp_dsp_train.argtypes = [c_void_p, c_void_p, c_void_p, c_int64, c_void_p, c_void_p]
         L.dbp_dsp_train.restype = c_int32
+        L.dbp_dsp_status.argtypes = [c_void_p, POINTER(c_int32)]
+        L.dbp_dsp_status.restype = c_int32
         L.dbp_dsp_equalize.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
         L.dbp_dsp_equalize.restype = c_int32
         L.dbp_dsp_cpr.argtypes = [c_void_p, c_void_p, c_void_p, c_int64, c_void_p, POINTER(c_int64), c_void_p]
@@ -519,6 +521,12 @@ class ReceiverDsp:
         _check(lib().dbp_dsp_train(self._h, _ptr(x2), _ptr(sym), n_train, _ptr(taps), _stream_ptr(stream)),
                "dbp_dsp_train")
         return taps
+
+    def status(self) -> int:
+        """Flags of the last completed training (bit 0: singular system; synchronous)."""
+        v = c_int32()
+        _check(lib().dbp_dsp_status(self._h, ctypes.byref(v)), "dbp_dsp_status")
+        return v.value
 
     def equalize(self, x2, taps, out=None, stream=None):
         import torch

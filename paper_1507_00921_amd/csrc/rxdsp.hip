@@ -9,6 +9,8 @@
 //   gram_kernel    per chunk of training symbols, every entry of U^H U and U^H s
 //                  (FP32 sums over the chunk's regressors staged in LDS)
 //   gram_reduce    the chunk sums added in FP64, chunk by chunk in order
+//   solve_kernel   one workgroup: the normal equations solved in FP64 (Gaussian
+//                  elimination with partial pivoting), the taps written as complex64
 //   eq_kernel      one symbol (both polarizations) per thread, taps in LDS
 //   cpr_theta      per 256-symbol block and polarization: fourth-power window
 //                  sums from an LDS tile, the phase estimate, its wrapped
@@ -19,7 +21,6 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
-#include <complex>
 #include <new>
 #include <vector>
 
@@ -123,6 +124,106 @@ __global__ __launch_bounds__(THREADS) void gram_kernel(const float2* __restrict_
         }
         out[e] = make_float2(ax, ay);
     }
+}
+
+constexpr int MAX_M = 2 * MAX_TAPS_EQ;   // unknowns of the least-squares butterfly
+
+__device__ __forceinline__ double2 zmul(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 zdiv(double2 a, double2 b) {
+    const double d = b.x * b.x + b.y * b.y;
+    return make_double2((a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d);
+}
+
+// A x = B for the M x M normal matrix and its two right-hand sides (sum = [A row-major |
+// B row-major M x 2], FP64), in the order of the textbook algorithm: for every column the
+// row with the largest |a| at or below the diagonal (the first on ties) is swapped up and
+// eliminated from the rows below, then back substitution.  taps[p M + i] = x[i][p].  A
+// zero pivot sets *flag to 1 and writes NaN taps.
+__global__ __launch_bounds__(THREADS) void solve_kernel(const double2* __restrict__ sum, int M,
+                                                        float2* __restrict__ taps, int* __restrict__ flag) {
+    __shared__ double2 a[MAX_M][MAX_M + 2];
+    __shared__ double2 f[MAX_M];
+    __shared__ double2 x[2][MAX_M];
+    __shared__ int piv;
+    __shared__ int bad;
+    const int t = threadIdx.x, lane = t & 63;
+    const int W = M + 2;
+    for (int e = t; e < M * W; e += THREADS) {
+        const int i = e / W, j = e - i * W;
+        a[i][j] = j < M ? sum[i * M + j] : sum[M * M + i * 2 + (j - M)];
+    }
+    if (t == 0) bad = 0;
+    __syncthreads();
+    for (int col = 0; col < M; ++col) {
+        if (t < 64) {
+            const int i = col + lane;
+            double v = -1.0;
+            if (i < M) v = a[i][col].x * a[i][col].x + a[i][col].y * a[i][col].y;
+            int idx = i;
+            for (int off = 32; off > 0; off >>= 1) {
+                const double ov = __shfl_xor(v, off);
+                const int oi = __shfl_xor(idx, off);
+                if (ov > v || (ov == v && oi < idx)) {
+                    v = ov;
+                    idx = oi;
+                }
+            }
+            if (lane == 0) {
+                piv = idx;
+                if (!(v > 0.0)) bad = 1;
+            }
+        }
+        __syncthreads();
+        if (bad) break;
+        const int pr = piv;
+        if (pr != col)
+            for (int j = col + t; j < W; j += THREADS) {
+                const double2 tmp = a[col][j];
+                a[col][j] = a[pr][j];
+                a[pr][j] = tmp;
+            }
+        __syncthreads();
+        for (int i = col + 1 + t; i < M; i += THREADS) f[i] = zdiv(a[i][col], a[col][col]);
+        __syncthreads();
+        const int rows = M - col - 1, cols = W - col - 1;
+        for (int e = t; e < rows * cols; e += THREADS) {
+            const int i = col + 1 + e / cols, j = col + 1 + e % cols;
+            const double2 m = zmul(f[i], a[col][j]);
+            a[i][j] = make_double2(a[i][j].x - m.x, a[i][j].y - m.y);
+        }
+        __syncthreads();
+    }
+    if (bad) {
+        for (int e = t; e < 2 * M; e += THREADS) taps[e] = make_float2(__builtin_nanf(""), __builtin_nanf(""));
+        if (t == 0) *flag = 1;
+        return;
+    }
+    // back substitution: wave p (p < 2) solves right-hand side p, one row at a time
+    if (t < 128) {
+        const int p = t >> 6;
+        for (int r = M - 1; r >= 0; --r) {
+            double2 acc = make_double2(0.0, 0.0);
+            if (lane > r && lane < M) acc = zmul(a[r][lane], x[p][lane]);
+            for (int off = 32; off > 0; off >>= 1) {
+                acc.x += __shfl_xor(acc.x, off);
+                acc.y += __shfl_xor(acc.y, off);
+            }
+            if (lane == 0) {
+                const double2 b = a[r][M + p];
+                x[p][r] = zdiv(make_double2(b.x - acc.x, b.y - acc.y), a[r][r]);
+            }
+            __syncthreads();
+        }
+    } else {
+        for (int r = M - 1; r >= 0; --r) __syncthreads();
+    }
+    for (int e = t; e < 2 * M; e += THREADS) {
+        const int p = e / M, i = e - p * M;
+        taps[e] = make_float2((float)x[p][i].x, (float)x[p][i].y);
+    }
+    if (t == 0) *flag = 0;
 }
 
 __global__ __launch_bounds__(THREADS) void gram_reduce(const float2* __restrict__ part, int n_chunks, int E,
@@ -335,6 +436,7 @@ struct dbp_dsp_s {
     int* errs = nullptr;           // [2][n_blocks]
     float2* gpart = nullptr;       // normal-equation chunk sums [ceil(n_sym / GRAM_CH)][E]
     double2* gsum = nullptr;       // their FP64 totals [E]
+    int* flag = nullptr;           // bit 0: the last training system was singular
     void* mem = nullptr;
     int device = -1;               // the device current at create, which owns mem
 };
@@ -360,40 +462,6 @@ bool valid(const dbp_dsp_desc* d, long long n_in) {
     const long long n_out = n_in * d->up / d->down;
     if (n_out & 1) return false;
     if (n_in < d->resample_taps || n_out / 2 < 2LL * d->cpr_half_window + 2 || n_out < 2LL * d->eq_taps) return false;
-    return true;
-}
-
-// Solve A x = B (A: m x m, B: m x r, row-major, complex FP64) by LU with partial pivoting.
-bool solve(std::vector<std::complex<double>>& A, std::vector<std::complex<double>>& B, int m, int r) {
-    for (int col = 0; col < m; ++col) {
-        int piv = col;
-        double best = std::abs(A[(size_t)col * m + col]);
-        for (int i = col + 1; i < m; ++i) {
-            const double v = std::abs(A[(size_t)i * m + col]);
-            if (v > best) {
-                best = v;
-                piv = i;
-            }
-        }
-        if (!(best > 0.0)) return false;
-        if (piv != col) {
-            for (int j = 0; j < m; ++j) std::swap(A[(size_t)col * m + j], A[(size_t)piv * m + j]);
-            for (int j = 0; j < r; ++j) std::swap(B[(size_t)col * r + j], B[(size_t)piv * r + j]);
-        }
-        const std::complex<double> dpiv = A[(size_t)col * m + col];
-        for (int i = col + 1; i < m; ++i) {
-            const std::complex<double> f = A[(size_t)i * m + col] / dpiv;
-            if (f == 0.0) continue;
-            for (int j = col; j < m; ++j) A[(size_t)i * m + j] -= f * A[(size_t)col * m + j];
-            for (int j = 0; j < r; ++j) B[(size_t)i * r + j] -= f * B[(size_t)col * r + j];
-        }
-    }
-    for (int i = m - 1; i >= 0; --i)
-        for (int j = 0; j < r; ++j) {
-            std::complex<double> s = B[(size_t)i * r + j];
-            for (int l = i + 1; l < m; ++l) s -= A[(size_t)i * m + l] * B[(size_t)l * r + j];
-            B[(size_t)i * r + j] = s / A[(size_t)i * m + i];
-        }
     return true;
 }
 
@@ -431,7 +499,7 @@ dbp_status dbp_dsp_create(const dbp_dsp_desc* desc, int64_t n_in, dbp_dsp_t* out
     const size_t gpart_b = (size_t)grid_of(s->n_sym, GRAM_CH) * E * sizeof(float2);
     const size_t bytes = al(table_b) + 2 * al(2 * sizeof(float)) + al(2 * s->n_sym * sizeof(float)) +
                          al(2 * nb * sizeof(float)) + al(2 * nb * sizeof(double)) + al(2 * nb * sizeof(int)) +
-                         al(gpart_b) + al((size_t)E * sizeof(double2));
+                         al(gpart_b) + al((size_t)E * sizeof(double2)) + al(sizeof(int));
     if (dbp::device_alloc(&s->mem, bytes) != hipSuccess) {
         delete s;
         return DBP_ERR_OOM;
@@ -454,12 +522,15 @@ dbp_status dbp_dsp_create(const dbp_dsp_desc* desc, int64_t n_in, dbp_dsp_t* out
     s->gpart = (float2*)m;
     m += al(gpart_b);
     s->gsum = (double2*)m;
+    m += al((size_t)E * sizeof(double2));
+    s->flag = (int*)m;
     // windowed sinc of every output phase ph / up, taps k = -K/2 + 1 .. K/2
     std::vector<float> tab((size_t)up * K);
     for (int ph = 0; ph < up; ++ph)
         for (int k = 0; k < K; ++k)
             tab[(size_t)ph * K + k] = (float)kaiser_sinc((double)ph / up - (k - K / 2 + 1), K / 2, desc->kaiser_beta);
-    if (hipMemcpy(s->table, tab.data(), table_b, hipMemcpyHostToDevice) != hipSuccess) {
+    if (hipMemcpy(s->table, tab.data(), table_b, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemset(s->flag, 0, sizeof(int)) != hipSuccess) {
         dbp_dsp_destroy(s);
         return DBP_ERR_HIP;
     }
@@ -500,23 +571,18 @@ dbp_status dbp_dsp_train(dbp_dsp_t s, const void* x2, const void* sym, int64_t n
                        (const float2*)sym, (long long)s->n_sym, (long long)n_train, N, part);
     hipLaunchKernelGGL(gram_reduce, dim3(grid_of(E, THREADS)), dim3(THREADS), 0, st, (const float2*)part, n_chunks, E,
                        sum);
-    std::vector<double2> h(E);
-    hipError_t e = hipGetLastError();
-    if (e == hipSuccess) e = hipMemcpyAsync(h.data(), sum, (size_t)E * sizeof(double2), hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
-    if (e != hipSuccess) return DBP_ERR_HIP;
-    std::vector<std::complex<double>> A((size_t)M * M), B((size_t)M * 2);
-    for (int i = 0; i < M * M; ++i) A[i] = {h[i].x, h[i].y};
-    for (int i = 0; i < M * 2; ++i) B[i] = {h[M * M + i].x, h[M * M + i].y};
-    if (!solve(A, B, M, 2)) return DBP_ERR_UNSUPPORTED;
-    // W[p][q][j] = w_p[q N + j]
-    std::vector<float2> w((size_t)4 * N);
-    for (int p = 0; p < 2; ++p)
-        for (int i = 0; i < M; ++i) w[(size_t)p * M + i] = make_float2((float)B[(size_t)i * 2 + p].real(),
-                                                                       (float)B[(size_t)i * 2 + p].imag());
-    e = hipMemcpyAsync(taps, w.data(), w.size() * sizeof(float2), hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
-    return e == hipSuccess ? DBP_OK : DBP_ERR_HIP;
+    // W[p][q][j] = w_p[q N + j]: solve_kernel writes taps[p M + i] = x_p[i]
+    hipLaunchKernelGGL(solve_kernel, dim3(1), dim3(THREADS), 0, st, (const double2*)sum, M, (float2*)taps, s->flag);
+    return hipGetLastError() == hipSuccess ? DBP_OK : DBP_ERR_HIP;
+}
+
+dbp_status dbp_dsp_status(dbp_dsp_t s, int32_t* flags) {
+    if (!s || !flags) return DBP_ERR_INVALID_ARG;
+    if (!on_device(s)) return DBP_ERR_INVALID_ARG;
+    int v = 0;
+    if (hipMemcpy(&v, s->flag, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return DBP_ERR_HIP;
+    *flags = v;
+    return DBP_OK;
 }
 
 dbp_status dbp_dsp_equalize(dbp_dsp_t s, const void* x2, const void* taps, void* y, void* stream) {

@@ -204,3 +204,21 @@ def test_degenerate_settings_match_oracle(dbp):
     z, _ = d.cpr(y)
     z_ref = D.cpr(host(y), 0)
     assert float(np.max(np.abs(host(z) - z_ref))) <= 1e-4
+
+
+def test_training_flags_a_singular_system(dbp):
+    # all-zero input: the normal matrix is zero, the GPU solve reports it and leaves NaN taps;
+    # a later well-posed training clears the flag
+    d = dbp.receiver_dsp(14625)                 # 16380 samples after resampling, 8190 symbols
+    x2 = torch.zeros(2, d.n_out, dtype=torch.complex64, device="cuda")
+    s = torch.ones(2, d.n_sym, dtype=torch.complex64, device="cuda")
+    taps = d.train(x2, s, 1000)
+    torch.cuda.synchronize()
+    assert d.status() == 1
+    assert torch.isnan(torch.view_as_real(taps)).all()
+    g = torch.Generator(device="cuda").manual_seed(3)
+    x2 = torch.view_as_complex(torch.randn(2, d.n_out, 2, device="cuda", generator=g)).contiguous()
+    taps = d.train(x2, s, 1000)
+    torch.cuda.synchronize()
+    assert d.status() == 0 and torch.isfinite(torch.view_as_real(taps)).all()
+    d.close()
