@@ -406,12 +406,22 @@ def grad_workload_mode(dbp, torch, sparse, reps):
     ws = p.workspace()
     wsg = p.workspace(grad=True)
     ms_f, _ = time_dbp(torch, p, x, out, ws, 1, reps)
-    e0.record()
-    for _ in range(reps):
-        p.backprop_grad(x, gout, taps=taps.detach(), fir=fir.detach(), workspace=wsg)
-    e1.record()
-    torch.cuda.synchronize()
-    ms_b = e0.elapsed_time(e1) / reps
+    td, fd = taps.detach(), fir.detach()
+
+    def timed(fn):
+        fn()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    # the training step's two halves: the forward that keeps the step states, and the
+    # reverse pass from them; and the one-call gradient (forward and reverse) beside them
+    ms_save = timed(lambda: p.backprop_save(x, taps=td, fir=fd, out=out, workspace=wsg))
+    ms_b = timed(lambda: p.backprop_grad_saved(x, out, wsg, gout, taps=td, fir=fd))
+    ms_whole = timed(lambda: p.backprop_grad(x, gout, taps=td, fir=fd, workspace=wsg))
     zz = p.backprop(x)
     e0.record()
     for _ in range(reps):
@@ -425,7 +435,9 @@ def grad_workload_mode(dbp, torch, sparse, reps):
                        f"{mode}, symbol-MSE loss head in the library",
            "loss_head_fwd_bwd_ms": round(ms_loss, 4),
            "fwd_bwd_ms": round(ms_step, 3), "dbp_forward_ms": round(ms_f, 3),
-           "dbp_backward_ms": round(ms_b, 3), "loss": round(float(loss.detach()), 5),
+           "dbp_forward_saving_ms": round(ms_save, 3), "dbp_backward_ms": round(ms_b, 3),
+           "backward_over_forward": round(ms_b / ms_f, 2), "dbp_grad_one_call_ms": round(ms_whole, 3),
+           "loss": round(float(loss.detach()), 5),
            "workspace_mib": round(wsg.numel() / 2**20, 1)}
     p.close()
     head.close()

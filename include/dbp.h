@@ -248,7 +248,9 @@ dbp_status dbp_backprop_noalloc(dbp_plan_t plan, const void* in, void* out, cons
  * be NULL for FFT-step plans, which have no FIR taps).  taps and fir
  * override the plan's parameters as in dbp_backprop.
  *   FIR plans: the forward pass runs once storing the input of every step,
- *     then the adjoint steps run in reverse.  With DBP_FLAG_GRAD_SPARSE, or
+ *     then the adjoint steps run in reverse, each from its step's input and
+ *     output (the output gives the nonlinear substep's intensity and the FIR
+ *     output without evaluating the FIR again).  With DBP_FLAG_GRAD_SPARSE, or
  *     when those N_s states would take more than 4 GiB, it stores every 8th
  *     step's input instead and recomputes each 8-step segment from its
  *     checkpoint before the segment's adjoint steps (less workspace, about
@@ -267,6 +269,24 @@ dbp_status dbp_backprop_grad(dbp_plan_t plan, const void* in, const float* taps,
                              const void* fir, const void* grad_out, void* grad_in,
                              float* grad_taps, void* grad_fir, void* ws, size_t ws_bytes,
                              void* stream);
+
+/* The two halves of dbp_backprop_grad, for callers that run the forward pass
+ * anyway (an autograd forward) and differentiate later: no forward step runs
+ * twice.  dbp_backprop_save computes out = dbp_backprop(in) (out must not
+ * overlap in) and leaves in ws (ws_bytes >= dbp_workspace_size(plan, 1)) what
+ * the reverse pass reads: for FIR plans the checkpointed step inputs, for
+ * FFT-step plans the pass inputs.  dbp_backprop_grad_saved then writes the
+ * gradients of dbp_backprop_grad for upstream grad_out, given the same plan,
+ * in, out, taps and fir, and ws as dbp_backprop_save left it (the reverse pass
+ * overwrites only the parts of ws it recomputes, so it may run again for
+ * another grad_out).  Errors as dbp_backprop_grad; a ws, in or out changed in
+ * between gives wrong gradients, which the library cannot detect. */
+dbp_status dbp_backprop_save(dbp_plan_t plan, const void* in, void* out, const float* taps,
+                             const void* fir, void* ws, size_t ws_bytes, void* stream);
+dbp_status dbp_backprop_grad_saved(dbp_plan_t plan, const void* in, const void* out,
+                                   const float* taps, const void* fir, const void* grad_out,
+                                   void* grad_in, float* grad_taps, void* grad_fir, void* ws,
+                                   size_t ws_bytes, void* stream);
 
 /* Ragged batch: n descriptors (each batch == 1; any mix of lengths, links,
  * methods and taps, same n_pol) planned together.  Signal i occupies

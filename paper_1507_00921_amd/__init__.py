@@ -83,6 +83,12 @@ def lib():
         L.dbp_backprop_grad.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                         c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]
         L.dbp_backprop_grad.restype = c_int32
+        L.dbp_backprop_save.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t,
+                                        c_void_p]
+        L.dbp_backprop_save.restype = c_int32
+        L.dbp_backprop_grad_saved.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                              c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]
+        L.dbp_backprop_grad_saved.restype = c_int32
         L.dbp_plan_batch.argtypes = [POINTER(Desc), c_int32, POINTER(c_void_p)]
         L.dbp_plan_batch.restype = c_int32
         L.dbp_batch_offsets.argtypes = [c_void_p, POINTER(c_int64), c_int32]
@@ -341,6 +347,43 @@ class Plan:
                                      _ptr(gt), _ptr(gf), _ptr(workspace), workspace.numel(),
                                      _stream_ptr(stream))
         _check(st, "dbp_backprop_grad")
+        return gx, gt, gf
+
+    def backprop_save(self, x, taps=None, fir=None, out=None, workspace=None, stream=None):
+        """Forward pass that keeps what the reverse pass needs: returns (out, workspace);
+        pass both, unchanged, to backprop_grad_saved (dbp_backprop_save)."""
+        import torch
+        self._check_field(x, "input")
+        self._check_params(taps, fir)
+        if out is None:
+            out = torch.empty_like(x)
+        self._check_field(out, "output")
+        if workspace is None:
+            workspace = self.workspace(grad=True)
+        st = lib().dbp_backprop_save(self._h, _ptr(x), _ptr(out), _ptr(taps), _ptr(fir), _ptr(workspace),
+                                     workspace.numel(), _stream_ptr(stream))
+        _check(st, "dbp_backprop_save")
+        return out, workspace
+
+    def backprop_grad_saved(self, x, out, workspace, grad_out, taps=None, fir=None, want_input=True,
+                            stream=None):
+        """Reverse pass after backprop_save(x, taps, fir) -> (out, workspace), without running
+        the forward steps again (dbp_backprop_grad_saved); returns as backprop_grad."""
+        import torch
+        self._check_field(x, "input")
+        self._check_field(out, "output")
+        self._check_field(grad_out, "grad_out")
+        self._check_params(taps, fir)
+        ns = self.n_steps
+        gx = torch.empty_like(x) if want_input else None
+        gt = (torch.empty(ns, self.desc.n_taps, dtype=torch.float32, device=x.device)
+              if self.desc.method == ESSFM else None)
+        gf = (torch.empty(ns, self.desc.n_fir, dtype=torch.complex64, device=x.device)
+              if self.desc.linear == LINEAR_FIR else None)
+        st = lib().dbp_backprop_grad_saved(self._h, _ptr(x), _ptr(out), _ptr(taps), _ptr(fir), _ptr(grad_out),
+                                           _ptr(gx), _ptr(gt), _ptr(gf), _ptr(workspace), workspace.numel(),
+                                           _stream_ptr(stream))
+        _check(st, "dbp_backprop_grad_saved")
         return gx, gt, gf
 
 
@@ -666,14 +709,25 @@ def _autograd_function():
         def forward(ctx, x, taps, fir, plan):
             x = x.contiguous()
             ctx.plan = plan
-            ctx.save_for_backward(x, taps, fir)
-            return plan.backprop(x, taps=taps, fir=fir)
+            if plan.workspace_size(grad=True) > 0:
+                # keep the forward's step states for the reverse pass (no forward step reruns)
+                out, ctx.ws = plan.backprop_save(x, taps=taps, fir=fir)
+                ctx.save_for_backward(x, taps, fir, out)
+            else:
+                out = plan.backprop(x, taps=taps, fir=fir)
+                ctx.ws = None
+                ctx.save_for_backward(x, taps, fir, None)
+            return out
 
         @staticmethod
         def backward(ctx, g):
-            x, taps, fir = ctx.saved_tensors
-            gx, gt, gf = ctx.plan.backprop_grad(x, g.contiguous(), taps=taps, fir=fir,
-                                                want_input=ctx.needs_input_grad[0])
+            x, taps, fir, out = ctx.saved_tensors
+            if ctx.ws is not None:
+                gx, gt, gf = ctx.plan.backprop_grad_saved(x, out, ctx.ws, g.contiguous(), taps=taps, fir=fir,
+                                                          want_input=ctx.needs_input_grad[0])
+            else:
+                gx, gt, gf = ctx.plan.backprop_grad(x, g.contiguous(), taps=taps, fir=fir,
+                                                    want_input=ctx.needs_input_grad[0])
             return (gx, gt if ctx.needs_input_grad[1] else None,
                     gf if ctx.needs_input_grad[2] and gf is not None else None, None)
 

@@ -1087,12 +1087,13 @@ static FirGeo fir_geo(const Plan* p) {
 }
 
 // Workspace of the checkpointed gradient: checkpoints 1.., the inputs of the
-// steps 1.. of one segment, two gradient buffers, then the per-tile partials.
+// steps 1.. of one segment, two gradient buffers, the last step's output, then
+// the per-tile partials.
 static size_t grad_ws_bytes(const Plan* p) {
     const FirGeo f = fir_geo(p);
     const size_t state = p->state_bytes();
     const size_t part = (size_t)p->geo.n_steps * f.n_wg * f.width * sizeof(float);
-    return (size_t)(f.n_ckpt - 1 + f.seg - 1 + 2) * state + part;
+    return (size_t)(f.n_ckpt - 1 + f.seg - 1 + 3) * state + part;
 }
 
 // FFT-step plans: geometry of the reverse pass.
@@ -1152,30 +1153,30 @@ static FirArgs fir_args(const Plan* p, int s, const float* taps, const void* fir
 // storing every pass input; then, pass by pass in reverse, every block re-runs
 // its steps from the stored pass input and runs their adjoints, leaving its
 // window gradient for the earlier pass to gather.
-static dbp_status fft_backprop_grad(Plan* p, const void* in, const float* taps, const void* grad_out,
-                                    void* grad_in, float* grad_taps, void* grad_fir, void* ws, size_t ws_bytes,
-                                    void* stream) {
+static dbp_status fft_grad_check(Plan* p, const void* grad_out, void* grad_in, void* grad_fir, void* ws,
+                                 size_t ws_bytes) {
     if (!fft_grad_supported(p)) return DBP_ERR_UNSUPPORTED;
     if (grad_fir) return DBP_ERR_INVALID_ARG;   // no FIR taps in an FFT-step plan
-    const FftGradGeo f = fft_grad_geo(p);
+    const size_t state = p->state_bytes();
     const char* go = (const char*)grad_out;
     const char* gi = (const char*)grad_in;
-    if (grad_in && gi < go + f.state && go < gi + f.state) return DBP_ERR_INVALID_ARG;
+    if (grad_out && grad_in && gi < go + state && go < gi + state) return DBP_ERR_INVALID_ARG;
     if (!ws || ws_bytes < fft_grad_ws_bytes(p)) return DBP_ERR_WORKSPACE;
     int dev = -1;
     if (hipGetDevice(&dev) != hipSuccess) return DBP_ERR_HIP;
     if (dev != p->device) return DBP_ERR_INVALID_ARG;
-    hipStream_t s = (hipStream_t)stream;
+    return DBP_OK;
+}
+
+// Forward passes storing the inputs of passes 1..P-1 in the workspace; with out,
+// the last pass too (its output is not needed by the reverse passes).
+static dbp_status fft_grad_forward(Plan* p, const void* in, void* out, const float* taps, void* ws,
+                                   hipStream_t s) {
+    const FftGradGeo f = fft_grad_geo(p);
     char* w = (char*)ws;
     auto ckpt = [&](int pass) {   // input of pass `pass`
         return pass == 0 ? (const float2*)in : (const float2*)(w + (size_t)(pass - 1) * f.state);
     };
-    float2* xs = (float2*)(w + (size_t)(f.n_passes - 1) * f.state);
-    float2* G[2] = {(float2*)((char*)xs + f.xs), (float2*)((char*)xs + f.xs + f.window)};
-    float* part = (float*)((char*)G[1] + f.window);
-    const float* tp = p->desc.method == DBP_ESSFM ? (taps ? taps : p->d_taps) : nullptr;
-
-    // forward: the inputs of passes 1..P-1
     LaunchFn fn = (LaunchFn)(p->launch_stream ? p->launch_stream : p->launch);
     PassArgs a{};
     a.L = p->desc.n_samples;
@@ -1186,17 +1187,30 @@ static dbp_status fft_backprop_grad(Plan* p, const void* in, const float* taps, 
     a.steps = p->d_steps;
     a.H = p->d_h;
     a.tw = p->d_tw;
-    a.taps = tp;
+    a.taps = p->desc.method == DBP_ESSFM ? (taps ? taps : p->d_taps) : nullptr;
     a.ntaps = p->desc.method == DBP_ESSFM ? p->desc.n_taps : 1;
     const int grid = p->launch_stream ? p->stream_grid : a.n_wg;
-    for (int pass = 0; pass + 1 < f.n_passes; ++pass) {
+    const int last = out ? f.n_passes : f.n_passes - 1;
+    for (int pass = 0; pass < last; ++pass) {
         a.in = ckpt(pass);
-        a.out = (float2*)ckpt(pass + 1);
+        a.out = pass + 1 < f.n_passes ? (float2*)ckpt(pass + 1) : (float2*)out;
         a.s0 = pass * f.k;
         a.ks = std::min(f.k, p->geo.n_steps - a.s0);
         if (fn(a, grid, s) != hipSuccess) return DBP_ERR_HIP;
     }
-    // reverse
+    return DBP_OK;
+}
+
+static dbp_status fft_grad_reverse(Plan* p, const void* in, const float* taps, const void* grad_out,
+                                   void* grad_in, float* grad_taps, void* ws, hipStream_t s) {
+    const FftGradGeo f = fft_grad_geo(p);
+    char* w = (char*)ws;
+    auto ckpt = [&](int pass) {
+        return pass == 0 ? (const float2*)in : (const float2*)(w + (size_t)(pass - 1) * f.state);
+    };
+    float2* xs = (float2*)(w + (size_t)(f.n_passes - 1) * f.state);
+    float2* G[2] = {(float2*)((char*)xs + f.xs), (float2*)((char*)xs + f.xs + f.window)};
+    float* part = (float*)((char*)G[1] + f.window);
     AdjArgs r{};
     r.xs = xs;
     r.kmax = f.k;
@@ -1208,8 +1222,8 @@ static dbp_status fft_backprop_grad(Plan* p, const void* in, const float* taps, 
     r.steps = p->d_steps;
     r.H = p->d_h;
     r.tw = p->d_tw;
-    r.taps = tp;
-    r.ntaps = a.ntaps;
+    r.taps = p->desc.method == DBP_ESSFM ? (taps ? taps : p->d_taps) : nullptr;
+    r.ntaps = p->desc.method == DBP_ESSFM ? p->desc.n_taps : 1;
     r.part = part;
     for (int pass = f.n_passes - 1, i = 0; pass >= 0; --pass, ++i) {
         r.x = ckpt(pass);
@@ -1226,6 +1240,107 @@ static dbp_status fft_backprop_grad(Plan* p, const void* in, const float* taps, 
     if (grad_taps && f.nw &&
         launch_reduce_partials(part, p->geo.n_steps, f.n_wg, f.nw, 0, grad_taps, nullptr, s) != hipSuccess)
         return DBP_ERR_HIP;
+    return DBP_OK;
+}
+
+// FIR-step plans.  Workspace: checkpoints 1.. (the input of every seg-th step),
+// the inputs of the steps 1.. of one segment, two gradient buffers, the output
+// of the last step for dbp_backprop_grad (dbp_backprop_save writes the caller's
+// output instead), then the per-tile partials.
+struct FirWs {
+    char* w;
+    size_t state;
+    int b_seg, b_grad, b_out;
+    float* part;
+    float2* buf(int i) const { return (float2*)(w + (size_t)i * state); }
+};
+
+static FirWs fir_ws(const Plan* p, void* ws) {
+    const FirGeo f = fir_geo(p);
+    FirWs r;
+    r.w = (char*)ws;
+    r.state = p->state_bytes();
+    r.b_seg = f.n_ckpt - 1;
+    r.b_grad = r.b_seg + f.seg - 1;
+    r.b_out = r.b_grad + 2;
+    r.part = (float*)(r.w + (size_t)(r.b_out + 1) * r.state);
+    return r;
+}
+
+static dbp_status fir_grad_check(Plan* p, const void* grad_out, void* grad_in, void* ws, size_t ws_bytes) {
+    if (p->desc.linear != DBP_LINEAR_FIR) return DBP_ERR_UNSUPPORTED;
+    const size_t state = p->state_bytes();
+    const char* go = (const char*)grad_out;
+    const char* gi = (const char*)grad_in;
+    if (grad_out && grad_in && gi < go + state && go < gi + state) return DBP_ERR_INVALID_ARG;
+    if (!ws || ws_bytes < grad_ws_bytes(p)) return DBP_ERR_WORKSPACE;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return DBP_ERR_HIP;
+    if (dev != p->device) return DBP_ERR_INVALID_ARG;
+    return DBP_OK;
+}
+
+// Every step once, keeping the input of every seg-th step (seg = 1: of every step);
+// the last step writes out.
+static dbp_status fir_grad_forward(Plan* p, const void* in, void* out, const float* taps, const void* fir,
+                                   void* ws, hipStream_t s) {
+    const FirGeo f = fir_geo(p);
+    const FirWs W = fir_ws(p, ws);
+    const int ns = p->geo.n_steps;
+    const float2* src = (const float2*)in;
+    int tog = 0;
+    for (int st = 0; st < ns; ++st) {
+        float2* dst = st + 1 == ns               ? (float2*)out
+                      : (st + 1) % f.seg == 0    ? W.buf((st + 1) / f.seg - 1)
+                                                 : W.buf(W.b_seg + (tog ^= 1));
+        FirArgs a = fir_args(p, st, taps, fir);
+        a.x = src;
+        a.z = dst;
+        if (launch_fir_step(p->desc.n_pol, a, s) != hipSuccess) return DBP_ERR_HIP;
+        src = dst;
+    }
+    return DBP_OK;
+}
+
+// Adjoint steps in reverse, each from its input and its output: segment by
+// segment, the inputs of the segment's steps are recomputed from its checkpoint.
+static dbp_status fir_grad_reverse(Plan* p, const void* in, const void* out, const float* taps, const void* fir,
+                                   const void* grad_out, void* grad_in, float* grad_taps, void* grad_fir, void* ws,
+                                   hipStream_t s) {
+    const FirGeo f = fir_geo(p);
+    const FirWs W = fir_ws(p, ws);
+    const int ns = p->geo.n_steps;
+    const int npol = p->desc.n_pol;
+    auto ckpt = [&](int c) { return c == 0 ? (const float2*)in : (const float2*)W.buf(c - 1); };
+    float2* gfinal = grad_in ? (float2*)grad_in : W.buf(W.b_grad + 1);
+    float2* galt = W.buf(W.b_grad + (gfinal == W.buf(W.b_grad + 1) ? 0 : 1));
+    const float2* gcur = (const float2*)grad_out;
+    int r = 0;
+    for (int c = f.n_ckpt - 1; c >= 0; --c) {
+        const int s0 = c * f.seg, len = std::min(f.seg, ns - s0);
+        for (int j = 1; j < len; ++j) {
+            FirArgs a = fir_args(p, s0 + j - 1, taps, fir);
+            a.x = j == 1 ? ckpt(c) : W.buf(W.b_seg + j - 2);
+            a.z = W.buf(W.b_seg + j - 1);
+            if (launch_fir_step(npol, a, s) != hipSuccess) return DBP_ERR_HIP;
+        }
+        for (int j = len - 1; j >= 0; --j, ++r) {
+            FirArgs a = fir_args(p, s0 + j, taps, fir, true);
+            a.x = j == 0 ? ckpt(c) : W.buf(W.b_seg + j - 1);
+            a.zo = j + 1 < len ? W.buf(W.b_seg + j) : (c + 1 < f.n_ckpt ? ckpt(c + 1) : (const float2*)out);
+            a.gz = gcur;
+            float2* gdst = ((ns - 1 - r) % 2 == 0) ? gfinal : galt;
+            a.z = gdst;
+            a.part = W.part + (size_t)(s0 + j) * f.n_wg * f.width;
+            if (launch_fir_adjoint(npol, a, s) != hipSuccess) return DBP_ERR_HIP;
+            gcur = gdst;
+        }
+    }
+    if ((grad_taps && f.nw) || grad_fir) {
+        if (launch_reduce_partials(W.part, ns, f.n_wg, f.nw, p->desc.n_fir, f.nw ? grad_taps : nullptr,
+                                   (float*)grad_fir, s) != hipSuccess)
+            return DBP_ERR_HIP;
+    }
     return DBP_OK;
 }
 
@@ -1364,72 +1479,48 @@ dbp_status dbp_backprop_grad(dbp_plan_t p, const void* in, const float* taps, co
                              const void* grad_out, void* grad_in, float* grad_taps, void* grad_fir,
                              void* ws, size_t ws_bytes, void* stream) {
     if (!p || !in || !grad_out || p->is_batch) return DBP_ERR_INVALID_ARG;
-    if (p->desc.linear == DBP_LINEAR_FFT)
-        return fft_backprop_grad(p, in, taps, grad_out, grad_in, grad_taps, grad_fir, ws, ws_bytes, stream);
-    if (p->desc.linear != DBP_LINEAR_FIR) return DBP_ERR_UNSUPPORTED;
-    const size_t state = p->state_bytes();
-    const char* go = (const char*)grad_out;
-    const char* gi = (const char*)grad_in;
-    if (grad_in && gi < go + state && go < gi + state) return DBP_ERR_INVALID_ARG;
-    const size_t need = grad_ws_bytes(p);
-    if (!ws || ws_bytes < need) return DBP_ERR_WORKSPACE;
-    int dev = -1;
-    if (hipGetDevice(&dev) != hipSuccess) return DBP_ERR_HIP;
-    if (dev != p->device) return DBP_ERR_INVALID_ARG;
     hipStream_t s = (hipStream_t)stream;
-    const FirGeo f = fir_geo(p);
-    const int ns = p->geo.n_steps;
-    const int npol = p->desc.n_pol;
-    char* w = (char*)ws;
-    auto buf = [&](int i) { return (float2*)(w + (size_t)i * state); };
-    // layout: [0, n_ckpt-1) checkpoints 1..; [n_ckpt-1, +seg-1) segment inputs; 2 gradient buffers
-    const int b_seg = f.n_ckpt - 1, b_grad = b_seg + f.seg - 1;
-    float* part = (float*)(w + (size_t)(b_grad + 2) * state);
-    auto ckpt = [&](int c) { return c == 0 ? (const float2*)in : (const float2*)buf(c - 1); };
+    dbp_status st;
+    if (p->desc.linear == DBP_LINEAR_FFT) {
+        if ((st = fft_grad_check(p, grad_out, grad_in, grad_fir, ws, ws_bytes)) != DBP_OK) return st;
+        if ((st = fft_grad_forward(p, in, nullptr, taps, ws, s)) != DBP_OK) return st;
+        return fft_grad_reverse(p, in, taps, grad_out, grad_in, grad_taps, ws, s);
+    }
+    if ((st = fir_grad_check(p, grad_out, grad_in, ws, ws_bytes)) != DBP_OK) return st;
+    float2* out = fir_ws(p, ws).buf(fir_ws(p, ws).b_out);
+    if ((st = fir_grad_forward(p, in, out, taps, fir, ws, s)) != DBP_OK) return st;
+    return fir_grad_reverse(p, in, out, taps, fir, grad_out, grad_in, grad_taps, grad_fir, ws, s);
+}
 
-    // forward with a checkpoint every f.seg steps (1: every step's input; the state after the
-    // last step is not needed)
-    {
-        const float2* src = (const float2*)in;
-        int tog = 0;
-        for (int st = 0; st + 1 < ns; ++st) {
-            float2* dst = ((st + 1) % f.seg == 0) ? buf((st + 1) / f.seg - 1) : buf(b_seg + (tog ^= 1));
-            FirArgs a = fir_args(p, st, taps, fir);
-            a.x = src;
-            a.z = dst;
-            if (launch_fir_step(npol, a, s) != hipSuccess) return DBP_ERR_HIP;
-            src = dst;
-        }
+dbp_status dbp_backprop_save(dbp_plan_t p, const void* in, void* out, const float* taps, const void* fir,
+                             void* ws, size_t ws_bytes, void* stream) {
+    if (!p || !in || !out || p->is_batch) return DBP_ERR_INVALID_ARG;
+    const size_t state = p->state_bytes();
+    const char* ib = (const char*)in;
+    const char* ob = (const char*)out;
+    if (ib < ob + state && ob < ib + state) return DBP_ERR_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    dbp_status st;
+    if (p->desc.linear == DBP_LINEAR_FFT) {
+        if ((st = fft_grad_check(p, nullptr, nullptr, nullptr, ws, ws_bytes)) != DBP_OK) return st;
+        return fft_grad_forward(p, in, out, taps, ws, s);
     }
-    // reverse: recompute each segment's step inputs from its checkpoint, then run its adjoint steps
-    float2* gfinal = grad_in ? (float2*)grad_in : buf(b_grad + 1);
-    const float2* gcur = (const float2*)grad_out;
-    int r = 0;
-    for (int c = f.n_ckpt - 1; c >= 0; --c) {
-        const int s0 = c * f.seg, len = std::min(f.seg, ns - s0);
-        for (int j = 1; j < len; ++j) {
-            FirArgs a = fir_args(p, s0 + j - 1, taps, fir);
-            a.x = j == 1 ? ckpt(c) : buf(b_seg + j - 2);
-            a.z = buf(b_seg + j - 1);
-            if (launch_fir_step(npol, a, s) != hipSuccess) return DBP_ERR_HIP;
-        }
-        for (int j = len - 1; j >= 0; --j, ++r) {
-            FirArgs a = fir_args(p, s0 + j, taps, fir, true);
-            a.x = j == 0 ? ckpt(c) : buf(b_seg + j - 1);
-            a.gz = gcur;
-            float2* gdst = ((ns - 1 - r) % 2 == 0) ? gfinal : buf(b_grad + (gfinal == buf(b_grad + 1) ? 0 : 1));
-            a.z = gdst;
-            a.part = part + (size_t)(s0 + j) * f.n_wg * f.width;
-            if (launch_fir_adjoint(npol, a, s) != hipSuccess) return DBP_ERR_HIP;
-            gcur = gdst;
-        }
+    if ((st = fir_grad_check(p, nullptr, nullptr, ws, ws_bytes)) != DBP_OK) return st;
+    return fir_grad_forward(p, in, out, taps, fir, ws, s);
+}
+
+dbp_status dbp_backprop_grad_saved(dbp_plan_t p, const void* in, const void* out, const float* taps,
+                                   const void* fir, const void* grad_out, void* grad_in, float* grad_taps,
+                                   void* grad_fir, void* ws, size_t ws_bytes, void* stream) {
+    if (!p || !in || !out || !grad_out || p->is_batch) return DBP_ERR_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    dbp_status st;
+    if (p->desc.linear == DBP_LINEAR_FFT) {
+        if ((st = fft_grad_check(p, grad_out, grad_in, grad_fir, ws, ws_bytes)) != DBP_OK) return st;
+        return fft_grad_reverse(p, in, taps, grad_out, grad_in, grad_taps, ws, s);
     }
-    if ((grad_taps && f.nw) || grad_fir) {
-        if (launch_reduce_partials(part, ns, f.n_wg, f.nw, p->desc.n_fir, f.nw ? grad_taps : nullptr,
-                                   (float*)grad_fir, s) != hipSuccess)
-            return DBP_ERR_HIP;
-    }
-    return DBP_OK;
+    if ((st = fir_grad_check(p, grad_out, grad_in, ws, ws_bytes)) != DBP_OK) return st;
+    return fir_grad_reverse(p, in, out, taps, fir, grad_out, grad_in, grad_taps, grad_fir, ws, s);
 }
 
 }  // extern "C"

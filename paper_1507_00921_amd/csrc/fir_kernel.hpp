@@ -28,9 +28,9 @@ constexpr int FR = 3;             // consecutive outputs per thread in the compi
 static_assert(FT_SPAN == FT_THREADS * FR, "one group of FR outputs per thread");
 
 // Output samples per tile of the forward step (FIR outputs on the tile +-NC) and of
-// the adjoint (recomputed FIR outputs on the tile +-(HF + 2 NC)); ntaps = 1 for SSFM.
+// the adjoint (the step output on the tile +-(HF + NC)); ntaps = 1 for SSFM.
 __host__ __device__ constexpr int fir_fwd_tile(int nfir, int ntaps) { return FT_SPAN - (ntaps - 1); }
-__host__ __device__ constexpr int fir_adj_tile(int nfir, int ntaps) { return FT_SPAN - (nfir - 1) - 2 * (ntaps - 1); }
+__host__ __device__ constexpr int fir_adj_tile(int nfir, int ntaps) { return FT_SPAN - (nfir - 1) - (ntaps - 1); }
 
 struct FirArgs {
     const float2* x;        // step input [n_sig][NPOL][L]
@@ -46,6 +46,7 @@ struct FirArgs {
     int ntaps;
     float phi;
     float* part;            // adjoint: per-tile partial gradients [ntaps + 2 nfir][n_wg]
+    const float2* zo;       // adjoint: the step's output [n_sig][NPOL][L]
 };
 
 __device__ __forceinline__ long long wrap(long long i, long long L) {
@@ -201,6 +202,13 @@ __global__ __launch_bounds__(FT_THREADS) void fir_step_kernel(FirArgs a) {
 
 // Adjoint of one step on one tile: g_x[a0 + o] for o < ts, plus this tile's
 // partial sums of dL/dw (owned outputs n in [a0, a0 + TS)) and dL/dh.
+//
+// The step's output z = u exp(-j phi J) is read, not recomputed: |z| = |u|, so
+// I = |z|^2 and J = w (*) I follow from z alone, and u = z exp(+j phi J).  With
+// Jbar = phi sum_p Im(conj(g_z) z) and Ibar = w^T (*) Jbar the gradient at the
+// FIR output is g_u = exp(+j phi J) (g_z + 2 Ibar z); the input gradient is the
+// FIR's adjoint applied to g_u and dL/dh correlates g_u with the input x.  No
+// FIR is evaluated twice: the input x enters only dL/dh.
 template <int NPOL, int NF, int NW>
 __global__ __launch_bounds__(FT_THREADS) void fir_adjoint_kernel(FirArgs a) {
     extern __shared__ float4 smem4[];
@@ -210,19 +218,16 @@ __global__ __launch_bounds__(FT_THREADS) void fir_adjoint_kernel(FirArgs a) {
     const int HF = (nfir - 1) / 2;
     const int NC = (ntaps - 1) / 2;
     const int TS = NF > 0 && NW >= 0 ? fir_adj_tile(NF, NW == 0 ? 1 : NW) : a.ts;
-    const int nx = TS + 4 * HF + 4 * NC;      // x on [a0 - 2HF - 2NC, ...)
-    const int nu = TS + 2 * HF + 4 * NC;      // u, I on [a0 - HF - 2NC, ...)
-    const int nz = TS + 2 * HF + 2 * NC;      // J, g_z, Jbar on [a0 - HF - NC, ...)
-    const int ng = TS + 2 * HF;               // g_u on [a0 - HF, ...)
+    const int nz = TS + 2 * HF + 2 * NC;      // z, g_z (then g_u), I, Jbar on [a0 - HF - NC, ...)
+    const int ng = TS + 2 * HF;               // g_u on [a0 - HF, a0 + TS + HF)
+    const int nxs = TS + 2 * HF;              // x on [a0 - HF, a0 + TS + HF), in z's LDS once z is read
     float2* hs = reinterpret_cast<float2*>(smem);
     float* wsm = reinterpret_cast<float*>(hs + 2 * FT_MAXH + 1);
-    float2* xs = reinterpret_cast<float2*>(wsm + 2 * FT_MAXC + 2);
-    float2* us = xs + NPOL * nx;
-    float2* gzs = us + NPOL * nu;              // g_z, then g_u in place
-    float* is = reinterpret_cast<float*>(gzs + NPOL * nz);
-    float* js = is + nu;
-    float* jb = js + nz;
-    float* red = jb + nz;                      // [4 waves][64] partial sums
+    float2* zs = reinterpret_cast<float2*>(wsm + 2 * FT_MAXC + 2);
+    float2* gs = zs + NPOL * nz;
+    float* is = reinterpret_cast<float*>(gs + NPOL * nz);
+    float* jb = is + nz;
+    float2* xs = zs;
 
     const int t = threadIdx.x;
     const int wg = xcd_remap(blockIdx.x, a.n_wg);
@@ -231,66 +236,95 @@ __global__ __launch_bounds__(FT_THREADS) void fir_adjoint_kernel(FirArgs a) {
     const long long L = a.L;
     const long long a0 = (long long)tile * TS;
     const float2* __restrict__ x = a.x + (long long)sig * NPOL * L;
+    const float2* __restrict__ zo = a.zo + (long long)sig * NPOL * L;
     const float2* __restrict__ gz = a.gz + (long long)sig * NPOL * L;
     float2* __restrict__ gx = a.z + (long long)sig * NPOL * L;
 
     for (int i = t; i < nfir; i += FT_THREADS) hs[i] = a.h[i];
     if constexpr (NW != 0)
         for (int i = t; i < ntaps; i += FT_THREADS) wsm[i] = a.w[i];
-    load_tile<NPOL>(xs, x, a0 - 2 * HF - 2 * NC, nx, L);
-    load_tile<NPOL>(gzs, gz, a0 - HF - NC, nz, L);
+    load_tile<NPOL>(zs, zo, a0 - HF - NC, nz, L);
+    load_tile<NPOL>(gs, gz, a0 - HF - NC, nz, L);
+    // the input is needed from the parameter sums on: loaded now into registers, stored
+    // into z's LDS once z has been read (compile-time tiles; run-time tiles load it then)
+    constexpr bool XREG = NF > 0 && NW >= 0;
+    constexpr int XR = XREG ? (fir_adj_tile(NF > 0 ? NF : 1, NW > 0 ? NW : 1) + (NF > 0 ? NF : 1) - 1 +
+                               FT_THREADS - 1) / FT_THREADS
+                            : 1;
+    float2 xr[NPOL][XR];
+    if constexpr (XREG) {
+#pragma unroll
+        for (int k = 0; k < XR; ++k) {
+            const int i = t + FT_THREADS * k;
+            if (i < nxs) {
+                const long long g = wrap(a0 - HF + i, L);
+#pragma unroll
+                for (int p = 0; p < NPOL; ++p) xr[p][k] = x[p * L + g];
+            }
+        }
+    }
     __syncthreads();
-    // recompute the step: u and I on the u range, J on the z range
-    fir_u<NPOL, NF>(us, is, xs, nx, nu, hs, nfir);
-    __syncthreads();
-    tap_filter<NW>(js, is, nz, wsm, ntaps);
-    __syncthreads();
-    // Jbar = phi sum_p Im(conj(g_z) z), z = u exp(-j phi J), on the z range
+    // I = sum_p |z|^2 and Jbar = phi sum_p Im(conj(g_z) z) on the z range
     for (int i = t; i < nz; i += FT_THREADS) {
-        const float2 rot = expj(-a.phi * js[i]);
-        const float cs = rot.x, sn = rot.y;
-        float acc = 0.f;
+        float in = 0.f, acc = 0.f;
 #pragma unroll
         for (int p = 0; p < NPOL; ++p) {
-            const float2 zz = cmul(us[p * nu + i + NC], make_float2(cs, sn));
-            const float2 g = gzs[p * nz + i];
+            const float2 zz = zs[p * nz + i];
+            const float2 g = gs[p * nz + i];
+            in = fmaf(zz.x, zz.x, fmaf(zz.y, zz.y, in));
             acc = fmaf(g.x, zz.y, fmaf(-g.y, zz.x, acc));
         }
+        is[i] = in;
         jb[i] = a.phi * acc;
     }
     __syncthreads();
-    // g_u = g_z exp(+j phi J) + 2 Ibar u on the g range, Ibar = w^T (*) Jbar
+    // g_u = exp(+j phi J) (g_z + 2 Ibar z) on the g range, J = w (*) I, Ibar = w^T (*) Jbar
     for (int i = t; i < ng; i += FT_THREADS) {
         const int iz = i + NC;                 // position in the z range
-        float ib = 0.f;
+        float jv = 0.f, ib = 0.f;
         if constexpr (NW != 0) {
 #pragma unroll
-            for (int m = 0; m < (NW > 0 ? NW : ntaps); ++m) ib = fmaf(wsm[m], jb[iz + m - NC], ib);
+            for (int m = 0; m < (NW > 0 ? NW : ntaps); ++m) {
+                jv = fmaf(wsm[m], is[iz + NC - m], jv);
+                ib = fmaf(wsm[m], jb[iz + m - NC], ib);
+            }
         } else {
+            jv = is[iz];
             ib = jb[iz];
         }
-        const float2 rot = expj(a.phi * js[iz]);
-        const float cs = rot.x, sn = rot.y;
-        float2 gu[NPOL];
+        const float2 rot = expj(a.phi * jv);
+        const float ib2 = 2.f * ib;
 #pragma unroll
         for (int p = 0; p < NPOL; ++p) {
-            const float2 uu = us[p * nu + iz + NC];
-            const float2 g = cmul(gzs[p * nz + iz], make_float2(cs, sn));
-            gu[p] = make_float2(fmaf(2.f * ib, uu.x, g.x), fmaf(2.f * ib, uu.y, g.y));
+            const float2 zz = zs[p * nz + iz];
+            const float2 g = gs[p * nz + iz];
+            // in place: this iteration alone reads and writes position iz of gs
+            gs[p * nz + iz] = cmul(make_float2(fmaf(ib2, zz.x, g.x), fmaf(ib2, zz.y, g.y)), rot);
         }
-        // in place: this iteration alone reads and writes position iz of gzs
-#pragma unroll
-        for (int p = 0; p < NPOL; ++p) gzs[p * nz + iz] = gu[p];
     }
     __syncthreads();
-    // input gradient: g_x[o] = sum_m conj(h[m]) g_u[o + m - HF]
+    // z is no longer read: its LDS takes the input on [a0 - HF, a0 + TS + HF)
+    if constexpr (XREG) {
+#pragma unroll
+        for (int k = 0; k < XR; ++k) {
+            const int i = t + FT_THREADS * k;
+            if (i < nxs)
+#pragma unroll
+                for (int p = 0; p < NPOL; ++p) xs[p * nxs + i] = xr[p][k];
+        }
+    } else {
+        load_tile<NPOL>(xs, x, a0 - HF, nxs, L);
+    }
+    // input gradient: g_x[o] = sum_m conj(h[m]) g_u[o + m - HF] (g_u at o - HF is gs[p][NC + o])
     if constexpr (NF > 0) {
-        // FR consecutive outputs per thread, window j = r + m of g_u in registers
+        // FR consecutive outputs per thread, window j = r + m of g_u in registers; the taps
+        // are uniform and come through scalar loads (no vector registers for them)
         constexpr int W = FR + NF - 1;
+        const auto hc = as_const(reinterpret_cast<const float*>(a.h));
         for (int base = t * FR; base < TS; base += FT_THREADS * FR) {
 #pragma unroll
             for (int p = 0; p < NPOL; ++p) {
-                const float2* gr = gzs + p * nz + NC + base;     // g_u at base - HF
+                const float2* gr = gs + p * nz + NC + base;
                 float2 win[W];
 #pragma unroll
                 for (int j = 0; j < W; ++j) win[j] = gr[j];
@@ -299,7 +333,7 @@ __global__ __launch_bounds__(FT_THREADS) void fir_adjoint_kernel(FirArgs a) {
                 for (int r = 0; r < FR; ++r) acc[r] = make_float2(0.f, 0.f);
 #pragma unroll
                 for (int m = 0; m < NF; ++m) {
-                    const float2 hv = hs[m];
+                    const float2 hv = make_float2(hc[2 * m], hc[2 * m + 1]);
 #pragma unroll
                     for (int r = 0; r < FR; ++r) {
                         const float2 g = win[r + m];
@@ -312,145 +346,163 @@ __global__ __launch_bounds__(FT_THREADS) void fir_adjoint_kernel(FirArgs a) {
                     if (base + r < TS && a0 + base + r < L) gx[p * L + a0 + base + r] = acc[r];
             }
         }
-    } else
-    for (int o = t; o < TS; o += FT_THREADS) {
-        if (a0 + o >= L) break;
+    } else {
+        for (int o = t; o < TS; o += FT_THREADS) {
+            if (a0 + o >= L) break;
 #pragma unroll
-        for (int p = 0; p < NPOL; ++p) {
-            float2 acc = make_float2(0.f, 0.f);
-            const float2* gr = gzs + p * nz + NC + o;     // g_u at o - HF is gzs[p][NC + o]
-#pragma unroll
-            for (int m = 0; m < (NF > 0 ? NF : nfir); ++m) {
-                const float2 hv = hs[m];
-                const float2 g = gr[m];
-                acc.x = fmaf(hv.x, g.x, fmaf(hv.y, g.y, acc.x));
-                acc.y = fmaf(hv.x, g.y, fmaf(-hv.y, g.x, acc.y));
+            for (int p = 0; p < NPOL; ++p) {
+                float2 acc = make_float2(0.f, 0.f);
+                const float2* gr = gs + p * nz + NC + o;
+                for (int m = 0; m < nfir; ++m) {
+                    const float2 hv = hs[m];
+                    const float2 g = gr[m];
+                    acc.x = fmaf(hv.x, g.x, fmaf(hv.y, g.y, acc.x));
+                    acc.y = fmaf(hv.x, g.y, fmaf(-hv.y, g.x, acc.y));
+                }
+                gx[p * L + a0 + o] = acc;
             }
-            gx[p * L + a0 + o] = acc;
         }
     }
+    __syncthreads();                           // x stored (and visible to every wave)
     const int n_own = (int)min((long long)TS, L - a0);
     const int nw = NW != 0 ? ntaps : 0;
+    const int width = nw + 2 * nfir;
     // partials parameter-major ([parameter][tile]) so that the reduction reads them contiguously
     float* part = a.part + wg;
     const long long pstride = a.n_wg;
+    // Parameter partials over the owned outputs n = a0 + o, o < n_own:
+    //   dL/dh[l] = sum g_u[n] conj(x[n - (l - HF)]),  dL/dw[m] = sum Jbar[n] I[n - (m - NC)],
+    // g_u at n in gs[p][o + HF + NC], x at n - l + HF in xs[p][o - l + 2 HF], Jbar at n in
+    // jb[o + HF + NC], I at n - m + NC in is[o + HF + 2 NC - m].  Lane (of any wave) sums its
+    // own run of outputs; the lags are split between the waves.  The 64 lane sums of every
+    // parameter then meet in LDS and are added in a fixed order.
+    const int lane = t & 63, wv = t >> 6;
+    float* red = reinterpret_cast<float*>(zs);   // [width][65] lane sums, then [width][2]
     if constexpr (NF > 0 && NW >= 0) {
-        // Parameter partials over the owned outputs n = a0 + o, o < n_own:
-        //   dL/dh[l] = sum g_u[n] conj(x[n - (l - HF)]),  dL/dw[m] = sum Jbar[n] I[n - (m - NC)].
-        // Every thread accumulates all parameters over its FR outputs, then the 256
-        // sums of each parameter are added through LDS in a fixed order.
         constexpr int NWC = NW;
-        constexpr int W = NWC + 2 * NF;
-        float acc[W];
-#pragma unroll
-        for (int j = 0; j < W; ++j) acc[j] = 0.f;
-        // FR consecutive outputs o0 + r per thread; x[o + 3HF + 2NC - l] from a window
-        // j = r - l + NF - 1 held in registers
-        constexpr int WX = FR + NF - 1;
-        for (int o0 = t * FR; o0 < n_own; o0 += FT_THREADS * FR) {
-#pragma unroll
+        constexpr int OS = 13;                   // outputs per lane (odd: reads spread over the banks)
+        static_assert(64 * OS >= fir_adj_tile(NF, NW == 0 ? 1 : NW), "one run of outputs per lane");
+        static_assert(NF > 24 && NF - 24 <= 9, "lags split 8 / 8 / 8 / NF - 24 between the waves");
+        const int o_s = lane * OS;
+        auto lags = [&](auto nl_c, int l0, float (&acc)[18]) {
+            constexpr int NL = decltype(nl_c)::value;
+            constexpr int WX = OS + NL - 1;
+#pragma unroll 1
             for (int p = 0; p < NPOL; ++p) {
-                float2 g[FR];
-#pragma unroll
-                for (int r = 0; r < FR; ++r)
-                    g[r] = o0 + r < n_own ? gzs[p * nz + NC + HF + o0 + r] : make_float2(0.f, 0.f);
-                const float2* xr = xs + p * nx + o0 + 3 * HF + 2 * NC - (NF - 1);
+                const float2* xrow = xs + p * nxs + o_s - (l0 + NL - 1) + 2 * HF;
+                const int jmax = nxs - (o_s - (l0 + NL - 1) + 2 * HF);   // window entries inside x
                 float2 win[WX];
 #pragma unroll
-                for (int j = 0; j < WX; ++j) win[j] = xr[j];
+                for (int j = 0; j < WX; ++j) win[j] = j < jmax ? xrow[j] : make_float2(0.f, 0.f);
 #pragma unroll
-                for (int l = 0; l < NF; ++l)
+                for (int r = 0; r < OS; ++r) {
+                    const float2 g = o_s + r < n_own ? gs[p * nz + o_s + r + HF + NC] : make_float2(0.f, 0.f);
 #pragma unroll
-                    for (int r = 0; r < FR; ++r) {
-                        const float2 xv = win[r - l + NF - 1];
-                        acc[NWC + 2 * l] = fmaf(g[r].x, xv.x, fmaf(g[r].y, xv.y, acc[NWC + 2 * l]));
-                        acc[NWC + 2 * l + 1] = fmaf(g[r].y, xv.x, fmaf(-g[r].x, xv.y, acc[NWC + 2 * l + 1]));
-                    }
-            }
-            if constexpr (NWC > 0) {
-#pragma unroll
-                for (int r = 0; r < FR; ++r) {
-                    const int o = o0 + r;
-                    if (o < n_own) {
-                        const float jv = jb[o + HF + NC];
-#pragma unroll
-                        for (int m = 0; m < NWC; ++m) acc[m] = fmaf(jv, is[o + HF + 3 * NC - m], acc[m]);
+                    for (int k = 0; k < NL; ++k) {
+                        const float2 xv = win[r - k + NL - 1];
+                        acc[2 * k] = fmaf(g.x, xv.x, fmaf(g.y, xv.y, acc[2 * k]));
+                        acc[2 * k + 1] = fmaf(g.y, xv.x, fmaf(-g.x, xv.y, acc[2 * k + 1]));
                     }
                 }
             }
+        };
+        float acc[18];
+#pragma unroll
+        for (int j = 0; j < 18; ++j) acc[j] = 0.f;
+        float accw[3] = {0.f, 0.f, 0.f};
+        const int l0 = 8 * wv;
+        if (o_s < n_own) {
+            if (wv < 3) {
+                lags(std::integral_constant<int, 8>{}, l0, acc);
+                if constexpr (NWC > 0) {
+                    // intensity taps 3 wv .. 3 wv + 2
+                    const int m0 = 3 * wv;
+                    if (m0 < NWC) {
+                        const float* irow = is + o_s + HF + 2 * NC - (m0 + 2);
+                        float iw[OS + 2];
+#pragma unroll
+                        for (int j = 0; j < OS + 2; ++j) iw[j] = irow[j];
+#pragma unroll
+                        for (int r = 0; r < OS; ++r) {
+                            const float jv = o_s + r < n_own ? jb[o_s + r + HF + NC] : 0.f;
+#pragma unroll
+                            for (int k = 0; k < 3; ++k) accw[k] = fmaf(jv, iw[r - k + 2], accw[k]);
+                        }
+                    }
+                }
+            } else {
+                lags(std::integral_constant<int, NF - 24>{}, l0, acc);
+            }
         }
-        // x, u and g_z are no longer read: their LDS holds the reduction, 16 parameters
-        // at a time ([16][256] per-thread sums in rows of RS floats, then [16][16] partial
-        // sums).  Thread (k, seg) adds the sums of threads seg + 16 i: the 64 lanes of a
-        // wave then read 64 different banks.
-        constexpr int RS = FT_THREADS + 16;
-        float* rb = reinterpret_cast<float*>(xs);
-        float* rb2 = rb + 16 * RS;
+        __syncthreads();                         // every wave is done reading gs and xs
+        const int nl = wv < 3 ? 8 : NF - 24;
 #pragma unroll
-        for (int c0 = 0; c0 < W; c0 += 16) {
-            __syncthreads();                   // previous readers of this LDS are done
-#pragma unroll
-            for (int k = 0; k < 16; ++k)
-                if (c0 + k < W) rb[k * RS + t] = acc[c0 + k];
-            __syncthreads();
-            {
-                const int k = t >> 4, seg = t & 15;
-                float sum = 0.f;
-#pragma unroll
-                for (int i = 0; i < 16; ++i) sum += rb[k * RS + seg + 16 * i];
-                rb2[k * 16 + seg] = sum;
+        for (int k = 0; k < 9; ++k)
+            if (k < nl) {
+                red[(nw + 2 * (l0 + k)) * 65 + lane] = acc[2 * k];
+                red[(nw + 2 * (l0 + k) + 1) * 65 + lane] = acc[2 * k + 1];
             }
-            __syncthreads();
-            if (t < 16 && c0 + t < W) {
-                float sum = 0.f;
+        if constexpr (NWC > 0) {
 #pragma unroll
-                for (int i = 0; i < 16; ++i) sum += rb2[t * 16 + i];
-                part[(c0 + t) * pstride] = sum;
-            }
+            for (int k = 0; k < 3; ++k)
+                if (wv < 3 && 3 * wv + k < NWC) red[(3 * wv + k) * 65 + lane] = accw[k];
         }
     } else {
-        // run-time tap counts: parameter l (chunks of 64, one per lane) summed by each of
-        // the 4 waves over a quarter of the outputs, the 4 quarters added in order
-        const int lane = t & 63, q = t >> 6;
+        // run-time tap counts: parameter j (chunks of 64, one per lane) summed by each of the
+        // 4 waves over a quarter of the outputs; the sums stay in registers until every wave
+        // has read the input, then meet in LDS and the 4 quarters are added in order
+        constexpr int NCH = (2 * (2 * FT_MAXH + 1) + 2 * FT_MAXC + 1 + 63) / 64;
         const int per = (n_own + 3) / 4;
-        const int o0 = q * per, o1 = min(n_own, o0 + per);
-        for (int pb = 0; pb < nfir + nw; pb += 64) {
-            const int l = pb + lane;
-            float2 acc = make_float2(0.f, 0.f);
-            if (l < nfir) {
-                for (int o = o0; o < o1; ++o) {
+        const int o0 = wv * per, o1 = min(n_own, o0 + per);
+        float sums[NCH];
 #pragma unroll
-                    for (int p = 0; p < NPOL; ++p) {
-                        const float2 g = gzs[p * nz + NC + HF + o];
-                        const float2 xv = xs[p * nx + o + 3 * HF + 2 * NC - l];
-                        acc.x = fmaf(g.x, xv.x, fmaf(g.y, xv.y, acc.x));
-                        acc.y = fmaf(g.y, xv.x, fmaf(-g.x, xv.y, acc.y));
+        for (int c = 0; c < NCH; ++c) {
+            const int j = c * 64 + lane;
+            float acc = 0.f;
+            if (c * 64 < width) {
+                if (j < nw) {
+                    for (int o = o0; o < o1; ++o) acc = fmaf(jb[o + HF + NC], is[o + HF + 2 * NC - j], acc);
+                } else if (j < width) {
+                    const int l = (j - nw) >> 1;
+                    const bool im = ((j - nw) & 1) != 0;
+                    for (int o = o0; o < o1; ++o) {
+#pragma unroll
+                        for (int p = 0; p < NPOL; ++p) {
+                            const float2 g = gs[p * nz + NC + HF + o];
+                            const float2 xv = xs[p * nxs + o - l + 2 * HF];
+                            acc = im ? fmaf(g.y, xv.x, fmaf(-g.x, xv.y, acc)) : fmaf(g.x, xv.x, fmaf(g.y, xv.y, acc));
+                        }
                     }
                 }
-            } else if (l < nfir + nw) {
-                const int m = l - nfir;
-                for (int o = o0; o < o1; ++o) acc.x = fmaf(jb[o + HF + NC], is[o + HF + 3 * NC - m], acc.x);
             }
-            __syncthreads();                   // previous chunk's sums have been read
-            red[(q * 64 + lane) * 2] = acc.x;
-            red[(q * 64 + lane) * 2 + 1] = acc.y;
-            __syncthreads();
-            if (q == 0) {
-                float sx = 0.f, sy = 0.f;
-#pragma unroll
-                for (int w = 0; w < 4; ++w) {
-                    sx += red[(w * 64 + lane) * 2];
-                    sy += red[(w * 64 + lane) * 2 + 1];
-                }
-                if (l < nfir) {
-                    part[(nw + 2 * l) * pstride] = sx;
-                    part[(nw + 2 * l + 1) * pstride] = sy;
-                } else if (l < nfir + nw) {
-                    part[(l - nfir) * pstride] = sx;
-                }
-            }
+            sums[c] = acc;
         }
+        __syncthreads();                         // every wave is done reading gs and xs
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            const int j = c * 64 + lane;
+            if (j < width) red[j * 4 + wv] = sums[c];
+        }
+        __syncthreads();
+        for (int j = t; j < width; j += FT_THREADS) {
+            const float* q = red + j * 4;
+            part[j * pstride] = ((q[0] + q[1]) + q[2]) + q[3];
+        }
+        return;
     }
+    __syncthreads();
+    // lane sums of every parameter: two halves of 32 added in order, then the two halves
+    float* red2 = red + width * 65;
+    for (int j = t; j < 2 * width; j += FT_THREADS) {
+        const int prm = j >> 1, h = j & 1;
+        const float* row = red + prm * 65 + 32 * h;
+        float s = 0.f;
+#pragma unroll 8
+        for (int i = 0; i < 32; ++i) s += row[i];
+        red2[j] = s;
+    }
+    __syncthreads();
+    for (int j = t; j < width; j += FT_THREADS) part[j * pstride] = red2[2 * j] + red2[2 * j + 1];
 }
 
 inline size_t fir_fwd_smem(int npol, int nfir, int ntaps_or_0, int ts) {
@@ -462,9 +514,15 @@ inline size_t fir_fwd_smem(int npol, int nfir, int ntaps_or_0, int ts) {
 
 inline size_t fir_adj_smem(int npol, int nfir, int ntaps_or_0, int ts) {
     const int HF = (nfir - 1) / 2, NC = ntaps_or_0 ? (ntaps_or_0 - 1) / 2 : 0;
-    const int nx = ts + 4 * HF + 4 * NC, nu = ts + 2 * HF + 4 * NC, nz = ts + 2 * HF + 2 * NC;
-    return (2 * FT_MAXH + 1) * 8 + (2 * FT_MAXC + 2) * 4 + (size_t)npol * (nx + nu + nz) * 8 +
-           (size_t)(nu + 2 * nz) * 4 + 4 * 64 * 2 * 4;
+    const int nz = ts + 2 * HF + 2 * NC;
+    const int width = (ntaps_or_0 ? ntaps_or_0 : 0) + 2 * nfir;
+    // z (then x and the parameter sums), g, I, Jbar.  The sums take width x 65 + 2 width
+    // floats in the variant with compile-time tap counts (33 FIR taps, none or 9 intensity
+    // taps: the launcher's dispatch), 4 width floats otherwise
+    const bool lane_sums = nfir == 33 && (ntaps_or_0 == 0 || ntaps_or_0 == 9);
+    const size_t zg = (size_t)npol * nz * 8 * 2;
+    const size_t red = (size_t)width * (lane_sums ? 67 : 4) * 4;
+    return (2 * FT_MAXH + 1) * 8 + (2 * FT_MAXC + 2) * 4 + (zg > red ? zg : red) + (size_t)nz * 4 * 2;
 }
 
 }  // namespace dbp

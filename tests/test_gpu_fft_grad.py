@@ -104,6 +104,24 @@ def test_fft_grad_is_deterministic_and_matches_autograd(dbp):
     assert torch.equal(tr.grad, a[1])
 
 
+def test_fft_saved_forward_then_reverse(dbp):
+    # the pass inputs kept by dbp_backprop_save give dbp_backprop_grad's gradients bit for bit
+    n, n_spans = 5000, 6
+    xs, taps, gout = case(8, 1, 2, n, n_spans, 4)
+    p = dbp.plan(n, n_spans, 1, batch=1, taps=taps[0], block=1024, overlap=256, steps_per_pass=2,
+                 beta2_ps2_km=B2)
+    x, t, g = dev(xs, np.complex64), dev(taps, np.float32), dev(gout, np.complex64)
+    ref_out = p.backprop(x, taps=t)
+    ref = p.backprop_grad(x, g, taps=t)
+    out, ws = p.backprop_save(x, taps=t)
+    got = p.backprop_grad_saved(x, out, ws, g, taps=t)
+    torch.cuda.synchronize()
+    assert torch.equal(torch.view_as_real(out), torch.view_as_real(ref_out))
+    assert torch.equal(torch.view_as_real(got[0]), torch.view_as_real(ref[0]))
+    assert torch.equal(got[1], ref[1])
+    assert got[2] is None
+
+
 def test_fft_grad_finite_difference_of_gpu_forward(dbp):
     # d/dw of <g, DBP(x; w)> along a tap direction, by central differences of the GPU forward
     n, n_spans = 4096, 4

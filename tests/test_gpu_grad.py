@@ -140,6 +140,39 @@ def test_dense_and_sparse_checkpoints_give_identical_gradients(dbp):
         assert torch.equal(a, b)
 
 
+@pytest.mark.parametrize("sparse", [False, True])
+def test_saved_forward_then_reverse_equals_backprop_grad(dbp, sparse):
+    # dbp_backprop_save writes the output dbp_backprop writes and keeps the step states;
+    # dbp_backprop_grad_saved then gives dbp_backprop_grad's gradients bit for bit, also
+    # when it runs twice on the same saved states; the autograd Function runs these two
+    n, n_spans, batch = 2600, 19, 2
+    xs, fir, taps, _ = setup(6, batch, 2, n, n_spans, True)
+    g = np.random.default_rng(9)
+    gout = dev((g.standard_normal(xs.shape) + 1j * g.standard_normal(xs.shape)).astype(np.complex64))
+    x, t, f = dev(xs, np.complex64), dev(taps), dev(fir)
+    p = make_plan(dbp, n, n_spans, batch, 2, taps, fir, grad_sparse=sparse)
+    ref_out = p.backprop(x, taps=t, fir=f)
+    ref = p.backprop_grad(x, gout, taps=t, fir=f)
+    out, ws = p.backprop_save(x, taps=t, fir=f)
+    torch.cuda.synchronize()
+    assert torch.equal(torch.view_as_real(out), torch.view_as_real(ref_out))
+    for _ in range(2):
+        got = p.backprop_grad_saved(x, out, ws, gout, taps=t, fir=f)
+        torch.cuda.synchronize()
+        for a, b in zip(got, ref):
+            assert torch.equal(torch.view_as_real(a) if a.is_complex() else a,
+                               torch.view_as_real(b) if b.is_complex() else b)
+    xr, tr, fr = x.clone().requires_grad_(True), t.clone().requires_grad_(True), f.clone().requires_grad_(True)
+    y = dbp.dbp_function().apply(xr, tr, fr, p)
+    (torch.view_as_real(y) * torch.view_as_real(gout)).sum().backward()
+    assert torch.equal(torch.view_as_real(y.detach()), torch.view_as_real(ref_out))
+    assert torch.equal(torch.view_as_real(xr.grad), torch.view_as_real(ref[0]))
+    assert torch.equal(tr.grad, ref[1])
+    assert torch.equal(torch.view_as_real(fr.grad), torch.view_as_real(ref[2]))
+    with pytest.raises(dbp.DbpError):
+        p.backprop_save(x, taps=t, fir=f, out=x)          # the output may not overlap the input
+
+
 def test_autograd_function_with_symbol_loss(dbp):
     # the differentiation workload's loss (matched filter, symbol MSE) written in torch on the
     # GPU by the caller; gradients through DBPFunction vs the oracle's chain rule
