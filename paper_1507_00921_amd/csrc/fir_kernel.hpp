@@ -55,9 +55,17 @@ __device__ __forceinline__ long long wrap(long long i, long long L) {
 }
 
 // Load x[(base + i) mod L], i < n, of every polarization into s[p][i] (row stride n).
+// Tiles inside the signal (all but the ones at its ends) skip the index wrap.
 template <int NPOL>
 __device__ __forceinline__ void load_tile(float2* s, const float2* __restrict__ x, long long base, int n,
                                           long long L) {
+    if (base >= 0 && base + n <= L) {
+        const float2* __restrict__ xb = x + base;
+        for (int i = threadIdx.x; i < n; i += FT_THREADS)
+#pragma unroll
+            for (int p = 0; p < NPOL; ++p) s[p * n + i] = xb[p * L + i];
+        return;
+    }
     for (int i = threadIdx.x; i < n; i += FT_THREADS) {
         const long long g = wrap(base + i, L);
 #pragma unroll
@@ -253,11 +261,12 @@ __global__ __launch_bounds__(FT_THREADS) void fir_adjoint_kernel(FirArgs a) {
                             : 1;
     float2 xr[NPOL][XR];
     if constexpr (XREG) {
+        const bool inside = a0 - HF >= 0 && a0 - HF + nxs <= L;
 #pragma unroll
         for (int k = 0; k < XR; ++k) {
             const int i = t + FT_THREADS * k;
             if (i < nxs) {
-                const long long g = wrap(a0 - HF + i, L);
+                const long long g = inside ? a0 - HF + i : wrap(a0 - HF + i, L);
 #pragma unroll
                 for (int p = 0; p < NPOL; ++p) xr[p][k] = x[p * L + g];
             }
@@ -363,8 +372,20 @@ __global__ __launch_bounds__(FT_THREADS) void fir_adjoint_kernel(FirArgs a) {
             }
         }
     }
-    __syncthreads();                           // x stored (and visible to every wave)
     const int n_own = (int)min((long long)TS, L - a0);
+    __syncthreads();                           // x stored (and visible to every wave), g_x done
+    if constexpr (NF > 0 && NW >= 0) {
+        // the lane runs of the parameter sums may pass the last owned output by up to OS - 1
+        // positions: g_u and Jbar there (read by nothing else from now on) become zeros, so
+        // those terms vanish without a test in the loops
+        if (t < 16) {
+            const int o = n_own + t;
+#pragma unroll
+            for (int p = 0; p < NPOL; ++p) gs[p * nz + o + HF + NC] = make_float2(0.f, 0.f);
+            jb[o + HF + NC] = 0.f;
+        }
+        __syncthreads();
+    }
     const int nw = NW != 0 ? ntaps : 0;
     const int width = nw + 2 * nfir;
     // partials parameter-major ([parameter][tile]) so that the reduction reads them contiguously
@@ -390,13 +411,13 @@ __global__ __launch_bounds__(FT_THREADS) void fir_adjoint_kernel(FirArgs a) {
 #pragma unroll 1
             for (int p = 0; p < NPOL; ++p) {
                 const float2* xrow = xs + p * nxs + o_s - (l0 + NL - 1) + 2 * HF;
-                const int jmax = nxs - (o_s - (l0 + NL - 1) + 2 * HF);   // window entries inside x
+                // entries past x (lanes whose run passes the tile) meet zero g_u
                 float2 win[WX];
 #pragma unroll
-                for (int j = 0; j < WX; ++j) win[j] = j < jmax ? xrow[j] : make_float2(0.f, 0.f);
+                for (int j = 0; j < WX; ++j) win[j] = xrow[j];
 #pragma unroll
                 for (int r = 0; r < OS; ++r) {
-                    const float2 g = o_s + r < n_own ? gs[p * nz + o_s + r + HF + NC] : make_float2(0.f, 0.f);
+                    const float2 g = gs[p * nz + o_s + r + HF + NC];
 #pragma unroll
                     for (int k = 0; k < NL; ++k) {
                         const float2 xv = win[r - k + NL - 1];
@@ -424,7 +445,7 @@ __global__ __launch_bounds__(FT_THREADS) void fir_adjoint_kernel(FirArgs a) {
                         for (int j = 0; j < OS + 2; ++j) iw[j] = irow[j];
 #pragma unroll
                         for (int r = 0; r < OS; ++r) {
-                            const float jv = o_s + r < n_own ? jb[o_s + r + HF + NC] : 0.f;
+                            const float jv = jb[o_s + r + HF + NC];
 #pragma unroll
                             for (int k = 0; k < 3; ++k) accw[k] = fmaf(jv, iw[r - k + 2], accw[k]);
                         }
