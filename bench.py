@@ -840,8 +840,39 @@ def evm_sweep_per_span_ase(dbp, torch, powers):
                              "cd_only": round(evm_db(cd.backprop(rx), sym), 3)}
         log(f"{pw:+.0f} dBm EVM with ASE per span " + json.dumps(out[f"{pw:+.0f}"]))
     best = min(out, key=lambda k: out[k]["ssfm_20_per_span"])
-    return {"evm_db_by_launch_dbm": out, "ssfm_20_best_launch_dbm": float(best),
-            "ssfm_20_best_at_sweep_edge": best == max(out, key=float)}
+    res = {"evm_db_by_launch_dbm": out, "ssfm_20_best_launch_dbm": float(best),
+           "ssfm_20_best_at_sweep_edge": best == max(out, key=float)}
+    if not res["ssfm_20_best_at_sweep_edge"]:
+        res["equal_evm_at_ssfm_20_best"] = equal_evm_at(dbp, torch, float(best))
+    return res
+
+
+def equal_evm_at(dbp, torch, p_dbm, counts=(1, 2, 3, 4, 5, 6, 8, 10, 20)):
+    """The metric's comparison at one launch power of the per-span-ASE link: ESSFM 1 step/span
+    (9 taps fitted there) against SSFM at the fewest steps per span whose EVM is at least as
+    good, and against SSFM 20 steps/span, with the time of each on the same field."""
+    b2 = siggen.beta2_ps2_km()
+    rx, sym = gpu_field(dbp, torch, p_dbm, per_span=True)
+    ssfm = dbp.plan(N, SPANS, 20, block=BLOCK, overlap=OVERLAP, beta2_ps2_km=b2)
+    target = ssfm.backprop(rx)
+    taps, _ = fit_taps(dbp, torch, rx, target)
+    essfm = dbp.plan(N, SPANS, 1, taps=taps, block=BLOCK, overlap=OVERLAP, beta2_ps2_km=b2)
+    out = torch.empty_like(rx)
+    evm_e = evm_db(essfm.backprop(rx), sym)
+    ms_e, _ = time_dbp(torch, essfm, rx, out, essfm.workspace(), 3, 20)
+    steps = ssfm_steps_sweep(dbp, torch, rx, sym, counts)
+    match = [n for n in sorted(steps) if steps[n]["evm_db"] <= evm_e]
+    n_eq = match[0] if match else None
+    res = {"launch_dbm": p_dbm, "essfm_evm_db": round(evm_e, 3), "essfm_ms": round(ms_e, 4),
+           "ssfm_20_evm_db": steps[20]["evm_db"], "essfm_minus_ssfm20_db": round(evm_e - steps[20]["evm_db"], 3),
+           "ssfm_steps_per_span_matching_essfm": n_eq,
+           "essfm_vs_matching_ssfm_speedup": round(steps[n_eq]["ms"] / ms_e, 2) if n_eq else None,
+           "essfm_vs_ssfm20_speedup_not_at_equal_evm": round(steps[20]["ms"] / ms_e, 2),
+           "ssfm_sweep": steps}
+    log(f"equal EVM at {p_dbm:+.0f} dBm (ASE per span) " + json.dumps(res))
+    essfm.close()
+    ssfm.close()
+    return res
 
 
 def nc_sweep(dbp, torch, rx, sym, target, evm_ssfm20, ms_ssfm20, counts=(4, 8, 16, 32), reps=20):
@@ -913,7 +944,7 @@ def main():
                     help="with --hbm-only: one case (e.g. k1_nb512), 2 + 10 launches (for counter runs)")
     ap.add_argument("--hbm-variant", default="per_block", choices=("per_block", "stream"),
                     help="with --hbm-case: the per-block kernel (the planner's default) or the streaming twin")
-    ap.add_argument("--only", default=None, choices=("precision", "gradient", "batch", "geometry"),
+    ap.add_argument("--only", default=None, choices=("precision", "gradient", "batch", "geometry", "ase"),
                     help="run one secondary workload alone and print its JSON (for profiler runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a plain 1 GiB device copy three times and exit (counter calibration)")
@@ -937,6 +968,9 @@ def main():
         taps = siggen.symmetric_taps(siggen.rng(1, 0, 7), NC)
         print(json.dumps(hbm_working_set(dbp, torch, rx, taps, only=args.hbm_case,
                                          only_variant=args.hbm_variant)), flush=True)
+        return
+    if args.only == "ase":
+        print(json.dumps(evm_sweep_per_span_ase(dbp, torch, [-2.0, 0.0, 2.0, 4.0, 6.0, 8.0, 10.0])), flush=True)
         return
     if args.only == "geometry":
         rx, _ = gpu_field(dbp, torch, P_DBM)
@@ -1003,7 +1037,7 @@ def main():
             "ssfm_sweep": steps,
             "essfm_nc_sweep": ncs,
         }
-        extras["ase_per_span"] = evm_sweep_per_span_ase(dbp, torch, [-2.0, 0.0, 2.0, 4.0, 6.0])
+        extras["ase_per_span"] = evm_sweep_per_span_ase(dbp, torch, [-2.0, 0.0, 2.0, 4.0, 6.0, 8.0, 10.0])
         taps_gn, info_gn = fit_taps(dbp, torch, rx, target, method="gauss_newton")
         extras["coefficient_fit"] = {
             "adjoint": {**{k: (round(v, 9) if isinstance(v, float) else v) for k, v in fit_info.items()},
