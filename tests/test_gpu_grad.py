@@ -88,9 +88,10 @@ def test_planner_designed_fir_matches_oracle(dbp):
 
 @pytest.mark.parametrize("essfm,n_spans,n,sparse", [(True, 20, 3000, False), (False, 9, 2100, False),
                                                     (True, 1, 1500, False), (True, 20, 3000, True),
-                                                    (False, 9, 2100, True)])
+                                                    (False, 9, 2100, True), (True, 3, 600, False)])
 def test_fir_gradient_parity(dbp, essfm, n_spans, n, sparse):
-    # sparse: checkpoints every 8 steps and recomputed segments (20 steps: 8 + 8 + 4)
+    # sparse: checkpoints every 8 steps and recomputed segments (20 steps: 8 + 8 + 4); 600
+    # samples: one tile longer than the signal, its windows wrapping around it
     batch = 2
     xs, fir, taps, steps = setup(3, batch, 2, n, n_spans, essfm)
     g = np.random.default_rng(7)
@@ -119,6 +120,40 @@ def test_fir_gradient_parity(dbp, essfm, n_spans, n, sparse):
         assert ew <= 1e-4
     else:
         assert gt is None
+
+
+@pytest.mark.parametrize("n_fir,nc,n_pol", [(21, 3, 2), (33, 3, 2), (45, 6, 1), (21, 4, 2)])
+def test_fir_gradient_parity_run_time_tap_counts(dbp, n_fir, nc, n_pol):
+    # the kernel variants with run-time FIR and / or intensity tap counts (compiled in: 33 FIR
+    # taps with none or 9 intensity taps) against the oracle, on a signal of a few tiles and a
+    # ragged tail
+    n, n_spans, batch = 3100, 6, 2
+    g = np.random.default_rng(n_fir * 100 + nc)
+    xs = np.stack([received(3, 700 + i, n_pol, n, 2.0, n_spans, 1)[0] for i in range(batch)])
+    base = R.schedule(n_spans, 80.0, 1, B2, siggen.GAMMA_W_KM, siggen.ALPHA_DB_KM)
+    h0 = R.ls_fir_taps(n_fir, base[0].b, FS, BAND)
+    fir = np.stack([h0 * (1 + 0.02 * (g.standard_normal(n_fir) + 1j * g.standard_normal(n_fir)))
+                    for _ in base]).astype(np.complex64)
+    taps = np.stack([siggen.symmetric_taps(siggen.rng(3, 70 + nc, s), nc) for s in range(n_spans)]).astype(np.float32)
+    steps = [R.Step(b=st.b, phi=st.phi, w=taps[s].astype(np.float64), h=fir[s].astype(np.complex128))
+             for s, st in enumerate(base)]
+    gout = (g.standard_normal(xs.shape) + 1j * g.standard_normal(xs.shape)).astype(np.complex64)
+    p = make_plan(dbp, n, n_spans, batch, n_pol, taps, fir)
+    gx, gt, gf = p.backprop_grad(dev(xs, np.complex64), dev(gout), taps=dev(taps), fir=dev(fir))
+    gx = gx.cpu().numpy().astype(np.complex128)
+    ref_w = 0
+    ref_h = 0
+    for i in range(batch):
+        gr = A.grad_whole(c64(xs[i]), steps, FS, gout[i].astype(np.complex128))
+        err = field_err(gx[i], gr.x)
+        print(f"n_fir {n_fir} taps {2 * nc + 1} pol {n_pol} signal {i}: grad x rel L2 {err:.3e}")
+        assert err <= 1e-4
+        ref_h = ref_h + np.stack(gr.h)
+        ref_w = ref_w + np.stack(gr.w)
+    eh = field_err(gf.cpu().numpy().astype(np.complex128), ref_h)
+    ew = field_err(gt.cpu().numpy().astype(np.float64), ref_w)
+    print(f"  grad fir {eh:.3e}, grad taps {ew:.3e}")
+    assert eh <= 1e-4 and ew <= 1e-4
 
 
 def test_dense_and_sparse_checkpoints_give_identical_gradients(dbp):
