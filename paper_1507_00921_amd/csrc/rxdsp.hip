@@ -136,19 +136,37 @@ __device__ __forceinline__ double2 zdiv(double2 a, double2 b) {
     return make_double2((a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d);
 }
 
+// Value of lane `lane` (uniform) of a wave-wide double.
+__device__ __forceinline__ double lane_value(double v, int lane) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
 // A x = B for the M x M normal matrix and its two right-hand sides (sum = [A row-major |
 // B row-major M x 2], FP64), in the order of the textbook algorithm: for every column the
 // row with the largest |a| at or below the diagonal (the first on ties) is swapped up and
 // eliminated from the rows below, then back substitution.  taps[p M + i] = x[i][p].  A
 // zero pivot sets *flag to 1 and writes NaN taps.
+//
+// Per column three phases between barriers: wave 0 finds the pivot row (a wave-wide
+// reduction, one lane per row) and its reciprocal; the pivot row and the current row are
+// copied aside and the factors f[i] = a[i][col] / pivot formed (the pivot row's swap taken
+// into account); then every row below is updated, lane = column and wave = row modulo 4.
+// The row swap is carried out by these updates (the current row takes the pivot row, the
+// pivot row the current row minus its multiple), so no phase reads what another writes.
+// Back substitution runs in wave 0 alone, lane = row, both right-hand sides at once: the
+// unknowns are found from the last row up and each is subtracted from the rows above it.
 __global__ __launch_bounds__(THREADS) void solve_kernel(const double2* __restrict__ sum, int M,
                                                         float2* __restrict__ taps, int* __restrict__ flag) {
     __shared__ double2 a[MAX_M][MAX_M + 2];
     __shared__ double2 f[MAX_M];
-    __shared__ double2 x[2][MAX_M];
+    __shared__ double2 prow[MAX_M + 2], crow[MAX_M + 2];
+    __shared__ double2 inv_s;
     __shared__ int piv;
     __shared__ int bad;
-    const int t = threadIdx.x, lane = t & 63;
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int W = M + 2;
     for (int e = t; e < M * W; e += THREADS) {
         const int i = e / W, j = e - i * W;
@@ -157,7 +175,7 @@ __global__ __launch_bounds__(THREADS) void solve_kernel(const double2* __restric
     if (t == 0) bad = 0;
     __syncthreads();
     for (int col = 0; col < M; ++col) {
-        if (t < 64) {
+        if (wv == 0) {
             const int i = col + lane;
             double v = -1.0;
             if (i < M) v = a[i][col].x * a[i][col].x + a[i][col].y * a[i][col].y;
@@ -173,25 +191,33 @@ __global__ __launch_bounds__(THREADS) void solve_kernel(const double2* __restric
             if (lane == 0) {
                 piv = idx;
                 if (!(v > 0.0)) bad = 1;
+                else inv_s = zdiv(make_double2(1.0, 0.0), a[idx][col]);
             }
         }
         __syncthreads();
         if (bad) break;
         const int pr = piv;
-        if (pr != col)
-            for (int j = col + t; j < W; j += THREADS) {
-                const double2 tmp = a[col][j];
-                a[col][j] = a[pr][j];
-                a[pr][j] = tmp;
+        if (t < W) {
+            if (t >= col) {
+                prow[t] = a[pr][t];
+                crow[t] = a[col][t];
             }
+        } else if (t >= 64 && t - 64 < M) {
+            const int i = t - 64;
+            if (i > col) f[i] = zmul(i == pr ? a[col][col] : a[i][col], inv_s);
+        }
         __syncthreads();
-        for (int i = col + 1 + t; i < M; i += THREADS) f[i] = zdiv(a[i][col], a[col][col]);
-        __syncthreads();
-        const int rows = M - col - 1, cols = W - col - 1;
-        for (int e = t; e < rows * cols; e += THREADS) {
-            const int i = col + 1 + e / cols, j = col + 1 + e % cols;
-            const double2 m = zmul(f[i], a[col][j]);
-            a[i][j] = make_double2(a[i][j].x - m.x, a[i][j].y - m.y);
+        const int j = lane;
+        if (j < W && j >= col) {
+            const double2 pj = prow[j];
+            if (wv == 0) a[col][j] = pj;
+            if (j > col) {
+                for (int i = col + 1 + wv; i < M; i += 4) {
+                    const double2 src = i == pr ? crow[j] : a[i][j];
+                    const double2 m = zmul(f[i], pj);
+                    a[i][j] = make_double2(src.x - m.x, src.y - m.y);
+                }
+            }
         }
         __syncthreads();
     }
@@ -200,30 +226,34 @@ __global__ __launch_bounds__(THREADS) void solve_kernel(const double2* __restric
         if (t == 0) *flag = 1;
         return;
     }
-    // back substitution: wave p (p < 2) solves right-hand side p, one row at a time
-    if (t < 128) {
-        const int p = t >> 6;
-        for (int r = M - 1; r >= 0; --r) {
-            double2 acc = make_double2(0.0, 0.0);
-            if (lane > r && lane < M) acc = zmul(a[r][lane], x[p][lane]);
-            for (int off = 32; off > 0; off >>= 1) {
-                acc.x += __shfl_xor(acc.x, off);
-                acc.y += __shfl_xor(acc.y, off);
-            }
-            if (lane == 0) {
-                const double2 b = a[r][M + p];
-                x[p][r] = zdiv(make_double2(b.x - acc.x, b.y - acc.y), a[r][r]);
-            }
-            __syncthreads();
+    if (wv != 0) return;
+    const int i = lane;
+    double2 b0 = make_double2(0.0, 0.0), b1 = b0, d = b0;
+    if (i < M) {
+        b0 = a[i][M];
+        b1 = a[i][M + 1];
+        d = zdiv(make_double2(1.0, 0.0), a[i][i]);
+    }
+    double2 x0 = make_double2(0.0, 0.0), x1 = x0;
+    for (int r = M - 1; r >= 0; --r) {
+        const double2 dr = make_double2(lane_value(d.x, r), lane_value(d.y, r));
+        const double2 u0 = zmul(make_double2(lane_value(b0.x, r), lane_value(b0.y, r)), dr);
+        const double2 u1 = zmul(make_double2(lane_value(b1.x, r), lane_value(b1.y, r)), dr);
+        if (i == r) {
+            x0 = u0;
+            x1 = u1;
+        } else if (i < r) {
+            const double2 air = a[i][r];
+            const double2 m0 = zmul(air, u0), m1 = zmul(air, u1);
+            b0 = make_double2(b0.x - m0.x, b0.y - m0.y);
+            b1 = make_double2(b1.x - m1.x, b1.y - m1.y);
         }
-    } else {
-        for (int r = M - 1; r >= 0; --r) __syncthreads();
     }
-    for (int e = t; e < 2 * M; e += THREADS) {
-        const int p = e / M, i = e - p * M;
-        taps[e] = make_float2((float)x[p][i].x, (float)x[p][i].y);
+    if (i < M) {
+        taps[i] = make_float2((float)x0.x, (float)x0.y);
+        taps[M + i] = make_float2((float)x1.x, (float)x1.y);
+        if (i == 0) *flag = 0;
     }
-    if (t == 0) *flag = 0;
 }
 
 __global__ __launch_bounds__(THREADS) void gram_reduce(const float2* __restrict__ part, int n_chunks, int E,
