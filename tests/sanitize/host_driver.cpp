@@ -193,6 +193,9 @@ static int check_device_paths() {
     CHECK(dbp_backprop_noalloc(nullptr, nullptr, nullptr, nullptr, nullptr, nullptr) == DBP_ERR_INVALID_ARG);
     CHECK(dbp_backprop_grad(nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0,
                             nullptr) == DBP_ERR_INVALID_ARG);
+    CHECK(dbp_backprop_save(nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0, nullptr) == DBP_ERR_INVALID_ARG);
+    CHECK(dbp_backprop_grad_saved(nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                                  nullptr, 0, nullptr) == DBP_ERR_INVALID_ARG);
     CHECK(dbp_workspace_size(nullptr, 0) == 0 && dbp_workspace_size(nullptr, 1) == 0);
     CHECK(dbp_plan_geometry(nullptr, nullptr, nullptr, nullptr, nullptr, nullptr) == DBP_ERR_INVALID_ARG);
     CHECK(std::strlen(dbp_plan_kernel(nullptr)) == 0);

@@ -158,6 +158,9 @@ def test_null_arguments():
     lib = dbp.lib()
     assert lib.dbp_plan(None, None) == 1
     assert lib.dbp_backprop(None, None, None, None, None, None, 0, None) == 1
+    assert lib.dbp_backprop_grad(None, None, None, None, None, None, None, None, None, 0, None) == 1
+    assert lib.dbp_backprop_save(None, None, None, None, None, None, 0, None) == 1
+    assert lib.dbp_backprop_grad_saved(None, None, None, None, None, None, None, None, None, None, 0, None) == 1
     assert lib.dbp_workspace_size(None, 0) == 0
     lib.dbp_destroy(None)
 
