@@ -279,8 +279,9 @@ dbp_status dbp_backprop_grad(dbp_plan_t plan, const void* in, const float* taps,
  * gradients of dbp_backprop_grad for upstream grad_out, given the same plan,
  * in, out, taps and fir, and ws as dbp_backprop_save left it (the reverse pass
  * overwrites only the parts of ws it recomputes, so it may run again for
- * another grad_out).  Errors as dbp_backprop_grad; a ws, in or out changed in
- * between gives wrong gradients, which the library cannot detect. */
+ * another grad_out).  Errors as dbp_backprop_grad (DBP_ERR_INVALID_ARG also for
+ * a field that overlaps ws); a ws, in or out changed in between gives wrong
+ * gradients, which the library cannot detect. */
 dbp_status dbp_backprop_save(dbp_plan_t plan, const void* in, void* out, const float* taps,
                              const void* fir, void* ws, size_t ws_bytes, void* stream);
 dbp_status dbp_backprop_grad_saved(dbp_plan_t plan, const void* in, const void* out,

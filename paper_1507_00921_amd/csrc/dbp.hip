@@ -9,6 +9,7 @@
 #include <cstdlib>
 #include <cstdio>
 #include <cstring>
+#include <initializer_list>
 #include <map>
 #include <mutex>
 #include <new>
@@ -1267,6 +1268,21 @@ static FirWs fir_ws(const Plan* p, void* ws) {
     return r;
 }
 
+// Whether [a, a + na) and [b, b + nb) share a byte (null or empty ranges share none).
+static bool overlap(const void* a, size_t na, const void* b, size_t nb) {
+    if (!a || !b || !na || !nb) return false;
+    const char* x = (const char*)a;
+    const char* y = (const char*)b;
+    return x < y + nb && y < x + na;
+}
+
+// The caller's fields must lie outside the workspace.
+static bool outside_ws(const Plan* p, const void* ws, size_t ws_bytes, std::initializer_list<const void*> fields) {
+    for (const void* f : fields)
+        if (overlap(f, p->state_bytes(), ws, ws_bytes)) return false;
+    return true;
+}
+
 static dbp_status fir_grad_check(Plan* p, const void* grad_out, void* grad_in, void* ws, size_t ws_bytes) {
     if (p->desc.linear != DBP_LINEAR_FIR) return DBP_ERR_UNSUPPORTED;
     const size_t state = p->state_bytes();
@@ -1481,6 +1497,7 @@ dbp_status dbp_backprop_grad(dbp_plan_t p, const void* in, const float* taps, co
     if (!p || !in || !grad_out || p->is_batch) return DBP_ERR_INVALID_ARG;
     hipStream_t s = (hipStream_t)stream;
     dbp_status st;
+    if (!outside_ws(p, ws, ws_bytes, {in, grad_out, grad_in})) return DBP_ERR_INVALID_ARG;
     if (p->desc.linear == DBP_LINEAR_FFT) {
         if ((st = fft_grad_check(p, grad_out, grad_in, grad_fir, ws, ws_bytes)) != DBP_OK) return st;
         if ((st = fft_grad_forward(p, in, nullptr, taps, ws, s)) != DBP_OK) return st;
@@ -1499,6 +1516,7 @@ dbp_status dbp_backprop_save(dbp_plan_t p, const void* in, void* out, const floa
     const char* ib = (const char*)in;
     const char* ob = (const char*)out;
     if (ib < ob + state && ob < ib + state) return DBP_ERR_INVALID_ARG;
+    if (!outside_ws(p, ws, ws_bytes, {in, out})) return DBP_ERR_INVALID_ARG;
     hipStream_t s = (hipStream_t)stream;
     dbp_status st;
     if (p->desc.linear == DBP_LINEAR_FFT) {
@@ -1513,6 +1531,7 @@ dbp_status dbp_backprop_grad_saved(dbp_plan_t p, const void* in, const void* out
                                    const void* fir, const void* grad_out, void* grad_in, float* grad_taps,
                                    void* grad_fir, void* ws, size_t ws_bytes, void* stream) {
     if (!p || !in || !out || !grad_out || p->is_batch) return DBP_ERR_INVALID_ARG;
+    if (!outside_ws(p, ws, ws_bytes, {in, out, grad_out, grad_in})) return DBP_ERR_INVALID_ARG;
     hipStream_t s = (hipStream_t)stream;
     dbp_status st;
     if (p->desc.linear == DBP_LINEAR_FFT) {

@@ -206,6 +206,11 @@ def test_saved_forward_then_reverse_equals_backprop_grad(dbp, sparse):
     assert torch.equal(torch.view_as_real(fr.grad), torch.view_as_real(ref[2]))
     with pytest.raises(dbp.DbpError):
         p.backprop_save(x, taps=t, fir=f, out=x)          # the output may not overlap the input
+    state = torch.view_as_complex(ws[:x.numel() * 8].view(torch.float32).view(*x.shape, 2))
+    with pytest.raises(dbp.DbpError):
+        p.backprop_save(x, taps=t, fir=f, out=state, workspace=ws)     # nor the workspace
+    with pytest.raises(dbp.DbpError):
+        p.backprop_grad_saved(x, out, ws, state, taps=t, fir=f)
 
 
 def test_autograd_function_with_symbol_loss(dbp):
