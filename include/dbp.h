@@ -76,7 +76,12 @@ typedef enum dbp_status {
 typedef enum dbp_method { DBP_SSFM = 0, DBP_ESSFM = 1 } dbp_method;
 
 /* Linear substep: FFT filter of Eq. (1) on overlap-and-save blocks, or a
- * time-domain complex FIR (learnable dispersion taps). */
+ * complex FIR (learnable dispersion taps).  FIR plans on signals of at least
+ * 1024 samples apply the FIR's frequency response on overlap-and-save FFT
+ * blocks of 1024 with overlap 256 (exact up to rounding: the FIR has finite
+ * support), as many steps per pass as the halo covers ((n_fir - 1) / 2 + N_c
+ * samples per step and side), the responses made from the taps of each call in
+ * the workspace; shorter signals take one time-domain launch per step. */
 typedef enum dbp_linear { DBP_LINEAR_FFT = 0, DBP_LINEAR_FIR = 1 } dbp_linear;
 
 /* DBP_FP32: dispersion tables and nonlinear phase argument in FP32.
@@ -247,14 +252,16 @@ dbp_status dbp_backprop_noalloc(dbp_plan_t plan, const void* in, void* out, cons
  * and grad_fir (device complex64 [N_s][n_fir], FIR plans; may be NULL; must
  * be NULL for FFT-step plans, which have no FIR taps).  taps and fir
  * override the plan's parameters as in dbp_backprop.
- *   FIR plans: the forward pass runs once storing the input of every step,
- *     then the adjoint steps run in reverse, each from its step's input and
- *     output (the output gives the nonlinear substep's intensity and the FIR
- *     output without evaluating the FIR again).  With DBP_FLAG_GRAD_SPARSE, or
- *     when those N_s states would take more than 4 GiB, it stores every 8th
- *     step's input instead and recomputes each 8-step segment from its
- *     checkpoint before the segment's adjoint steps (less workspace, about
- *     one more forward pass of time).
+ *   FIR plans: the forward pass runs once storing the input of every step
+ *     (one time-domain launch per step), then the adjoint steps run in
+ *     reverse, each from its step's input and output (the output gives the
+ *     nonlinear substep's intensity and the FIR output without evaluating the
+ *     FIR again).  With DBP_FLAG_GRAD_SPARSE, or when those N_s states would
+ *     take more than 4 GiB, it stores every 8th step's input instead (each
+ *     8-step segment run as FFT-block passes on signals of at least 1024
+ *     samples) and recomputes each segment step by step from its checkpoint
+ *     before the segment's adjoint steps (less workspace, about one more
+ *     forward pass of time).
  *   FFT-step plans (overlap-and-save, Sec. III): the derivative of exactly the
  *     blocked cascade dbp_backprop computes (same Nb, O, k).  The passes run
  *     forward once storing every pass input; then each pass, in reverse,

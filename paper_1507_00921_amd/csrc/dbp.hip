@@ -268,14 +268,26 @@ dbp_status choose_geometry(const dbp_desc* d, const std::vector<double>& b, Geom
     const int ns = (int)b.size();
     const int nc = d->method == DBP_ESSFM ? (d->n_taps - 1) / 2 : 0;
     if (d->linear == DBP_LINEAR_FIR) {
-        // time-domain steps: one launch per step on tiles whose halo covers the
-        // FIR and tap spans, so tiling is exact for any signal length
         if (nc > FT_MAXC || (d->n_fir - 1) / 2 > FT_MAXH) return DBP_ERR_UNSUPPORTED;
+        g.n_steps = ns;
+        if (d->n_samples >= FIR_FFT_NB) {
+            // forward steps as overlap-and-save FFT blocks: the FIR's frequency response
+            // applied per block is exact (finite support) while the halo covers the spread
+            // of the pass, (n_fir - 1) / 2 + N_c samples per step on each side
+            g.block = FIR_FFT_NB;
+            g.overlap = FIR_FFT_OVERLAP;
+            g.e = 4;
+            const int kmax = std::max(1, (FIR_FFT_OVERLAP / 2) / ((d->n_fir - 1) / 2 + nc));
+            g.k = balance_k(ns, std::min(kmax, ns));
+            g.n_passes = (ns + g.k - 1) / g.k;
+            return DBP_OK;
+        }
+        // shorter signals: time-domain steps, one launch per step on tiles whose halo
+        // covers the FIR and tap spans, so tiling is exact for any signal length
         g.block = fir_fwd_tile(d->n_fir, 2 * nc + 1);
         g.overlap = 2 * ((d->n_fir - 1) / 2 + nc);
         g.k = 1;
         g.e = 0;
-        g.n_steps = ns;
         g.n_passes = ns;
         return DBP_OK;
     }
@@ -911,6 +923,15 @@ dbp_status dbp_plan(const dbp_desc* desc, dbp_plan_t* out) {
         else
             std::snprintf(p->kernel_name, sizeof(p->kernel_name), "dbp_pass_kernel<%d, %d, %d, %s, %d>", nb,
                           p->geo.e, desc->n_pol, b, nt);
+    } else if (p->geo.block == FIR_FFT_NB) {
+        const int nt = tap_variant(desc->method, desc->n_taps);
+        p->fir_fft_launch = (void*)find_kernel(FIR_FFT_NB, p->geo.e, desc->n_pol, fp64, nt);
+        if (!p->fir_fft_launch) {
+            delete p;
+            return DBP_ERR_UNSUPPORTED;
+        }
+        std::snprintf(p->kernel_name, sizeof(p->kernel_name), "dbp_pass_kernel<%d, %d, %d, %s, %d>", FIR_FFT_NB,
+                      p->geo.e, desc->n_pol, fp64 ? "true" : "false", nt);
     } else {
         std::snprintf(p->kernel_name, sizeof(p->kernel_name), "fir_step_kernel<%d>", desc->n_pol);
     }
@@ -959,7 +980,12 @@ dbp_status dbp_plan(const dbp_desc* desc, dbp_plan_t* out) {
         steps[s].phi64 = p->phi[s];
     }
     std::vector<float2> tw;
-    if (!fir_mode) twiddle_table(nb, tw);
+    if (!fir_mode || p->fir_fft_launch) twiddle_table(nb, tw);
+    std::vector<StepDev> fsteps;
+    if (p->fir_fft_launch) {
+        fsteps = steps;
+        for (int s = 0; s < ns; ++s) fsteps[s].h_off = s * FIR_FFT_NB;
+    }
     std::vector<float> taps;
     if (desc->method == DBP_ESSFM) {
         const int nt = desc->n_taps;
@@ -1007,7 +1033,8 @@ dbp_status dbp_plan(const dbp_desc* desc, dbp_plan_t* out) {
         (st = upload((void**)&p->d_tw, tw.data(), tw.size() * sizeof(float2))) != DBP_OK ||
         (st = upload((void**)&p->d_steps, steps.data(), steps.size() * sizeof(StepDev))) != DBP_OK ||
         (st = upload((void**)&p->d_taps, taps.data(), taps.size() * sizeof(float))) != DBP_OK ||
-        (st = upload((void**)&p->d_fir, fir.data(), fir.size() * sizeof(float2))) != DBP_OK) {
+        (st = upload((void**)&p->d_fir, fir.data(), fir.size() * sizeof(float2))) != DBP_OK ||
+        (st = upload((void**)&p->d_fsteps, fsteps.data(), fsteps.size() * sizeof(StepDev))) != DBP_OK) {
         dbp_destroy(p);
         return st;
     }
@@ -1027,6 +1054,7 @@ void dbp_destroy(dbp_plan_t p) {
     if (p->d_steps) (void)hipFree(p->d_steps);
     if (p->d_taps) (void)hipFree(p->d_taps);
     if (p->d_fir) (void)hipFree(p->d_fir);
+    if (p->d_fsteps) (void)hipFree(p->d_fsteps);
     if (p->d_frag) (void)hipFree(p->d_frag);
     if (p->d_xb) (void)hipFree(p->d_xb);
     if (p->d_pub) (void)hipFree(p->d_pub);
@@ -1087,6 +1115,12 @@ static FirGeo fir_geo(const Plan* p) {
     return f;
 }
 
+// The per-step FIR frequency responses of a FIR plan whose forward steps run as FFT blocks
+// (made at call time in the workspace, after the states).
+static size_t fir_table_bytes(const Plan* p) {
+    return p->fir_fft_launch ? (size_t)p->geo.n_steps * FIR_FFT_NB * sizeof(float2) : 0;
+}
+
 // Workspace of the checkpointed gradient: checkpoints 1.., the inputs of the
 // steps 1.. of one segment, two gradient buffers, the last step's output, then
 // the per-tile partials.
@@ -1094,7 +1128,7 @@ static size_t grad_ws_bytes(const Plan* p) {
     const FirGeo f = fir_geo(p);
     const size_t state = p->state_bytes();
     const size_t part = (size_t)p->geo.n_steps * f.n_wg * f.width * sizeof(float);
-    return (size_t)(f.n_ckpt - 1 + f.seg - 1 + 3) * state + part;
+    return (size_t)(f.n_ckpt - 1 + f.seg - 1 + 3) * state + part + fir_table_bytes(p);
 }
 
 // FFT-step plans: geometry of the reverse pass.
@@ -1253,6 +1287,7 @@ struct FirWs {
     size_t state;
     int b_seg, b_grad, b_out;
     float* part;
+    float2* tables;         // the steps' FIR frequency responses (FFT-block plans), after the partials
     float2* buf(int i) const { return (float2*)(w + (size_t)i * state); }
 };
 
@@ -1265,7 +1300,50 @@ static FirWs fir_ws(const Plan* p, void* ws) {
     r.b_grad = r.b_seg + f.seg - 1;
     r.b_out = r.b_grad + 2;
     r.part = (float*)(r.w + (size_t)(r.b_out + 1) * r.state);
+    r.tables = (float2*)((char*)r.part + (size_t)p->geo.n_steps * f.n_wg * f.width * sizeof(float));
     return r;
+}
+
+// One forward step of a FIR plan from x to z in the time domain (the states the reverse
+// pass reads are made one step per launch).
+static dbp_status fir_forward_step(Plan* p, int st, const float* taps, const void* fir, const float2* x, float2* z,
+                                   hipStream_t s) {
+    FirArgs a = fir_args(p, st, taps, fir);
+    a.x = x;
+    a.z = z;
+    return launch_fir_step(p->desc.n_pol, a, s) == hipSuccess ? DBP_OK : DBP_ERR_HIP;
+}
+
+// Steps [s0, s0 + len) of a FIR plan on FFT blocks, from x to dst, in passes of as many steps
+// as the halo covers (intermediate pass outputs alternate between t0 and t1).
+static dbp_status fir_fft_range(Plan* p, const float* taps, const float2* tables, const float2* x, float2* dst,
+                                int s0, int len, float2* t0, float2* t1, hipStream_t s) {
+    const int nc = p->desc.method == DBP_ESSFM ? (p->desc.n_taps - 1) / 2 : 0;
+    const int kmax = std::max(1, (p->geo.overlap / 2) / ((p->desc.n_fir - 1) / 2 + nc));
+    const int k = balance_k(len, std::min(kmax, len));
+    const int passes = (len + k - 1) / k;
+    PassArgs a{};
+    a.L = p->desc.n_samples;
+    a.V = p->geo.block - p->geo.overlap;
+    a.halo = p->geo.overlap / 2;
+    a.n_blk = (int)((a.L + a.V - 1) / a.V);
+    a.n_wg = a.n_blk * p->desc.batch;
+    a.steps = p->d_fsteps;
+    a.H = tables;
+    a.tw = p->d_tw;
+    a.taps = p->desc.method == DBP_ESSFM ? (taps ? taps : p->d_taps) : nullptr;
+    a.ntaps = p->desc.method == DBP_ESSFM ? p->desc.n_taps : 1;
+    const float2* src = x;
+    for (int q = 0; q < passes; ++q) {
+        float2* out = q + 1 == passes ? dst : ((q & 1) ? t1 : t0);
+        a.in = src;
+        a.out = out;
+        a.s0 = s0 + q * k;
+        a.ks = std::min(k, s0 + len - a.s0);
+        if (((LaunchFn)p->fir_fft_launch)(a, a.n_wg, s) != hipSuccess) return DBP_ERR_HIP;
+        src = out;
+    }
+    return DBP_OK;
 }
 
 // Whether [a, a + na) and [b, b + nb) share a byte (null or empty ranges share none).
@@ -1303,16 +1381,29 @@ static dbp_status fir_grad_forward(Plan* p, const void* in, void* out, const flo
     const FirGeo f = fir_geo(p);
     const FirWs W = fir_ws(p, ws);
     const int ns = p->geo.n_steps;
+    if (p->fir_fft_launch && f.seg > 1) {
+        // only the checkpoints are kept: each segment runs as FFT passes (the segment
+        // buffers hold the passes' intermediate outputs until the reverse pass refills them)
+        if (launch_fir_tables(fir ? (const float2*)fir : p->d_fir, ns, p->desc.n_fir, p->d_tw, W.tables, s) !=
+            hipSuccess)
+            return DBP_ERR_HIP;
+        for (int c = 0; c < f.n_ckpt; ++c) {
+            const int s0 = c * f.seg, len = std::min(f.seg, ns - s0);
+            const float2* x = c == 0 ? (const float2*)in : W.buf(c - 1);
+            float2* dst = c + 1 < f.n_ckpt ? W.buf(c) : (float2*)out;
+            dbp_status e = fir_fft_range(p, taps, W.tables, x, dst, s0, len, W.buf(W.b_seg), W.buf(W.b_seg + 1), s);
+            if (e != DBP_OK) return e;
+        }
+        return DBP_OK;
+    }
     const float2* src = (const float2*)in;
     int tog = 0;
     for (int st = 0; st < ns; ++st) {
         float2* dst = st + 1 == ns               ? (float2*)out
                       : (st + 1) % f.seg == 0    ? W.buf((st + 1) / f.seg - 1)
                                                  : W.buf(W.b_seg + (tog ^= 1));
-        FirArgs a = fir_args(p, st, taps, fir);
-        a.x = src;
-        a.z = dst;
-        if (launch_fir_step(p->desc.n_pol, a, s) != hipSuccess) return DBP_ERR_HIP;
+        dbp_status e = fir_forward_step(p, st, taps, fir, src, dst, s);
+        if (e != DBP_OK) return e;
         src = dst;
     }
     return DBP_OK;
@@ -1335,10 +1426,9 @@ static dbp_status fir_grad_reverse(Plan* p, const void* in, const void* out, con
     for (int c = f.n_ckpt - 1; c >= 0; --c) {
         const int s0 = c * f.seg, len = std::min(f.seg, ns - s0);
         for (int j = 1; j < len; ++j) {
-            FirArgs a = fir_args(p, s0 + j - 1, taps, fir);
-            a.x = j == 1 ? ckpt(c) : W.buf(W.b_seg + j - 2);
-            a.z = W.buf(W.b_seg + j - 1);
-            if (launch_fir_step(npol, a, s) != hipSuccess) return DBP_ERR_HIP;
+            dbp_status e = fir_forward_step(p, s0 + j - 1, taps, fir, j == 1 ? ckpt(c) : W.buf(W.b_seg + j - 2),
+                                            W.buf(W.b_seg + j - 1), s);
+            if (e != DBP_OK) return e;
         }
         for (int j = len - 1; j >= 0; --j, ++r) {
             FirArgs a = fir_args(p, s0 + j, taps, fir, true);
@@ -1367,10 +1457,41 @@ size_t dbp_workspace_size(dbp_plan_t p, int32_t grad) {
     const size_t state = p->state_bytes();
     if (p->is_batch) return grad ? 0 : 2 * state;
     if (grad) return p->desc.linear == DBP_LINEAR_FIR ? grad_ws_bytes(p) : fft_grad_ws_bytes(p);
-    return p->geo.n_passes == 1 ? state : 2 * state;
+    return (p->geo.n_passes == 1 ? state : 2 * state) + fir_table_bytes(p);
 }
 
 }  // extern "C"
+
+// The passes of the plan's geometry, k steps each, from in to out through the
+// workspace states w0, w1 (the last pass lands in out; in place, the first pass
+// leaves in untouched until every block has read it).
+static dbp_status run_passes(Plan* p, LaunchFn fn, PassArgs a, int grid, const void* in, void* out, float2* w0,
+                             float2* w1, hipStream_t s) {
+    const Geometry& g = p->geo;
+    const bool inplace = in == out;
+    const int P = g.n_passes;
+    const float2* src = (const float2*)in;
+    for (int pass = 0; pass < P; ++pass) {
+        float2* dst;
+        if (P == 1) {
+            dst = inplace ? w0 : (float2*)out;
+        } else if (pass == 0 && inplace) {
+            dst = w1;
+        } else {
+            dst = ((P - 1 - pass) % 2 == 0) ? (float2*)out : w0;
+        }
+        a.in = src;
+        a.out = dst;
+        a.s0 = pass * g.k;
+        a.ks = std::min(g.k, g.n_steps - a.s0);
+        if (fn(a, grid, s) != hipSuccess) return DBP_ERR_HIP;
+        src = dst;
+    }
+    if (P == 1 && inplace) {
+        if (hipMemcpyAsync(out, w0, p->state_bytes(), hipMemcpyDeviceToDevice, s) != hipSuccess) return DBP_ERR_HIP;
+    }
+    return DBP_OK;
+}
 
 // The passes of dbp_backprop on a workspace the caller has checked to be at
 // least dbp_workspace_size(p, 0) bytes (or NULL when that size is 0).
@@ -1385,6 +1506,26 @@ static dbp_status backprop_passes(Plan* p, const void* in, void* out, const floa
     float2* w0 = (float2*)ws;
     float2* w1 = ws ? (float2*)((char*)ws + state) : nullptr;
     const bool inplace = in == out;
+    if (p->desc.linear == DBP_LINEAR_FIR && p->fir_fft_launch) {
+        // the steps' FIR frequency responses from the taps of this call, then FFT passes
+        float2* tab = (float2*)((char*)ws + (g.n_passes == 1 ? state : 2 * state));
+        if (launch_fir_tables(fir ? (const float2*)fir : p->d_fir, g.n_steps, p->desc.n_fir, p->d_tw, tab, s) !=
+            hipSuccess)
+            return DBP_ERR_HIP;
+        PassArgs a{};
+        a.L = p->desc.n_samples;
+        a.V = g.block - g.overlap;
+        a.halo = g.overlap / 2;
+        a.n_blk = (int)((a.L + a.V - 1) / a.V);
+        a.n_wg = a.n_blk * p->desc.batch;
+        a.steps = p->d_fsteps;
+        a.H = tab;
+        a.tw = p->d_tw;
+        a.taps = p->desc.method == DBP_ESSFM ? (taps ? taps : p->d_taps) : nullptr;
+        a.ntaps = p->desc.method == DBP_ESSFM ? p->desc.n_taps : 1;
+        a.nt_store = state > kStreamStoreBytes ? 1 : 0;
+        return run_passes(p, (LaunchFn)p->fir_fft_launch, a, a.n_wg, in, out, w0, w1, s);
+    }
     if (p->desc.linear == DBP_LINEAR_FIR) {
         const float2* src = (const float2*)in;
         const int P = g.n_steps;
@@ -1443,27 +1584,7 @@ static dbp_status backprop_passes(Plan* p, const void* in, void* out, const floa
         pa.spin_limit = 1LL << 20;
         return ((PersistLaunchFn)p->launch_persist)(pa, s) == hipSuccess ? DBP_OK : DBP_ERR_HIP;
     }
-    const float2* src = (const float2*)in;
-    for (int pass = 0; pass < P; ++pass) {
-        float2* dst;
-        if (P == 1) {
-            dst = inplace ? w0 : (float2*)out;
-        } else if (pass == 0 && inplace) {
-            dst = w1;
-        } else {
-            dst = ((P - 1 - pass) % 2 == 0) ? (float2*)out : w0;
-        }
-        a.in = src;
-        a.out = dst;
-        a.s0 = pass * g.k;
-        a.ks = std::min(g.k, g.n_steps - a.s0);
-        if (fn(a, grid, s) != hipSuccess) return DBP_ERR_HIP;
-        src = dst;
-    }
-    if (P == 1 && inplace) {
-        if (hipMemcpyAsync(out, w0, state, hipMemcpyDeviceToDevice, s) != hipSuccess) return DBP_ERR_HIP;
-    }
-    return DBP_OK;
+    return run_passes(p, fn, a, grid, in, out, w0, w1, s);
 }
 
 extern "C" {

@@ -20,6 +20,11 @@
 
 namespace dbp {
 
+// FIR plans on signals of at least this many samples run their forward steps as
+// overlap-and-save FFT blocks of this size (half the overlap is the halo).
+constexpr int FIR_FFT_NB = 1024;
+constexpr int FIR_FFT_OVERLAP = 256;
+
 constexpr int FT_THREADS = 256;
 constexpr int FT_SPAN = 768;      // FIR outputs per tile (the tile's samples and their halo)
 constexpr int FT_MAXH = 64;       // largest FIR half-width

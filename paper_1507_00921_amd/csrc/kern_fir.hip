@@ -80,6 +80,36 @@ hipError_t launch_fir_adjoint(int npol, const FirArgs& a, hipStream_t s) {
     return npol == 1 ? launch_nf<1>(true, a, sm, s) : launch_nf<2>(true, a, sm, s);
 }
 
+// Frequency response of every step's FIR for overlap-and-save blocks of FIR_FFT_NB points:
+// H[s][k] = (1 / NB) sum_m h[s][m] W^(k (m - HF)), W = exp(-2 pi i / NB) (the taps centred on
+// offset 0, as the time-domain step applies them; the inverse transform's 1 / NB folded in),
+// in natural bin order.  One workgroup per step; the twiddle table supplies W^q.
+__global__ __launch_bounds__(256) void fir_tables_kernel(const float2* __restrict__ h, int nfir,
+                                                         const float2* __restrict__ tw, float2* __restrict__ H) {
+    __shared__ float2 hs[2 * FT_MAXH + 1];
+    const int s = blockIdx.x, t = threadIdx.x;
+    const int HF = (nfir - 1) / 2;
+    for (int m = t; m < nfir; m += 256) hs[m] = h[(long long)s * nfir + m];
+    __syncthreads();
+    constexpr int NB = FIR_FFT_NB;
+    constexpr float inv = 1.0f / NB;
+    for (int k = t; k < NB; k += 256) {
+        float ax = 0.f, ay = 0.f;
+        for (int m = 0; m < nfir; ++m) {
+            const float2 w = tw[(k * (m - HF)) & (NB - 1)];
+            const float2 v = hs[m];
+            ax = fmaf(v.x, w.x, fmaf(-v.y, w.y, ax));
+            ay = fmaf(v.x, w.y, fmaf(v.y, w.x, ay));
+        }
+        H[(long long)s * NB + k] = make_float2(ax * inv, ay * inv);
+    }
+}
+
+hipError_t launch_fir_tables(const float2* h, int n_steps, int nfir, const float2* tw, float2* H, hipStream_t s) {
+    hipLaunchKernelGGL(fir_tables_kernel, dim3(n_steps), dim3(256), 0, s, h, nfir, tw, H);
+    return hipGetLastError();
+}
+
 hipError_t launch_reduce_partials(const float* part, int n_steps, int n_tiles, int nw, int nfir, float* wout,
                                   float* hout, hipStream_t s) {
     const long long waves = (long long)n_steps * (nw + 2 * nfir);

@@ -44,6 +44,10 @@ struct dbp_plan_s {
     int2* d_pub = nullptr;           // per block: published prefix / suffix of its centre
     int* d_err = nullptr;            // set when one of its waits gave up
     std::atomic<unsigned> flag_next{1};  // flag of the next call's first pass
+    // FIR plans whose forward steps run as overlap-and-save FFT blocks (geo holds their
+    // geometry; the per-step tables are made from the FIR taps at call time in the workspace)
+    void* fir_fft_launch = nullptr;
+    dbp::StepDev* d_fsteps = nullptr;        // their steps: table offset s * FIR_FFT_NB
     char kernel_name[96] = {0};      // the pass-kernel variant, as the profiler names it
     std::vector<float> h_taps;
 

@@ -97,7 +97,12 @@ static int check_fir_design() {
         d.n_fir = 33;
         d.fir_band_thz = band;
         int32_t nb, o, k;
-        CHECK(dbp_choose_geometry(&d, &nb, &o, &k) == DBP_OK && k == 1);
+        // 32768 samples: FFT blocks of 1024, the 8 steps of the SSFM link in one pass
+        // (halo 128 covers 16 samples of FIR spread per step)
+        CHECK(dbp_choose_geometry(&d, &nb, &o, &k) == DBP_OK && nb == 1024 && o == 256 && k == 8);
+        dbp_desc short_d = d;
+        short_d.n_samples = 1000;      // shorter than a block: one time-domain launch per step
+        CHECK(dbp_choose_geometry(&short_d, &nb, &o, &k) == DBP_OK && k == 1 && o == 32);
         std::vector<float> h(2 * 33);
         for (int s = 0; s < 8; ++s) {
             CHECK(dbp_fir_taps(&d, s, h.data()) == DBP_OK);

@@ -65,7 +65,11 @@ def dev(a, dtype=None):
 def test_fir_forward_parity(dbp, essfm, n_pol):
     xs, fir, taps, steps = setup(1, 2, n_pol, 5000, 12, essfm)
     p = make_plan(dbp, 5000, 12, 2, n_pol, taps, fir)
-    assert p.steps_per_pass == 1 and p.n_passes == 12
+    # at least 1024 samples: the FIR steps run as overlap-and-save FFT blocks, several steps
+    # per pass while the halo covers their spread (16 + N_c samples per step and side)
+    kmax = 128 // (16 + (0 if taps is None else 4))
+    passes = -(-12 // kmax)
+    assert (p.block, p.overlap, p.n_passes, p.steps_per_pass) == (1024, 256, passes, -(-12 // passes))
     y = p.backprop(dev(xs, np.complex64), taps=None if taps is None else dev(taps), fir=dev(fir))
     y = y.cpu().numpy().astype(np.complex128)
     for i in range(2):
@@ -156,10 +160,14 @@ def test_fir_gradient_parity_run_time_tap_counts(dbp, n_fir, nc, n_pol):
     assert eh <= 1e-4 and ew <= 1e-4
 
 
-def test_dense_and_sparse_checkpoints_give_identical_gradients(dbp):
-    # the recomputed segment states are the stored ones bit for bit, so both schedules
-    # return the same gradients exactly; the dense one needs more workspace
-    n, n_spans, batch = 2500, 19, 2
+@pytest.mark.parametrize("n", [2500, 900])
+def test_dense_and_sparse_checkpoints_give_the_same_gradients(dbp, n):
+    # dense: every step's input stored, one time-domain launch per step; sparse: the
+    # checkpoints come from FFT-block passes over each 8-step segment (signals of at least
+    # 1024 samples) and the segments are recomputed step by step.  The states agree to FP32
+    # rounding, so the gradients do (900 samples: time-domain steps throughout, bit for bit);
+    # the dense schedule needs more workspace
+    n_spans, batch = 19, 2
     xs, fir, taps, _ = setup(5, batch, 2, n, n_spans, True)
     g = np.random.default_rng(8)
     gout = dev((g.standard_normal(xs.shape) + 1j * g.standard_normal(xs.shape)).astype(np.complex64))
@@ -172,7 +180,13 @@ def test_dense_and_sparse_checkpoints_give_identical_gradients(dbp):
     (ws_dense, gd), (ws_sparse, gs) = out
     assert ws_dense > ws_sparse
     for a, b in zip(gd, gs):
-        assert torch.equal(a, b)
+        if n < 1024:
+            assert torch.equal(a, b)
+        else:
+            ea = field_err(b.numpy().astype(np.complex128 if b.is_complex() else np.float64),
+                           a.numpy().astype(np.complex128 if a.is_complex() else np.float64))
+            print(f"dense vs sparse: rel L2 {ea:.2e}")
+            assert ea <= 1e-5
 
 
 @pytest.mark.parametrize("sparse", [False, True])
@@ -190,7 +204,10 @@ def test_saved_forward_then_reverse_equals_backprop_grad(dbp, sparse):
     ref = p.backprop_grad(x, gout, taps=t, fir=f)
     out, ws = p.backprop_save(x, taps=t, fir=f)
     torch.cuda.synchronize()
-    assert torch.equal(torch.view_as_real(out), torch.view_as_real(ref_out))
+    # the saving forward keeps step states (time-domain steps, or FFT blocks per 8-step
+    # segment), the plain one runs FFT blocks of several steps: equal within the FP32 budget
+    # the path is held to against the oracle (the rounding of 19 steps taken two ways)
+    assert field_err(out.cpu().numpy(), ref_out.cpu().numpy()) <= 1e-5
     for _ in range(2):
         got = p.backprop_grad_saved(x, out, ws, gout, taps=t, fir=f)
         torch.cuda.synchronize()
@@ -200,7 +217,7 @@ def test_saved_forward_then_reverse_equals_backprop_grad(dbp, sparse):
     xr, tr, fr = x.clone().requires_grad_(True), t.clone().requires_grad_(True), f.clone().requires_grad_(True)
     y = dbp.dbp_function().apply(xr, tr, fr, p)
     (torch.view_as_real(y) * torch.view_as_real(gout)).sum().backward()
-    assert torch.equal(torch.view_as_real(y.detach()), torch.view_as_real(ref_out))
+    assert torch.equal(torch.view_as_real(y.detach()), torch.view_as_real(out))
     assert torch.equal(torch.view_as_real(xr.grad), torch.view_as_real(ref[0]))
     assert torch.equal(tr.grad, ref[1])
     assert torch.equal(torch.view_as_real(fr.grad), torch.view_as_real(ref[2]))
