@@ -306,7 +306,8 @@ dbp_status dbp_plan_batch(const dbp_desc* descs, int32_t n, dbp_plan_t* out);
 dbp_status dbp_batch_offsets(dbp_plan_t plan, int64_t* offsets, int32_t n_plus_1);
 
 /* Geometry chosen for signal i of a batch plan (the autotuner measures the
- * cost of each block size once per process and kernel variant, then picks
+ * cost of each block size once per process and kernel variant, timing the batch
+ * kernel on a synthetic signal at 1 and 4 steps per pass, then picks
  * for every signal the block, overlap and steps per pass of least modelled
  * time; explicit block/overlap/steps_per_pass in a descriptor are kept). */
 dbp_status dbp_batch_geometry(dbp_plan_t plan, int32_t i, int32_t* block, int32_t* overlap,

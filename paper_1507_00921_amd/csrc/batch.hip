@@ -22,8 +22,10 @@ namespace dbp {
 
 // ------------------------------------------------------------------ autotuner
 
-// Measured cost of one block item of a kernel variant at full occupancy:
-// c0 + k * c1 microseconds of chip time per block for a k-step pass.
+// Measured cost of one block item of a kernel variant in the persistent batch kernel:
+// c0 + k * c1 microseconds of chip time per block for a k-step pass.  c0 carries what a
+// pass costs beyond its steps there: the block's window load and store and its share of
+// the item's queue pop, dependency waits and cache writeback / invalidation.
 struct Cost {
     double c0 = 0, c1 = 0;
 };
@@ -33,86 +35,65 @@ static std::map<std::tuple<int, int, int, int, int>, Cost> g_costs;   // (device
 
 static const int kBatchBlocks[] = {256, 512, 1024, 2048, 4096};
 
-static float time_launches(LaunchFn fn, PassArgs& a, int reps, hipStream_t s) {
-    hipEvent_t e0, e1;
-    if (hipEventCreate(&e0) != hipSuccess) return -1.f;
-    if (hipEventCreate(&e1) != hipSuccess) {
-        (void)hipEventDestroy(e0);
-        return -1.f;
-    }
-    float ms = -1.f;
-    if (fn(a, a.n_wg, s) == hipSuccess && hipEventRecord(e0, s) == hipSuccess) {
-        bool ok = true;
-        for (int r = 0; r < reps && ok; ++r) ok = fn(a, a.n_wg, s) == hipSuccess;
-        if (ok && hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess)
-            (void)hipEventElapsedTime(&ms, e0, e1);
-    }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    return ms < 0 ? -1.f : ms / reps;
-}
-
-// Time the pass kernel of a variant on a synthetic signal of 2^22 samples per
-// polarization with O = Nb/2, at k = 1 and k = 4 steps per pass.
+// Time the batch kernel of a variant on one synthetic signal of 2^20 samples per
+// polarization, 8 steps, O = Nb/2, at 1 and at 4 steps per pass (8 and 2 passes): a plan
+// of the batch API itself, so that every per-item cost of the queue is in the figure.
 static dbp_status measure_cost(int npol, int nt, bool p64, int nb, Cost& out) {
-    const int e = measured_e(nb, 1 << 20);
-    LaunchFn fn = find_kernel(nb, e, npol, p64, nt);
-    if (!fn) return DBP_ERR_UNSUPPORTED;
-    const int V = nb / 2;
-    const long long L = 1LL << 22;
-    const int n_blk = (int)(L / V);
-    const int ntaps = nt > 0 ? nt : (nt < 0 ? 9 : 1);
-    std::vector<float2> h(nb, make_float2(1.0f / nb, 0.f)), tw;
-    twiddle_table(nb, tw);
-    std::vector<StepDev> st(4);
-    for (auto& x : st) {
-        x.h_off = 0;
-        x.phi = 0.01f;
-        x.phi64 = 0.01;
+    const int ntaps = nt > 0 ? nt : (nt < 0 ? 7 : 1);
+    std::vector<float> taps(ntaps, 1.0f / ntaps);
+    dbp_desc d;
+    dbp_desc_init(&d);
+    d.n_pol = npol;
+    d.batch = 1;
+    d.n_samples = 1LL << 20;
+    d.n_spans = 8;
+    d.steps_per_span = 1;
+    if (nt != 0) {
+        d.method = DBP_ESSFM;
+        d.n_taps = ntaps;
+        d.taps = taps.data();
     }
-    std::vector<float> taps(4 * ntaps, 1.0f / ntaps);
-    float2 *d_in = nullptr, *d_out = nullptr, *d_h = nullptr, *d_tw = nullptr;
-    StepDev* d_st = nullptr;
-    float* d_taps = nullptr;
-    const size_t bytes = (size_t)npol * L * sizeof(float2);
-    dbp_status rc = DBP_ERR_HIP;
+    d.precision = p64 ? DBP_FP32_FP64PHASE : DBP_FP32;
+    d.block = nb;
+    d.overlap = nb / 2;
+    const size_t bytes = (size_t)npol * d.n_samples * sizeof(float2);
+    float2 *d_in = nullptr, *d_out = nullptr;
+    void* d_ws = nullptr;
     hipStream_t s = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    dbp_status rc = DBP_ERR_HIP;
+    float ms[2] = {-1.f, -1.f};
     if (device_alloc(&d_in, bytes) == hipSuccess && device_alloc(&d_out, bytes) == hipSuccess &&
-        device_alloc(&d_h, nb * sizeof(float2)) == hipSuccess && device_alloc(&d_tw, nb * sizeof(float2)) == hipSuccess &&
-        device_alloc(&d_st, st.size() * sizeof(StepDev)) == hipSuccess &&
-        device_alloc(&d_taps, taps.size() * sizeof(float)) == hipSuccess &&
-        hipMemset(d_in, 0, bytes) == hipSuccess &&
-        hipMemcpy(d_h, h.data(), nb * sizeof(float2), hipMemcpyHostToDevice) == hipSuccess &&
-        hipMemcpy(d_tw, tw.data(), nb * sizeof(float2), hipMemcpyHostToDevice) == hipSuccess &&
-        hipMemcpy(d_st, st.data(), st.size() * sizeof(StepDev), hipMemcpyHostToDevice) == hipSuccess &&
-        hipMemcpy(d_taps, taps.data(), taps.size() * sizeof(float), hipMemcpyHostToDevice) == hipSuccess &&
-        hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess) {
-        PassArgs a{};
-        a.in = d_in;
-        a.out = d_out;
-        a.L = L;
-        a.V = V;
-        a.halo = (nb - V) / 2;
-        a.n_blk = n_blk;
-        a.n_wg = n_blk;
-        a.steps = d_st;
-        a.s0 = 0;
-        a.H = d_h;
-        a.tw = d_tw;
-        a.taps = nt == 0 ? nullptr : d_taps;
-        a.ntaps = ntaps;
-        a.ks = 1;
-        const float t1 = time_launches(fn, a, 3, s);
-        a.ks = 4;
-        const float t4 = time_launches(fn, a, 3, s);
-        if (t1 > 0 && t4 > 0) {
-            out.c1 = std::max(0.0, (t4 - t1) / 3.0) * 1e3 / n_blk;
-            out.c0 = std::max(1e-6, t1 * 1e3 / n_blk - out.c1);
-            rc = DBP_OK;
+        device_alloc(&d_ws, 2 * bytes) == hipSuccess && hipMemset(d_in, 0, bytes) == hipSuccess &&
+        hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess && hipEventCreate(&e0) == hipSuccess &&
+        hipEventCreate(&e1) == hipSuccess) {
+        rc = DBP_OK;
+        for (int i = 0; i < 2 && rc == DBP_OK; ++i) {
+            d.steps_per_pass = i == 0 ? 1 : 4;
+            dbp_plan_t bp = nullptr;
+            rc = dbp_plan_batch(&d, 1, &bp);
+            if (rc != DBP_OK) break;
+            rc = dbp_backprop_batch(bp, d_in, d_out, d_ws, 2 * bytes, s);   // warm-up
+            if (rc == DBP_OK && hipEventRecord(e0, s) != hipSuccess) rc = DBP_ERR_HIP;
+            for (int r = 0; r < 3 && rc == DBP_OK; ++r) rc = dbp_backprop_batch(bp, d_in, d_out, d_ws, 2 * bytes, s);
+            if (rc == DBP_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                                 hipEventElapsedTime(&ms[i], e0, e1) != hipSuccess))
+                rc = DBP_ERR_HIP;
+            dbp_destroy(bp);
         }
     }
+    if (rc == DBP_OK && ms[0] > 0 && ms[1] > 0) {
+        const double n_blk = (double)((d.n_samples + nb / 2 - 1) / (nb / 2));
+        const double t1 = ms[0] / 3 * 1e3 / n_blk, t4 = ms[1] / 3 * 1e3 / n_blk;   // us per block
+        out.c0 = std::max(1e-6, (t1 - t4) / 6.0);                                     // 8 vs 2 passes
+        out.c1 = std::max(1e-6, (t1 - 8.0 * out.c0) / 8.0);
+    } else if (rc == DBP_OK) {
+        rc = DBP_ERR_HIP;
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
     if (s) (void)hipStreamDestroy(s);
-    for (void* ptr : {(void*)d_in, (void*)d_out, (void*)d_h, (void*)d_tw, (void*)d_st, (void*)d_taps})
+    for (void* ptr : {(void*)d_in, (void*)d_out, d_ws})
         if (ptr) (void)hipFree(ptr);
     return rc;
 }
