@@ -41,6 +41,8 @@ def _makers(dbp):
     return {
         "plan": lambda: dbp.plan(262144, 40, 1, taps=TAPS9, block=1024, overlap=256, beta2_ps2_km=B2),
         "plan_tuned": lambda: dbp.plan(1 << 20, 8, 1, taps=TAPS9, beta2_ps2_km=B2, tune=True),
+        "plan_fir": lambda: dbp.plan(4096, 8, 1, taps=TAPS9, linear=dbp.LINEAR_FIR, n_fir=33, fir_band_thz=0.0154,
+                                     beta2_ps2_km=B2),
         "batch": lambda: dbp.plan_batch(descs),
         "receiver": lambda: dbp.receiver(64 * 768, 40, 1, taps=TAPS9, block=1024, overlap=256, beta2_ps2_km=B2),
         "dsp": lambda: dbp.receiver_dsp(234050),
@@ -48,7 +50,7 @@ def _makers(dbp):
     }
 
 
-@pytest.mark.parametrize("what", ["plan", "plan_tuned", "batch", "receiver", "dsp", "mse"])
+@pytest.mark.parametrize("what", ["plan", "plan_tuned", "plan_fir", "batch", "receiver", "dsp", "mse"])
 def test_allocation_failures_are_reported_and_released(dbp, monkeypatch, what):
     make = _makers(dbp)[what]
     make().close()                   # first use: runtime and autotuner state, outside the count
@@ -74,8 +76,9 @@ def test_allocation_failures_are_reported_and_released(dbp, monkeypatch, what):
     assert abs(free1 - free0) <= 4 * MIB
     # the library still works after the failures
     obj = make()
-    if what == "plan":
-        x = torch.zeros(1, 2, 262144, dtype=torch.complex64, device="cuda")
+    if what in ("plan", "plan_fir"):
+        n = 262144 if what == "plan" else 4096
+        x = torch.zeros(1, 2, n, dtype=torch.complex64, device="cuda")
         y = obj.backprop(x)
         torch.cuda.synchronize()
         assert torch.count_nonzero(y).item() == 0
