@@ -253,15 +253,16 @@ dbp_status dbp_backprop_noalloc(dbp_plan_t plan, const void* in, void* out, cons
  * be NULL for FFT-step plans, which have no FIR taps).  taps and fir
  * override the plan's parameters as in dbp_backprop.
  *   FIR plans: the forward pass runs once storing the input of every step
- *     (one time-domain launch per step), then the adjoint steps run in
+ *     (FFT-block passes that keep each step's state; one time-domain launch
+ *     per step on signals under 1024 samples), then the adjoint steps run in
  *     reverse, each from its step's input and output (the output gives the
  *     nonlinear substep's intensity and the FIR output without evaluating the
  *     FIR again).  With DBP_FLAG_GRAD_SPARSE, or when those N_s states would
  *     take more than 4 GiB, it stores every 8th step's input instead (each
  *     8-step segment run as FFT-block passes on signals of at least 1024
- *     samples) and recomputes each segment step by step from its checkpoint
- *     before the segment's adjoint steps (less workspace, about one more
- *     forward pass of time).
+ *     samples) and recomputes each segment from its checkpoint before the
+ *     segment's adjoint steps (less workspace, about one more forward pass of
+ *     time).
  *   FFT-step plans (overlap-and-save, Sec. III): the derivative of exactly the
  *     blocked cascade dbp_backprop computes (same Nb, O, k).  The passes run
  *     forward once storing every pass input; then each pass, in reverse,

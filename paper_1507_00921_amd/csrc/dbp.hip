@@ -24,6 +24,7 @@
 #include "fir_launch.hpp"
 #include "mfma_kernel.hpp"
 #include "persist_launch.hpp"
+#include "each_kernel.hpp"
 
 namespace dbp {
 
@@ -926,7 +927,8 @@ dbp_status dbp_plan(const dbp_desc* desc, dbp_plan_t* out) {
     } else if (p->geo.block == FIR_FFT_NB) {
         const int nt = tap_variant(desc->method, desc->n_taps);
         p->fir_fft_launch = (void*)find_kernel(FIR_FFT_NB, p->geo.e, desc->n_pol, fp64, nt);
-        if (!p->fir_fft_launch) {
+        p->fir_each_launch = (void*)find_each_kernel(desc->n_pol, fp64, nt);
+        if (!p->fir_fft_launch || !p->fir_each_launch) {
             delete p;
             return DBP_ERR_UNSUPPORTED;
         }
@@ -1315,9 +1317,11 @@ static dbp_status fir_forward_step(Plan* p, int st, const float* taps, const voi
 }
 
 // Steps [s0, s0 + len) of a FIR plan on FFT blocks, from x to dst, in passes of as many steps
-// as the halo covers (intermediate pass outputs alternate between t0 and t1).
+// as the halo covers.  Without `each` the intermediate pass outputs alternate between t0
+// and t1; with it the output of step s0 + i (i < len - 1) is kept in each + i * stride
+// (consecutive workspace states) and only the last one goes to dst.
 static dbp_status fir_fft_range(Plan* p, const float* taps, const float2* tables, const float2* x, float2* dst,
-                                int s0, int len, float2* t0, float2* t1, hipStream_t s) {
+                                int s0, int len, float2* t0, float2* t1, hipStream_t s, float2* each = nullptr) {
     const int nc = p->desc.method == DBP_ESSFM ? (p->desc.n_taps - 1) / 2 : 0;
     const int kmax = std::max(1, (p->geo.overlap / 2) / ((p->desc.n_fir - 1) / 2 + nc));
     const int k = balance_k(len, std::min(kmax, len));
@@ -1333,14 +1337,21 @@ static dbp_status fir_fft_range(Plan* p, const float* taps, const float2* tables
     a.tw = p->d_tw;
     a.taps = p->desc.method == DBP_ESSFM ? (taps ? taps : p->d_taps) : nullptr;
     a.ntaps = p->desc.method == DBP_ESSFM ? p->desc.n_taps : 1;
+    const long long stride = (long long)(p->state_bytes() / sizeof(float2));
     const float2* src = x;
     for (int q = 0; q < passes; ++q) {
-        float2* out = q + 1 == passes ? dst : ((q & 1) ? t1 : t0);
-        a.in = src;
-        a.out = out;
         a.s0 = s0 + q * k;
         a.ks = std::min(k, s0 + len - a.s0);
-        if (((LaunchFn)p->fir_fft_launch)(a, a.n_wg, s) != hipSuccess) return DBP_ERR_HIP;
+        const int last = a.s0 + a.ks - 1 - s0;           // index in the range of the pass's last step
+        float2* out = q + 1 == passes ? dst : (each ? each + last * stride : ((q & 1) ? t1 : t0));
+        a.in = src;
+        a.out = out;
+        if (each) {
+            if (((EachLaunchFn)p->fir_each_launch)(a, each + (a.s0 - s0) * stride, stride, s) != hipSuccess)
+                return DBP_ERR_HIP;
+        } else if (((LaunchFn)p->fir_fft_launch)(a, a.n_wg, s) != hipSuccess) {
+            return DBP_ERR_HIP;
+        }
         src = out;
     }
     return DBP_OK;
@@ -1381,12 +1392,17 @@ static dbp_status fir_grad_forward(Plan* p, const void* in, void* out, const flo
     const FirGeo f = fir_geo(p);
     const FirWs W = fir_ws(p, ws);
     const int ns = p->geo.n_steps;
-    if (p->fir_fft_launch && f.seg > 1) {
+    if (p->fir_fft_launch &&
+        launch_fir_tables(fir ? (const float2*)fir : p->d_fir, ns, p->desc.n_fir, p->d_tw, W.tables, s) != hipSuccess)
+        return DBP_ERR_HIP;
+    if (p->fir_fft_launch && f.seg == 1) {
+        // every step's input kept: FFT passes that leave each step's state in the checkpoints
+        return fir_fft_range(p, taps, W.tables, (const float2*)in, (float2*)out, 0, ns, nullptr, nullptr, s,
+                             ns > 1 ? W.buf(0) : nullptr);
+    }
+    if (p->fir_fft_launch) {
         // only the checkpoints are kept: each segment runs as FFT passes (the segment
         // buffers hold the passes' intermediate outputs until the reverse pass refills them)
-        if (launch_fir_tables(fir ? (const float2*)fir : p->d_fir, ns, p->desc.n_fir, p->d_tw, W.tables, s) !=
-            hipSuccess)
-            return DBP_ERR_HIP;
         for (int c = 0; c < f.n_ckpt; ++c) {
             const int s0 = c * f.seg, len = std::min(f.seg, ns - s0);
             const float2* x = c == 0 ? (const float2*)in : W.buf(c - 1);
@@ -1425,7 +1441,13 @@ static dbp_status fir_grad_reverse(Plan* p, const void* in, const void* out, con
     int r = 0;
     for (int c = f.n_ckpt - 1; c >= 0; --c) {
         const int s0 = c * f.seg, len = std::min(f.seg, ns - s0);
-        for (int j = 1; j < len; ++j) {
+        if (p->fir_fft_launch && len > 1) {
+            // the inputs of the segment's steps 1.. on FFT blocks, each step's state kept
+            dbp_status e = fir_fft_range(p, taps, W.tables, ckpt(c), W.buf(W.b_seg + len - 2), s0, len - 1, nullptr,
+                                         nullptr, s, len > 2 ? W.buf(W.b_seg) : nullptr);
+            if (e != DBP_OK) return e;
+        }
+        for (int j = 1; j < len && !p->fir_fft_launch; ++j) {
             dbp_status e = fir_forward_step(p, s0 + j - 1, taps, fir, j == 1 ? ckpt(c) : W.buf(W.b_seg + j - 2),
                                             W.buf(W.b_seg + j - 1), s);
             if (e != DBP_OK) return e;

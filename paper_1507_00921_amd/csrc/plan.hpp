@@ -47,6 +47,7 @@ struct dbp_plan_s {
     // FIR plans whose forward steps run as overlap-and-save FFT blocks (geo holds their
     // geometry; the per-step tables are made from the FIR taps at call time in the workspace)
     void* fir_fft_launch = nullptr;
+    void* fir_each_launch = nullptr;         // the same steps, keeping the state after each step
     dbp::StepDev* d_fsteps = nullptr;        // their steps: table offset s * FIR_FFT_NB
     char kernel_name[96] = {0};      // the pass-kernel variant, as the profiler names it
     std::vector<float> h_taps;
