@@ -297,6 +297,35 @@ def hbm_working_set(dbp, torch, rx, taps, batch=64, reps=10, only=None, only_var
     return res
 
 
+def small_whole_signal(dbp, torch, reps=50):
+    """The single-polarization whole-signal case: 16384 samples, 4 x 80 km, one step per span on
+    one circular block of the whole signal (Sec. II with Nb = L).  Microseconds per DBP (one
+    short launch: latency, not a roofline) and EVM beside the dispersion-only receiver.  The
+    channel runs on the GPU: 1000 fine steps at 0 dBm, then ASE at 20 dB OSNR."""
+    n, spans = 16384, 4
+    b2 = siggen.beta2_ps2_km()
+    x, sym = siggen.transmitted_field(0, 0, 1, n, 0.0)
+    fwd = dbp.plan(n, spans, 250, n_pol=1, forward=True, whole=True, beta2_ps2_km=b2)
+    r = fwd.backprop(torch.from_numpy(x.astype(np.complex64)).reshape(1, 1, n).cuda())
+    torch.cuda.synchronize()
+    r = siggen.add_awgn(siggen.rng(0, 0, 2), r.cpu().numpy().reshape(1, n).astype(np.complex128),
+                        siggen.awgn_sigma2(siggen.dbm_to_w(0.0), OSNR_DB))
+    rx = torch.from_numpy(r.astype(np.complex64)).reshape(1, 1, n).cuda()
+    res = {"workload": "1x16384 (one polarization), 4x80 km, 0 dBm, 20 dB OSNR; SSFM one step per span, "
+                       "whole-signal FFT"}
+    for name, kw in (("ssfm_1_per_span", {}), ("cd_only", {"gamma_w_km": 0.0})):
+        p = dbp.plan(n, spans, 1, n_pol=1, whole=True, beta2_ps2_km=b2, **kw)
+        out = torch.empty_like(rx)
+        us = time_dbp_settled(torch, p, rx, out, p.workspace(), reps=reps) * 1e3
+        y = p.backprop(rx)
+        evm = siggen.evm_db(y.cpu().numpy().reshape(1, n).astype(np.complex128), sym)
+        res[name] = {"geometry": [p.block, p.overlap, p.steps_per_pass], "kernel": p.kernel,
+                     "us_per_dbp": round(us, 2), "msamples_per_s": round(n / us, 2), "evm_db": round(evm, 3)}
+        p.close()
+    fwd.close()
+    return res
+
+
 def fft_gradient(torch, plan, rx, reps=10):
     """Reverse mode of the headline ESSFM cascade (Nb=1024 O=256, k=5): input and tap
     gradients for a fixed upstream gradient; one call = forward storing the 8 pass inputs +
@@ -944,7 +973,8 @@ def main():
                     help="with --hbm-only: one case (e.g. k1_nb512), 2 + 10 launches (for counter runs)")
     ap.add_argument("--hbm-variant", default="per_block", choices=("per_block", "stream"),
                     help="with --hbm-case: the per-block kernel (the planner's default) or the streaming twin")
-    ap.add_argument("--only", default=None, choices=("precision", "gradient", "batch", "geometry", "ase"),
+    ap.add_argument("--only", default=None,
+                    choices=("precision", "gradient", "batch", "geometry", "ase", "whole"),
                     help="run one secondary workload alone and print its JSON (for profiler runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a plain 1 GiB device copy three times and exit (counter calibration)")
@@ -979,6 +1009,9 @@ def main():
                                                                      spans_per_step=SPANS))
         taps9, _ = fit_taps(dbp, torch, rx, target)
         print(json.dumps(measured_geometry(dbp, torch, rx, link, taps9)), flush=True)
+        return
+    if args.only == "whole":
+        print(json.dumps(small_whole_signal(dbp, torch)), flush=True)
         return
     if args.only:
         fn = {"precision": precision_workload, "gradient": grad_workload, "batch": batch_workload}[args.only]
@@ -1047,6 +1080,8 @@ def main():
             "objective": "sum over samples 1024..99999 of |ESSFM(c) - SSFM 20 steps/span|^2, both pols",
         }
         log("coefficient fit " + json.dumps(extras["coefficient_fit"]))
+        extras["whole_signal"] = small_whole_signal(dbp, torch)
+        log("whole-signal case " + json.dumps(extras["whole_signal"]))
         extras["fft_gradient"] = fft_gradient(torch, essfm, rx)
         log("FFT-step gradient " + json.dumps(extras["fft_gradient"]))
         extras["receiver"] = {f"chunk_{cb}_blocks": receiver_workload(dbp, torch, rx, taps, chunk_blocks=cb)

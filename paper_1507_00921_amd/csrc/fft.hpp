@@ -18,6 +18,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
 #include <utility>
 
 namespace dbp {
@@ -159,6 +160,11 @@ template <int NB, int E> struct FftShape {
     static constexpr int tw_off(int p) { return p == 0 ? 0 : tw_off(p - 1) + n_tw(p - 1); }
     static constexpr int NTW = tw_off(P);
     static constexpr int NTW_ALLOC = NTW > 0 ? NTW : 1;
+    // Blocks of 8192 points and more read their inter-pass twiddles from the table (it stays
+    // in the L2) instead of holding them in registers: 38-42 complex values per thread there,
+    // which with the data and the dispersion factors exceed what a thread of a 512- or
+    // 1024-thread workgroup may hold, and spilled to scratch.
+    static constexpr bool TW_MEM = NB >= 8192;
     // LDS position of element i: the low five bits XORed with the five bits
     // above log2(E), a bijection on [0, NB) that spreads both the NB/R-strided
     // Stockham writes and the T-strided reads over all banks
@@ -166,35 +172,45 @@ template <int NB, int E> struct FftShape {
     static constexpr int PADDED = NB;
 };
 
-template <int NB, int E> using TwReg = float2[FftShape<NB, E>::NTW_ALLOC];
+// Where a transform finds its inter-pass twiddles: per-thread registers loaded once per launch,
+// or (TW_MEM shapes) the table itself.
+struct TwTable {
+    const float2* __restrict__ p;   // tw[q] = exp(-2 pi i q / NB)
+};
+template <int NB, int E>
+using TwReg = std::conditional_t<FftShape<NB, E>::TW_MEM, TwTable, float2[FftShape<NB, E>::NTW_ALLOC]>;
 
 // Load the per-thread twiddles of every pass from the table tw[q] = exp(-2 pi i q / NB).
 template <int NB, int E>
 __device__ __forceinline__ void load_twiddles(TwReg<NB, E>& twr,
                                               const float2* __restrict__ tw, int t) {
     using S = FftShape<NB, E>;
-    [&]<int... Ps>(std::integer_sequence<int, Ps...>) {
-        (([&] {
-             constexpr int p = Ps;
-             if constexpr (p > 0) {
-                 constexpr int R = S::radix(p), LS = S::ls(p), M = E / R;
-                 constexpr int stride = NB / (LS * R);
-                 if constexpr (LS <= S::T) {
-                     const int k = t & (LS - 1);
+    if constexpr (S::TW_MEM) {
+        twr.p = tw;
+    } else {
+        [&]<int... Ps>(std::integer_sequence<int, Ps...>) {
+            (([&] {
+                 constexpr int p = Ps;
+                 if constexpr (p > 0) {
+                     constexpr int R = S::radix(p), LS = S::ls(p), M = E / R;
+                     constexpr int stride = NB / (LS * R);
+                     if constexpr (LS <= S::T) {
+                         const int k = t & (LS - 1);
 #pragma unroll
-                     for (int r = 1; r < R; ++r) twr[S::tw_off(p) + r - 1] = tw[r * k * stride];
-                 } else {
+                         for (int r = 1; r < R; ++r) twr[S::tw_off(p) + r - 1] = tw[r * k * stride];
+                     } else {
 #pragma unroll
-                     for (int m = 0; m < M; ++m) {
-                         const int k = (t + m * S::T) & (LS - 1);
+                         for (int m = 0; m < M; ++m) {
+                             const int k = (t + m * S::T) & (LS - 1);
 #pragma unroll
-                         for (int r = 1; r < R; ++r) twr[S::tw_off(p) + m * (R - 1) + r - 1] = tw[r * k * stride];
+                             for (int r = 1; r < R; ++r) twr[S::tw_off(p) + m * (R - 1) + r - 1] = tw[r * k * stride];
+                         }
                      }
                  }
-             }
-         }()),
-         ...);
-    }(std::make_integer_sequence<int, S::P>{});
+             }()),
+             ...);
+        }(std::make_integer_sequence<int, S::P>{});
+    }
 }
 
 // Exchange buffers: a block of NPOL padded arrays per buffer.  Multi-wave
@@ -231,7 +247,15 @@ __device__ __forceinline__ void fft_pass(float2 (&v)[NPOL][E], float2* __restric
             if constexpr (PASS > 0) {
 #pragma unroll
                 for (int r = 1; r < R; ++r) {
-                    if constexpr (LS <= T) {
+                    if constexpr (S::TW_MEM) {
+                        // through a buffer resource over the table: one 32-bit offset per load
+                        typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+                        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                            const_cast<float2*>(twr.p), 0, NB * (int)sizeof(float2), 0x00020000);
+                        const unsigned off = (unsigned)(r * k * (NB / (LS * R))) * (unsigned)sizeof(float2);
+                        const float2 w = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0));
+                        a[r] = cmul_dir<INV>(a[r], w);
+                    } else if constexpr (LS <= T) {
                         a[r] = cmul_dir<INV>(a[r], twr[S::tw_off(PASS) + r - 1]);
                     } else {
                         a[r] = cmul_dir<INV>(a[r], twr[S::tw_off(PASS) + m * (R - 1) + r - 1]);

@@ -187,15 +187,21 @@ __device__ __forceinline__ void run_steps(float2 (&v)[NPOL][E], const BlockJob& 
     for (int s = a.s0; s < a.s0 + a.ks; ++s) {
         const StepDev st = load_step(a.steps + s);
         // issue this step's table and tap loads first: the forward FFT hides their latency
+        // (except in blocks of 8192 points and more, where the E table values would stay live
+        // through the transform beside its radix-16 butterflies and spill: loaded after it)
+        constexpr bool H_EARLY = !S::TW_MEM;
         float2 h[E];
-        if constexpr (HLDS) {
+        auto load_h = [&] {
+            if constexpr (HLDS) {
 #pragma unroll
-            for (int q = 0; q < E; ++q) h[q] = hl[t + T * q];
-        } else {
-            const float2* __restrict__ hs = a.H + st.h_off;
+                for (int q = 0; q < E; ++q) h[q] = hl[t + T * q];
+            } else {
+                const float2* __restrict__ hs = a.H + st.h_off;
 #pragma unroll
-            for (int q = 0; q < E; ++q) h[q] = hs[disp_index<NB, E, WF>(t, q)];
-        }
+                for (int q = 0; q < E; ++q) h[q] = hs[disp_index<NB, E, WF>(t, q)];
+            }
+        };
+        if constexpr (H_EARLY) load_h();
         const auto w = as_const(a.taps) + (long long)s * ntaps;
         float wr[NT > 0 ? NT : 1];
         if constexpr (NT > 0) {
@@ -212,15 +218,26 @@ __device__ __forceinline__ void run_steps(float2 (&v)[NPOL][E], const BlockJob& 
                 for (int p = 0; p < NPOL; ++p) v[p][q] = cmul(v[p][q], h[q]);
             wave_fft_1024<NPOL, true>(v, lds + NPOL * NB, twr, t);
         } else {
+            // In blocks of 8192 points and more the transforms take the thread index through an
+            // empty asm statement: their LDS and table addresses, which depend on it alone,
+            // are then formed inside each step instead of being hoisted out of the step loop,
+            // where they would stay live (and spill) through every step.
+            // The inverse gets its own copy, so that the forward transform's addresses are not
+            // kept for it either.
+            int tf = t;
+            if constexpr (S::TW_MEM) asm volatile("" : "+v"(tf));
             // (i) forward FFT of both polarizations
-            block_fft<NB, E, NPOL, false>(v, lds, twr, t);
+            block_fft<NB, E, NPOL, false>(v, lds, twr, tf);
+            if constexpr (!H_EARLY) load_h();
             // (ii) dispersion, Eq. (1), with the inverse FFT's 1/Nb folded in
 #pragma unroll
             for (int q = 0; q < E; ++q)
 #pragma unroll
                 for (int p = 0; p < NPOL; ++p) v[p][q] = cmul(v[p][q], h[q]);
             // (iii) inverse FFT
-            block_fft<NB, E, NPOL, true>(v, lds, twr, t);
+            int ti = t;
+            if constexpr (S::TW_MEM) asm volatile("" : "+v"(ti));
+            block_fft<NB, E, NPOL, true>(v, lds, twr, ti);
         }
         // (iv) nonlinear phase driven by the total intensity, Eqs. (2)-(3)
         float J[E];
@@ -362,7 +379,11 @@ __device__ __forceinline__ void process_block(const BlockJob& a, const TwReg<NB,
     float2 v[NPOL][E];
     load_block<NB, E, NPOL>(v, a.src, a.L, (long long)a.blk * a.V - a.halo, t);
     run_steps<NB, E, NPOL, PHASE64, NT>(v, a, twr, sm, nullptr);
-    store_block<NB, E, NPOL>(v, a, t);
+    // blocks of 8192 points and more: the output addresses are formed here, not kept live
+    // (and spilled) through the steps from the load's
+    int ts = t;
+    if constexpr (FftShape<NB, E>::TW_MEM) asm volatile("" : "+v"(ts));
+    store_block<NB, E, NPOL>(v, a, ts);
     // before the LDS is reused by a following job, every wave is done with it
     if constexpr (NB / E > 64) __syncthreads();
 }

@@ -84,6 +84,8 @@ def test_cfg0_whole_signal_single_polarization(dbp):
     (2048, 512, 2, True, 10, 1, 2, 30000),
     (4096, 1024, 2, True, 12, 1, 0, 50000),
     (8192, 2048, 2, False, 16, 1, 0, 40000),
+    (8192, 2048, 2, True, 16, 1, 0, 40000),           # the largest two-polarization blocks, ESSFM
+    (16384, 4096, 1, True, 12, 1, 0, 50000),          # the largest blocks (one polarization), ESSFM
     (1024, 256, 1, True, 5, 1, 2, 1024),              # a single block: the halo wraps around the signal
 ])
 def test_blocked_parity(dbp, block, overlap, n_pol, essfm, n_spans, sps, k, n):
