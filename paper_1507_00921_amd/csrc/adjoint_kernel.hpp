@@ -30,7 +30,7 @@ struct AdjArgs {
     const float2* gsig;     // gradient at the pass output [n_sig][NPOL][L], or nullptr:
     const float2* gprev;    //   then gathered from the following pass's window gradients
     float2* gout;           // this pass's window gradients [n_wg][NPOL][NB]
-    float2* xs;             // block states of steps 1..ks-1 [n_wg][kmax - 1][NPOL][NB]
+    float2* xs;             // block fields after the linear substep of steps 0..ks-2 [n_wg][kmax - 1][NPOL][NB]
     int kmax;               // steps per pass of the plan (slot count of xs + 1)
     long long L;
     int V, halo, n_blk, n_wg;
@@ -77,11 +77,25 @@ template <int NB, int E, int NPOL, int NT> struct AdjSmem {
     float red[NR * NW];
 };
 
-// Wave-wide sum (lanes combined in a fixed butterfly order).
+// Wave-wide sum in a fixed order, returned uniform: within each row of 16 lanes by DPP moves
+// (rotations by 8 and 4 inside the row, then the quad permutations [2,3,0,1] and [1,0,3,2]:
+// every lane of a row ends with the row's sum), then the four row sums read from lanes 0, 16,
+// 32 and 48 and added as (r0 + r1) + (r2 + r3).  VALU only: no LDS round trips.
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+}
+
 __device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    return v;
+    v += dpp_move<0x128>(v);     // row_ror:8
+    v += dpp_move<0x124>(v);     // row_ror:4
+    v += dpp_move<0x4E>(v);      // quad_perm [2,3,0,1]
+    v += dpp_move<0xB1>(v);      // quad_perm [1,0,3,2]
+    const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
+    const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16));
+    const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
+    const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48));
+    return (r0 + r1) + (r2 + r3);
 }
 
 // Forward or inverse block transform: the in-wave one (WF; forward exchange in the first
@@ -117,29 +131,64 @@ __global__ __launch_bounds__(NB / E) void dbp_adjoint_kernel(AdjArgs a) {
     const int ntaps = NT >= 0 ? NT : a.ntaps;
     const int c = (ntaps - 1) >> 1;
 
-    // forward through the pass on the block, keeping the inputs of steps 1..ks-1
+    auto load_h = [&](const StepDev& st, float2 (&h)[E]) {
+#pragma unroll
+        for (int q = 0; q < E; ++q) h[q] = a.H[st.h_off + disp_index<NB, E>(t, q)];
+    };
+    // J = w (*) I for the field u after a step's linear substep (I = sum_p |u|^2), the tap
+    // filter through sm.inten; sm.inten is rewritten only after a transform's barriers
+    auto filtered = [&](const float2 (&u)[NPOL][E], int s, float (&J)[E]) {
+#pragma unroll
+        for (int q = 0; q < E; ++q) {
+            float in = 0.f;
+#pragma unroll
+            for (int p = 0; p < NPOL; ++p) in = fmaf(u[p][q].x, u[p][q].x, fmaf(u[p][q].y, u[p][q].y, in));
+            J[q] = in;
+        }
+        if constexpr (NT != 0) {
+            const float* __restrict__ w = a.taps + (long long)s * ntaps;
+#pragma unroll
+            for (int q = 0; q < E; ++q) sm.inten[t + T * q] = J[q];
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < E; ++q) J[q] = 0.f;
+            for (int m = 0; m < ntaps; ++m) {
+                const float wm = w[m];
+#pragma unroll
+                for (int q = 0; q < E; ++q) J[q] = fmaf(wm, sm.inten[(t + T * q - m + c) & (NB - 1)], J[q]);
+            }
+        }
+    };
+
+    // Forward through the pass on the block.  A step's adjoint needs only the field u after its
+    // linear substep (I, J and the phase factor follow from u, and the linear adjoint acts on
+    // the gradient), so u of steps 0..ks-2 is kept and the last one stays in registers: the
+    // reverse sweep below runs no forward transform.
     float2 v[NPOL][E];
     load_block<NB, E, NPOL>(v, xsig, L, start, t);
-    BlockJob job;
-    job.L = L;
-    job.V = a.V;
-    job.halo = a.halo;
-    job.blk = blk;
-    job.steps = a.steps;
-    job.ks = 1;
-    job.H = a.H;
-    job.taps = a.taps;
-    job.ntaps = a.ntaps;
-    for (int j = 0; j + 1 < a.ks; ++j) {
-        job.s0 = a.s0 + j;
-        BlockSmem<NB, E, NPOL, NT>& fs = *reinterpret_cast<BlockSmem<NB, E, NPOL, NT>*>(&sm);
-        static_assert(sizeof(BlockSmem<NB, E, NPOL, NT>) <= sizeof(Sm), "forward step workspace");
-        run_steps<NB, E, NPOL, PHASE64, NT>(v, job, twr, fs, nullptr);
-        __syncthreads();
+    for (int j = 0;; ++j) {
+        const StepDev st = load_step(a.steps + a.s0 + j);
+        float2 h[E];
+        load_h(st, h);
+        transform<WF, false, NB, E, NPOL>(v, sm.lds, twr, t);
+#pragma unroll
+        for (int q = 0; q < E; ++q)
+#pragma unroll
+            for (int p = 0; p < NPOL; ++p) v[p][q] = cmul(v[p][q], h[q]);
+        transform<WF, true, NB, E, NPOL>(v, sm.lds, twr, t);
+        if (j + 1 == a.ks) break;
 #pragma unroll
         for (int p = 0; p < NPOL; ++p)
 #pragma unroll
             for (int q = 0; q < E; ++q) xs[((long long)j * NPOL + p) * NB + t + T * q] = v[p][q];
+        float J[E];
+        filtered(v, a.s0 + j, J);
+#pragma unroll
+        for (int q = 0; q < E; ++q) {
+            const float2 f = phase_factor<PHASE64>(J[q], st);
+#pragma unroll
+            for (int p = 0; p < NPOL; ++p) v[p][q] = cmul(v[p][q], f);
+        }
     }
 
     // gradient at the pass output: the kept centre, zero in the halo
@@ -164,46 +213,19 @@ __global__ __launch_bounds__(NB / E) void dbp_adjoint_kernel(AdjArgs a) {
 
     for (int j = a.ks - 1; j >= 0; --j) {
         const int s = a.s0 + j;
-        if (j == 0) {
-            load_block<NB, E, NPOL>(v, xsig, L, start, t);
-        } else {
+        if (j + 1 < a.ks) {
 #pragma unroll
             for (int p = 0; p < NPOL; ++p)
 #pragma unroll
-                for (int q = 0; q < E; ++q) v[p][q] = xs[((long long)(j - 1) * NPOL + p) * NB + t + T * q];
+                for (int q = 0; q < E; ++q) v[p][q] = xs[((long long)j * NPOL + p) * NB + t + T * q];
         }
         const StepDev st = load_step(a.steps + s);
         float2 h[E];
-#pragma unroll
-        for (int q = 0; q < E; ++q) h[q] = a.H[st.h_off + disp_index<NB, E>(t, q)];
-        // recompute u, I, J and the phase factor f = exp(-j phi J) of step s
-        transform<WF, false, NB, E, NPOL>(v, sm.lds, twr, t);
-#pragma unroll
-        for (int q = 0; q < E; ++q)
-#pragma unroll
-            for (int p = 0; p < NPOL; ++p) v[p][q] = cmul(v[p][q], h[q]);
-        transform<WF, true, NB, E, NPOL>(v, sm.lds, twr, t);
+        load_h(st, h);
+        // u of step s is in v: its I, J and the phase factor f = exp(-j phi J)
         float J[E];
-#pragma unroll
-        for (int q = 0; q < E; ++q) {
-            float in = 0.f;
-#pragma unroll
-            for (int p = 0; p < NPOL; ++p) in = fmaf(v[p][q].x, v[p][q].x, fmaf(v[p][q].y, v[p][q].y, in));
-            J[q] = in;
-        }
+        filtered(v, s, J);
         const float* __restrict__ w = a.taps + (long long)s * ntaps;
-        if constexpr (NT != 0) {
-#pragma unroll
-            for (int q = 0; q < E; ++q) sm.inten[t + T * q] = J[q];
-            __syncthreads();
-#pragma unroll
-            for (int q = 0; q < E; ++q) J[q] = 0.f;
-            for (int m = 0; m < ntaps; ++m) {
-                const float wm = w[m];
-#pragma unroll
-                for (int q = 0; q < E; ++q) J[q] = fmaf(wm, sm.inten[(t + T * q - m + c) & (NB - 1)], J[q]);
-            }
-        }
         // adjoint of the phase rotation: Jbar, and g <- g conj(f)
         float jb[E];
 #pragma unroll
