@@ -974,7 +974,7 @@ def main():
     ap.add_argument("--hbm-variant", default="per_block", choices=("per_block", "stream"),
                     help="with --hbm-case: the per-block kernel (the planner's default) or the streaming twin")
     ap.add_argument("--only", default=None,
-                    choices=("precision", "gradient", "batch", "geometry", "ase", "whole"),
+                    choices=("precision", "gradient", "batch", "geometry", "ase", "whole", "fftgrad"),
                     help="run one secondary workload alone and print its JSON (for profiler runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a plain 1 GiB device copy three times and exit (counter calibration)")
@@ -1012,6 +1012,14 @@ def main():
         return
     if args.only == "whole":
         print(json.dumps(small_whole_signal(dbp, torch)), flush=True)
+        return
+    if args.only == "fftgrad":
+        # reverse mode of the headline cascade with seeded 9-tap ESSFM coefficients
+        rx, _ = gpu_field(dbp, torch, P_DBM)
+        taps = siggen.symmetric_taps(siggen.rng(1, 0, 7), NC)
+        essfm = dbp.plan(N, SPANS, 1, taps=taps, block=BLOCK, overlap=OVERLAP, beta2_ps2_km=b2)
+        for _ in range(3):
+            print(json.dumps(fft_gradient(torch, essfm, rx, reps=20)), flush=True)
         return
     if args.only:
         fn = {"precision": precision_workload, "gradient": grad_workload, "batch": batch_workload}[args.only]
