@@ -49,6 +49,8 @@ def case(seed, batch, n_pol, n, n_spans, nc):
     (256, 64, 2, 2, 3, 5, 2000, 1),         # 7 taps (run-time tap count), odd pass count
     (2048, 512, 3, 2, 4, 6, 9000, 1),
     (4096, 1024, 2, 2, None, 4, 10000, 1),
+    (4096, 1024, 2, 2, 4, 4, 10000, 1),     # the largest adjoint blocks with 9 taps
+    (512, 128, 2, 1, 4, 4, 3000, 1),        # ESSFM on one polarization
     (1024, 256, 3, 2, 4, 3, 1024, 1),       # one block: its window wraps around the signal
 ])
 def test_fft_grad_matches_oracle(dbp, nb, o, k, n_pol, nc, n_spans, n, batch):
