@@ -8,8 +8,6 @@ call on ordinary allocations, and every guard word afterwards.  Covers the pass 
 (blocked, whole-signal, the 8192-point blocks, both FIR paths), both reverse modes through the
 C ABI, the ragged batch, the receiver mode and the receiver DSP.
 """
-import ctypes
-
 import numpy as np
 import pytest
 
