@@ -53,6 +53,10 @@
  *            library's n-th device allocation counted since the tag last
  *            changed fails as out of memory; the call then returns
  *            DBP_ERR_OOM (or DBP_ERR_HIP) having released what it allocated.
+ *   Tracing  DBP_LOG=1: every plan made (dbp_plan, dbp_plan_batch) writes its
+ *            decisions to stderr: the descriptor's shape, the geometry (Nb,
+ *            O, steps per pass, passes, values per thread), the kernel and
+ *            the workspace sizes; a batch, its kernel groups.
  */
 #ifndef DBP_H
 #define DBP_H

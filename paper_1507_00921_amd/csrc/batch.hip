@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <cstring>
 #include <map>
 #include <mutex>
 #include <new>
@@ -490,6 +491,14 @@ dbp_status dbp_plan_batch(const dbp_desc* descs, int32_t n, dbp_plan_t* out) {
         return st;
     }
     p->geo.n_passes = 0;
+    // DBP_LOG=1: the batch's kernel groups (one persistent launch each) on stderr
+    if (const char* on = std::getenv("DBP_LOG"); on && *on && std::strcmp(on, "0") != 0) {
+        std::fprintf(stderr, "dbp_plan_batch: signals=%d groups=%zu workspace=%zu\n", n, B->groups.size(),
+                     dbp_workspace_size(p, 0));
+        for (const BatchGroup& G : B->groups)
+            std::fprintf(stderr, "  dbp_batch_kernel<%d, %d, %d, %s, %d>: %d work items, grid %d, %.3g sample-steps\n",
+                         G.nb, G.e, G.npol, G.p64 ? "true" : "false", G.nt, G.n_items, G.grid, G.work);
+    }
     *out = p;
     return DBP_OK;
 }

@@ -885,6 +885,24 @@ dbp_status dbp_fir_taps(const dbp_desc* desc, int32_t step, float* out) {
     return DBP_OK;
 }
 
+// DBP_LOG=1: one line per created plan on stderr with the planner's decisions (geometry,
+// kernel, passes, workspace sizes), for tracing what a descriptor turned into.
+static void log_plan(const dbp_plan_s* p) {
+    const char* on = std::getenv("DBP_LOG");
+    if (!on || !*on || std::strcmp(on, "0") == 0) return;
+    const dbp_desc& d = p->desc;
+    std::fprintf(stderr,
+                 "dbp_plan: L=%lld pol=%d batch=%d %s taps=%d %s%s steps=%d geometry Nb=%d O=%d k=%d "
+                 "passes=%d E=%d%s kernel=%s workspace=%zu grad_workspace=%zu%s%s\n",
+                 (long long)d.n_samples, d.n_pol, d.batch, d.method == DBP_ESSFM ? "ESSFM" : "SSFM",
+                 d.method == DBP_ESSFM ? d.n_taps : 0, d.linear == DBP_LINEAR_FIR ? "FIR" : "FFT",
+                 d.precision == DBP_BF16X3 ? " BF16X3" : (d.precision == DBP_FP32 ? " FP32" : ""),
+                 p->geo.n_steps, p->geo.block, p->geo.overlap, p->geo.k, p->geo.n_passes, p->geo.e,
+                 p->geo.split ? " split" : "", p->kernel_name, dbp_workspace_size(const_cast<dbp_plan_s*>(p), 0),
+                 dbp_workspace_size(const_cast<dbp_plan_s*>(p), 1), (d.flags & DBP_FLAG_WHOLE) ? " whole" : "",
+                 (d.flags & DBP_FLAG_PERSISTENT) ? " persistent" : "");
+}
+
 dbp_status dbp_plan(const dbp_desc* desc, dbp_plan_t* out) {
     if (!out) return DBP_ERR_INVALID_ARG;
     *out = nullptr;
@@ -1045,6 +1063,7 @@ dbp_status dbp_plan(const dbp_desc* desc, dbp_plan_t* out) {
         dbp_destroy(p);
         return st;
     }
+    log_plan(p);
     *out = p;
     return DBP_OK;
 }

@@ -365,3 +365,22 @@ def test_tuned_geometry_is_the_fastest_candidate_and_matches_oracle(dbp, tmp_pat
           f"{[(c['block'], c['overlap'], c['k'], round(c['ms'], 4)) for c in cands if c['model_pick']]}): rel L2 {err:.3e}")
     assert err <= 1e-5
     p.close()
+
+
+def test_plan_log_traces_the_planner_decisions(dbp, capfd, monkeypatch):
+    """DBP_LOG=1: one line per plan on stderr naming the geometry, the kernel and the workspace."""
+    monkeypatch.setenv("DBP_LOG", "1")
+    p = dbp.plan(5000, 6, 1, taps=TAPS9, block=1024, overlap=256, beta2_ps2_km=B2)
+    bp = dbp.plan_batch([dbp.make_desc(3000, 3, 1, taps=TAPS9, beta2_ps2_km=B2),
+                         dbp.make_desc(900, 2, 4, beta2_ps2_km=B2)])
+    err = capfd.readouterr().err
+    line = [ln for ln in err.splitlines() if ln.startswith("dbp_plan: L=5000")]
+    assert len(line) == 1, err
+    assert f"Nb={p.block} O={p.overlap} k={p.steps_per_pass} passes={p.n_passes}" in line[0]
+    assert f"kernel={p.kernel}" in line[0] and f"workspace={p.workspace_size()}" in line[0]
+    assert "dbp_plan_batch: signals=2" in err and "dbp_batch_kernel<" in err
+    monkeypatch.delenv("DBP_LOG")
+    dbp.plan(5000, 6, 1, taps=TAPS9, block=1024, overlap=256, beta2_ps2_km=B2).close()
+    assert "dbp_plan:" not in capfd.readouterr().err
+    p.close()
+    bp.close()
