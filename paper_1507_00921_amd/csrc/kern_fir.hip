@@ -36,22 +36,18 @@ static hipError_t allow_smem(K kernel) {
 
 // Variant for the tap counts: FIR 33 taps compiled in (else run time); intensity
 // taps none (SSFM), 9, or run time.
+// The attribute is set once per kernel variant, by the first launch (a function-local static:
+// its initialization is thread-safe, so concurrent first calls from several host threads
+// neither race nor set it twice).
 template <int NPOL, int NF, int NW>
 static hipError_t launch_variant(bool adjoint, const FirArgs& a, size_t sm, hipStream_t s) {
-    hipError_t e;
     if (adjoint) {
-        static bool ok = false;
-        if (!ok) {
-            if ((e = allow_smem(fir_adjoint_kernel<NPOL, NF, NW>)) != hipSuccess) return e;
-            ok = true;
-        }
+        static const hipError_t set = allow_smem(fir_adjoint_kernel<NPOL, NF, NW>);
+        if (set != hipSuccess) return set;
         hipLaunchKernelGGL((fir_adjoint_kernel<NPOL, NF, NW>), dim3(a.n_wg), dim3(FT_THREADS), sm, s, a);
     } else {
-        static bool ok = false;
-        if (!ok) {
-            if ((e = allow_smem(fir_step_kernel<NPOL, NF, NW>)) != hipSuccess) return e;
-            ok = true;
-        }
+        static const hipError_t set = allow_smem(fir_step_kernel<NPOL, NF, NW>);
+        if (set != hipSuccess) return set;
         hipLaunchKernelGGL((fir_step_kernel<NPOL, NF, NW>), dim3(a.n_wg), dim3(FT_THREADS), sm, s, a);
     }
     return hipGetLastError();
