@@ -314,7 +314,11 @@ dbp_status dbp_batch_offsets(dbp_plan_t plan, int64_t* offsets, int32_t n_plus_1
  * cost of each block size once per process and kernel variant, timing the batch
  * kernel on a synthetic signal at 1 and 4 steps per pass, then picks
  * for every signal the block, overlap and steps per pass of least modelled
- * time; explicit block/overlap/steps_per_pass in a descriptor are kept). */
+ * time; explicit block/overlap/steps_per_pass in a descriptor are kept).
+ * DBP_TUNE_CACHE=<file> keeps the measured costs across processes: JSON
+ * lines keyed by GPU architecture, CU count and kernel variant, read before
+ * timing and appended after it (unparsable lines and non-positive or
+ * non-finite costs are ignored; the last matching line wins). */
 dbp_status dbp_batch_geometry(dbp_plan_t plan, int32_t i, int32_t* block, int32_t* overlap,
                               int32_t* steps_per_pass);
 

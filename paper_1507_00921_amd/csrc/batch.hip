@@ -99,6 +99,51 @@ static dbp_status measure_cost(int npol, int nt, bool p64, int nb, Cost& out) {
     return rc;
 }
 
+// DBP_TUNE_CACHE=<file>: measured costs persist across processes as JSON lines, one per
+// (GPU architecture, CU count, variant); a process looks its variant up there before timing it
+// and appends what it times.  Lines it cannot parse, or with costs that are not positive and
+// finite, are ignored.
+struct DeviceKey {
+    char arch[64] = {};
+    int cus = 0;
+};
+
+static DeviceKey device_key(int dev) {
+    DeviceKey k;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+        std::snprintf(k.arch, sizeof(k.arch), "%s", prop.gcnArchName);
+        for (char* q = k.arch; *q; ++q)
+            if (*q == '"' || *q == '\\') *q = '_';
+        k.cus = prop.multiProcessorCount;
+    }
+    return k;
+}
+
+static bool cache_lookup(const char* path, const DeviceKey& dk, int npol, int nt, bool p64, int nb, Cost& c) {
+    FILE* f = std::fopen(path, "r");
+    if (!f) return false;
+    char line[512];
+    bool found = false;
+    while (std::fgets(line, sizeof(line), f)) {
+        char arch[64];
+        int cus, lp, lt, l64, lnb;
+        double c0, c1;
+        if (std::sscanf(line, "{\"arch\": \"%63[^\"]\", \"cus\": %d, \"npol\": %d, \"nt\": %d, \"p64\": %d, "
+                              "\"nb\": %d, \"c0_us\": %lf, \"c1_us\": %lf}",
+                        arch, &cus, &lp, &lt, &l64, &lnb, &c0, &c1) != 8)
+            continue;
+        if (std::strcmp(arch, dk.arch) != 0 || cus != dk.cus || lp != npol || lt != nt || l64 != (int)p64 ||
+            lnb != nb || !std::isfinite(c0) || !std::isfinite(c1) || c0 <= 0 || c1 <= 0)
+            continue;
+        c.c0 = c0;                     // the last matching line wins
+        c.c1 = c1;
+        found = true;
+    }
+    std::fclose(f);
+    return found;
+}
+
 static dbp_status get_cost(int dev, int npol, int nt, bool p64, int nb, Cost& c) {
     std::lock_guard<std::mutex> lk(g_cost_mu);
     const auto key = std::make_tuple(dev, npol, nt, (int)p64, nb);
@@ -107,9 +152,24 @@ static dbp_status get_cost(int dev, int npol, int nt, bool p64, int nb, Cost& c)
         c = it->second;
         return DBP_OK;
     }
+    const char* cache = std::getenv("DBP_TUNE_CACHE");
+    const DeviceKey dk = cache && *cache ? device_key(dev) : DeviceKey{};
+    if (cache && *cache && dk.cus > 0 && cache_lookup(cache, dk, npol, nt, p64, nb, c)) {
+        g_costs[key] = c;
+        return DBP_OK;
+    }
     dbp_status st = measure_cost(npol, nt, p64, nb, c);
     if (st != DBP_OK) return st;
     g_costs[key] = c;
+    if (cache && *cache && dk.cus > 0) {
+        if (FILE* f = std::fopen(cache, "a")) {
+            std::fprintf(f,
+                         "{\"arch\": \"%s\", \"cus\": %d, \"npol\": %d, \"nt\": %d, \"p64\": %d, \"nb\": %d, "
+                         "\"c0_us\": %.9g, \"c1_us\": %.9g}\n",
+                         dk.arch, dk.cus, npol, nt, (int)p64, nb, c.c0, c.c1);
+            std::fclose(f);
+        }
+    }
     if (const char* path = std::getenv("DBP_AUTOTUNE_LOG")) {
         if (FILE* f = std::fopen(path, "a")) {
             std::fprintf(f, "{\"npol\": %d, \"nt\": %d, \"p64\": %d, \"nb\": %d, \"c0_us\": %.6g, \"c1_us\": %.6g}\n",

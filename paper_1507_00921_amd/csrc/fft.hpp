@@ -249,7 +249,6 @@ __device__ __forceinline__ void fft_pass(float2 (&v)[NPOL][E], float2* __restric
                 for (int r = 1; r < R; ++r) {
                     if constexpr (S::TW_MEM) {
                         // through a buffer resource over the table: one 32-bit offset per load
-                        typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
                         const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
                             const_cast<float2*>(twr.p), 0, NB * (int)sizeof(float2), 0x00020000);
                         const unsigned off = (unsigned)(r * k * (NB / (LS * R))) * (unsigned)sizeof(float2);

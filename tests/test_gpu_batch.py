@@ -176,3 +176,42 @@ def test_concurrent_groups_equal_serial_groups(dbp, monkeypatch):
         outs.append(y.clone())
         bp.close()
     assert torch.equal(torch.view_as_real(outs[0]), torch.view_as_real(outs[1]))
+
+
+def test_tune_cache_persists_measured_costs(dbp, tmp_path):
+    """DBP_TUNE_CACHE: a first process times the batch kernel variants it needs and appends
+    them to the cache; a second process reads them instead of timing (it writes no timing log)
+    and chooses the same geometries; a cache that prices 2048-point blocks far below the other
+    sizes makes the tuner choose them.  Separate processes: the costs are also kept in memory."""
+    import json
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = ("import sys, json; sys.path.insert(0, %r); import numpy as np; import paper_1507_00921_amd as d\n"
+            "bp = d.plan_batch([d.make_desc(300000, 4, 1, taps=np.full(9, 1 / 9, np.float32)),"
+            " d.make_desc(200000, 3, 4)])\n"
+            "print(json.dumps([bp.geometry(i) for i in range(2)]))\n" % root)
+
+    def run(cache, log):
+        env = dict(os.environ, DBP_TUNE_CACHE=str(cache), DBP_AUTOTUNE_LOG=str(log))
+        r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=150,
+                           cwd=root)
+        assert r.returncode == 0, r.stderr[-2000:]
+        return json.loads(r.stdout.strip().splitlines()[-1])
+
+    cache = tmp_path / "tune.jsonl"
+    geo1 = run(cache, tmp_path / "log1.jsonl")
+    rows = [json.loads(ln) for ln in cache.read_text().splitlines()]
+    assert rows and (tmp_path / "log1.jsonl").exists()
+    assert all(r["arch"].startswith("gfx950") and r["cus"] > 0 and r["c0_us"] > 0 for r in rows)
+    assert {r["nb"] for r in rows} >= {1024, 2048}
+    geo2 = run(cache, tmp_path / "log2.jsonl")
+    assert not (tmp_path / "log2.jsonl").exists()        # read from the cache, not timed
+    assert geo2 == geo1
+    forced = tmp_path / "forced.jsonl"
+    forced.write_text("".join(json.dumps(dict(r, c0_us=0.01 if r["nb"] == 2048 else 100.0,
+                                              c1_us=0.01 if r["nb"] == 2048 else 100.0)) + "\n" for r in rows))
+    geo3 = run(forced, tmp_path / "log3.jsonl")
+    assert not (tmp_path / "log3.jsonl").exists()
+    assert all(g[0] == 2048 for g in geo3), geo3
