@@ -194,17 +194,37 @@ __global__ __launch_bounds__(NB / E) void dbp_adjoint_kernel(AdjArgs a) {
     // gradient at the pass output: the kept centre, zero in the halo
     float2 g[NPOL][E];
     const float2* __restrict__ gprev = a.gprev + (long long)sig * a.n_blk * NPOL * NB;
+    // Away from the signal's ends only the blocks blk - 1, blk, blk + 1 of the following pass
+    // cover an output o (at window index pos - j V): three independent loads, added in block
+    // order with the general gather's operations, so the sum is bit for bit its sum.  Three
+    // blocks suffice when halo <= V (kept positions pos < halo + V give |j| <= 1); o has no
+    // wrapped terms if o < L - halo (none from o - L) and o + L lies past the last block's
+    // window (none from o + L).
+    const long long wrap_hi = (long long)(a.n_blk - 1) * a.V - a.halo + NB - L;
+    const bool three = a.halo <= a.V;
 #pragma unroll
     for (int q = 0; q < E; ++q) {
         const int pos = t + T * q;
         const long long o = (long long)blk * a.V + pos - a.halo;
         const bool keep = pos >= a.halo && pos < a.halo + a.V && o < L;
+        const bool interior = three && o < L - a.halo && o >= wrap_hi;
 #pragma unroll
         for (int p = 0; p < NPOL; ++p) {
             if (!keep) {
                 g[p][q] = make_float2(0.f, 0.f);
             } else if (a.gsig) {
                 g[p][q] = a.gsig[((long long)sig * NPOL + p) * L + o];
+            } else if (interior) {
+                float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+                for (int j = -1; j <= 1; ++j) {
+                    const int b = blk + j, m = pos - j * a.V;
+                    const bool ok = b >= 0 && b < a.n_blk && m >= 0 && m < NB;
+                    const float2 gv = gprev[((long long)(ok ? b : blk) * NPOL + p) * NB + (ok ? m : pos)];
+                    acc.x = ok ? acc.x + gv.x : acc.x;
+                    acc.y = ok ? acc.y + gv.y : acc.y;
+                }
+                g[p][q] = acc;
             } else {
                 g[p][q] = gather_window_grad<NPOL>(gprev, p, o, L, NB, a.V, a.halo, a.n_blk);
             }
