@@ -326,25 +326,35 @@ def small_whole_signal(dbp, torch, reps=50):
     return res
 
 
-def fft_gradient(torch, plan, rx, reps=10):
+def fft_gradient(torch, plan, rx, reps=10, recompute_plan=None):
     """Reverse mode of the headline ESSFM cascade (Nb=1024 O=256, k=5): input and tap
-    gradients for a fixed upstream gradient; one call = forward storing the 8 pass inputs +
-    8 reverse passes + the input-gradient gather + the tap reduction."""
+    gradients for a fixed upstream gradient; one call = 8 forward passes keeping every
+    block's field after each linear substep + 8 reverse passes + the input-gradient gather +
+    the tap reduction.  recompute_plan (the same cascade with DBP_FLAG_GRAD_SPARSE): the
+    forward keeps the pass inputs only and every reverse pass re-runs its steps first."""
     g = torch.view_as_complex(torch.randn(*rx.shape, 2, device="cuda", generator=torch.Generator(
         device="cuda").manual_seed(5)))
-    ws = plan.workspace(grad=True)
-    for _ in range(2):
-        plan.backprop_grad(rx, g, workspace=ws)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        plan.backprop_grad(rx, g, workspace=ws)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
-    return {"workload": "headline ESSFM 40 steps on 2x262144, Nb=1024 O=256 k=5: d/dx and d/dw",
-            "fwd_bwd_ms": round(ms, 4), "workspace_mib": round(ws.numel() / 2**20, 1)}
+
+    def timed(p):
+        ws = p.workspace(grad=True)
+        for _ in range(2):
+            p.backprop_grad(rx, g, workspace=ws)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            p.backprop_grad(rx, g, workspace=ws)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps, ws.numel()
+
+    ms, wsb = timed(plan)
+    out = {"workload": "headline ESSFM 40 steps on 2x262144, Nb=1024 O=256 k=5: d/dx and d/dw",
+           "fwd_bwd_ms": round(ms, 4), "workspace_mib": round(wsb / 2**20, 1)}
+    if recompute_plan is not None:
+        ms_r, wsb_r = timed(recompute_plan)
+        out["recompute"] = {"fwd_bwd_ms": round(ms_r, 4), "workspace_mib": round(wsb_r / 2**20, 1)}
+    return out
 
 
 def receiver_workload(dbp, torch, rx_field, taps, chunk_blocks=64, pushes=40):
@@ -1018,8 +1028,10 @@ def main():
         rx, _ = gpu_field(dbp, torch, P_DBM)
         taps = siggen.symmetric_taps(siggen.rng(1, 0, 7), NC)
         essfm = dbp.plan(N, SPANS, 1, taps=taps, block=BLOCK, overlap=OVERLAP, beta2_ps2_km=b2)
+        recompute = dbp.plan(N, SPANS, 1, taps=taps, block=BLOCK, overlap=OVERLAP, grad_sparse=True,
+                             beta2_ps2_km=b2)
         for _ in range(3):
-            print(json.dumps(fft_gradient(torch, essfm, rx, reps=20)), flush=True)
+            print(json.dumps(fft_gradient(torch, essfm, rx, reps=20, recompute_plan=recompute)), flush=True)
         return
     if args.only:
         fn = {"precision": precision_workload, "gradient": grad_workload, "batch": batch_workload}[args.only]
@@ -1090,7 +1102,8 @@ def main():
         log("coefficient fit " + json.dumps(extras["coefficient_fit"]))
         extras["whole_signal"] = small_whole_signal(dbp, torch)
         log("whole-signal case " + json.dumps(extras["whole_signal"]))
-        extras["fft_gradient"] = fft_gradient(torch, essfm, rx)
+        extras["fft_gradient"] = fft_gradient(torch, essfm, rx, recompute_plan=dbp.plan(
+            N, SPANS, 1, taps=taps, block=BLOCK, overlap=OVERLAP, grad_sparse=True, beta2_ps2_km=b2))
         log("FFT-step gradient " + json.dumps(extras["fft_gradient"]))
         extras["receiver"] = {f"chunk_{cb}_blocks": receiver_workload(dbp, torch, rx, taps, chunk_blocks=cb)
                               for cb in (64, 336)}

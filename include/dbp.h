@@ -99,7 +99,8 @@ typedef enum dbp_precision {
 
 #define DBP_FLAG_FORWARD 0x1u   /* physical direction (forward propagation) */
 #define DBP_FLAG_WHOLE   0x2u   /* one circular block of the whole signal */
-#define DBP_FLAG_GRAD_SPARSE 0x4u  /* FIR gradient: checkpoint every 8th step only */
+#define DBP_FLAG_GRAD_SPARSE 0x4u  /* gradient: FIR, checkpoint every 8th step only;
+                                      FFT steps, keep pass inputs only */
 #define DBP_FLAG_TUNE    0x8u   /* measured geometry: time candidates at plan creation */
 #define DBP_FLAG_PERSISTENT 0x10u  /* all passes in one resident launch, halos exchanged */
 
@@ -269,11 +270,18 @@ dbp_status dbp_backprop_noalloc(dbp_plan_t plan, const void* in, void* out, cons
  *     time).
  *   FFT-step plans (overlap-and-save, Sec. III): the derivative of exactly the
  *     blocked cascade dbp_backprop computes (same Nb, O, k).  The passes run
- *     forward once storing every pass input; then each pass, in reverse,
- *     re-runs every block's steps from that input and their adjoints, and the
- *     window gradients of overlapping blocks are summed per sample in block
- *     order.  Block sizes 256..4096; not the BF16X3 precision (UNSUPPORTED).
- *     The phase argument of the recomputed steps is formed in FP64.
+ *     forward once, keeping every block's field after the linear substep of
+ *     every step; then each pass, in reverse, runs its blocks' step adjoints
+ *     from those fields, and the window gradients of overlapping blocks are
+ *     summed per sample in block order.  With DBP_FLAG_GRAD_SPARSE, or when
+ *     the kept fields would take more than 4 GiB, or the plan's forward kernel
+ *     is not the plain per-block one (polarization-split or streaming blocks,
+ *     other values per thread, DBP_FP32), the forward keeps the pass inputs
+ *     only and each reverse pass first re-runs its blocks' steps from them
+ *     (less workspace, about one more forward pass of time; the same
+ *     gradients, bit for bit, where both modes apply).  Block sizes
+ *     256..4096; not the BF16X3 precision (UNSUPPORTED).  The phase argument
+ *     of the reverse steps is formed in FP64.
  * Parameter gradients are summed over blocks, tiles and the batch in a fixed
  * order (bitwise reproducible).  ws_bytes >= dbp_workspace_size(plan, 1).
  * Gradients are overwritten, not accumulated. */
@@ -287,7 +295,7 @@ dbp_status dbp_backprop_grad(dbp_plan_t plan, const void* in, const float* taps,
  * twice.  dbp_backprop_save computes out = dbp_backprop(in) (out must not
  * overlap in) and leaves in ws (ws_bytes >= dbp_workspace_size(plan, 1)) what
  * the reverse pass reads: for FIR plans the checkpointed step inputs, for
- * FFT-step plans the pass inputs.  dbp_backprop_grad_saved then writes the
+ * FFT-step plans the kept block fields (or the pass inputs).  dbp_backprop_grad_saved then writes the
  * gradients of dbp_backprop_grad for upstream grad_out, given the same plan,
  * in, out, taps and fir, and ws as dbp_backprop_save left it (the reverse pass
  * overwrites only the parts of ws it recomputes, so it may run again for

@@ -17,7 +17,7 @@ SOURCES = ["dbp.hip", "kern_small.hip", "kern_1024.hip", "kern_2048.hip", "kern_
            "kern_large.hip", "kern_fir.hip", "kern_mfma.hip",
            "kern_batch1.hip", "kern_batch2.hip", "batch.hip", "kern_adj1.hip", "kern_adj2.hip",
            "rx.hip", "kern_rx1.hip", "kern_rx2.hip", "rxdsp.hip", "mse.hip", "kern_persist.hip",
-           "kern_each.hip"]
+           "kern_each.hip", "kern_keep1.hip", "kern_keep2.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++20", "--offload-arch=gfx950", "-fPIC",

@@ -30,8 +30,10 @@ struct AdjArgs {
     const float2* gsig;     // gradient at the pass output [n_sig][NPOL][L], or nullptr:
     const float2* gprev;    //   then gathered from the following pass's window gradients
     float2* gout;           // this pass's window gradients [n_wg][NPOL][NB]
-    float2* xs;             // block fields after the linear substep of steps 0..ks-2 [n_wg][kmax - 1][NPOL][NB]
-    int kmax;               // steps per pass of the plan (slot count of xs + 1)
+    float2* xs;             // block fields after the linear substep of the pass's steps [n_wg][slots][NPOL][NB]
+    int slots;              // fields per block in xs: kmax - 1 (steps 0..ks-2, recomputed here) or kmax
+    int saved;              // 1: xs holds the fields of every step of the pass (kept by the forward
+                            // pass, dbp_keep_pass_kernel); 0: the pass is recomputed from x
     long long L;
     int V, halo, n_blk, n_wg;
     const StepDev* steps;
@@ -127,7 +129,7 @@ __global__ __launch_bounds__(NB / E) void dbp_adjoint_kernel(AdjArgs a) {
     TwReg<NB, E> twr;
     load_step_twiddles<NB, E>(twr, a.tw, t);
     const float2* __restrict__ xsig = a.x + (long long)sig * NPOL * L;
-    float2* __restrict__ xs = a.xs + (long long)wg * (a.kmax - 1) * NPOL * NB;
+    float2* __restrict__ xs = a.xs + (long long)wg * a.slots * NPOL * NB;
     const int ntaps = NT >= 0 ? NT : a.ntaps;
     const int c = (ntaps - 1) >> 1;
 
@@ -163,10 +165,11 @@ __global__ __launch_bounds__(NB / E) void dbp_adjoint_kernel(AdjArgs a) {
     // Forward through the pass on the block.  A step's adjoint needs only the field u after its
     // linear substep (I, J and the phase factor follow from u, and the linear adjoint acts on
     // the gradient), so u of steps 0..ks-2 is kept and the last one stays in registers: the
-    // reverse sweep below runs no forward transform.
+    // reverse sweep below runs no forward transform.  When the forward pass kept u of every
+    // step (a.saved), nothing is recomputed.
     float2 v[NPOL][E];
-    load_block<NB, E, NPOL>(v, xsig, L, start, t);
-    for (int j = 0;; ++j) {
+    if (!a.saved) load_block<NB, E, NPOL>(v, xsig, L, start, t);
+    for (int j = 0; !a.saved; ++j) {
         const StepDev st = load_step(a.steps + a.s0 + j);
         float2 h[E];
         load_h(st, h);
@@ -231,14 +234,20 @@ __global__ __launch_bounds__(NB / E) void dbp_adjoint_kernel(AdjArgs a) {
         }
     }
 
+    // Blocks of up to 2048 points read u of step j one step ahead: issued once step j + 1 is
+    // done with its own u, the loads run during step j + 1's linear adjoint (the transforms'
+    // barriers wait on LDS only).  The 4096-point variants would spill with it.
+    constexpr bool AHEAD = NB <= 2048;
+    auto load_u = [&](int j) {
+#pragma unroll
+        for (int p = 0; p < NPOL; ++p)
+#pragma unroll
+            for (int q = 0; q < E; ++q) v[p][q] = xs[((long long)j * NPOL + p) * NB + t + T * q];
+    };
+    if (AHEAD && a.saved) load_u(a.ks - 1);
     for (int j = a.ks - 1; j >= 0; --j) {
         const int s = a.s0 + j;
-        if (j + 1 < a.ks) {
-#pragma unroll
-            for (int p = 0; p < NPOL; ++p)
-#pragma unroll
-                for (int q = 0; q < E; ++q) v[p][q] = xs[((long long)j * NPOL + p) * NB + t + T * q];
-        }
+        if (!AHEAD && (a.saved || j + 1 < a.ks)) load_u(j);
         const StepDev st = load_step(a.steps + s);
         float2 h[E];
         load_h(st, h);
@@ -300,6 +309,7 @@ __global__ __launch_bounds__(NB / E) void dbp_adjoint_kernel(AdjArgs a) {
                 g[p][q].x = fmaf(2.f * ib[q], v[p][q].x, g[p][q].x);
                 g[p][q].y = fmaf(2.f * ib[q], v[p][q].y, g[p][q].y);
             }
+        if (AHEAD && j > 0) load_u(j - 1);
         transform<WF, false, NB, E, NPOL>(g, sm.lds, twr, t);
 #pragma unroll
         for (int q = 0; q < E; ++q)
@@ -315,6 +325,48 @@ __global__ __launch_bounds__(NB / E) void dbp_adjoint_kernel(AdjArgs a) {
     for (int p = 0; p < NPOL; ++p)
 #pragma unroll
         for (int q = 0; q < E; ++q) gout[p * NB + t + T * q] = g[p][q];
+}
+
+// The forward pass of dbp_pass_kernel that also keeps, for the reverse mode, every block's
+// field after the linear substep of each of the pass's steps (slot j of block wg at
+// xs[wg][j], slots per block): the same routine (run_steps with a store as its keep), so its
+// output is bit for bit that kernel's, and the fields are those the reverse pass would
+// recompute.  Blocks of up to 4096 points (no opaque thread-index copies needed).
+template <int NB, int E, int NPOL, int NT>
+__global__ __launch_bounds__(NB / E) void dbp_keep_pass_kernel(PassArgs a, float2* __restrict__ xs, int slots) {
+    static_assert(!FftShape<NB, E>::TW_MEM, "blocks of up to 4096 points");
+    constexpr int T = NB / E;
+    __shared__ BlockSmem<NB, E, NPOL, NT> sm;
+    const int t = threadIdx.x;
+    const int wg = xcd_remap(blockIdx.x, a.n_wg);
+    const int sig = wg / a.n_blk;
+    TwReg<NB, E> twr;
+    load_step_twiddles<NB, E>(twr, a.tw, t);
+    BlockJob j;
+    j.src = a.in + (long long)sig * NPOL * a.L;
+    j.dst = a.out + (long long)sig * NPOL * a.L;
+    j.L = a.L;
+    j.V = a.V;
+    j.halo = a.halo;
+    j.blk = wg - sig * a.n_blk;
+    j.steps = a.steps;
+    j.s0 = a.s0;
+    j.ks = a.ks;
+    j.H = a.H;
+    j.taps = a.taps;
+    j.ntaps = a.ntaps;
+    j.nt = a.nt_store != 0;
+    float2* __restrict__ xb = xs + (long long)wg * slots * NPOL * NB;
+    auto keep = [&](const float2 (&u)[NPOL][E], int k) {
+#pragma unroll
+        for (int p = 0; p < NPOL; ++p)
+#pragma unroll
+            for (int q = 0; q < E; ++q) xb[((long long)k * NPOL + p) * NB + t + T * q] = u[p][q];
+    };
+    float2 v[NPOL][E];
+    load_block<NB, E, NPOL>(v, j.src, j.L, (long long)j.blk * j.V - j.halo, t);
+    run_steps<NB, E, NPOL, true, NT>(v, j, twr, sm, nullptr, keep);
+    store_block<NB, E, NPOL>(v, j, t);
 }
 
 // Input gradient of the first pass: for every sample, the sum of the window

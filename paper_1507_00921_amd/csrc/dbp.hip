@@ -1152,9 +1152,13 @@ static size_t grad_ws_bytes(const Plan* p) {
     return (size_t)(f.n_ckpt - 1 + f.seg - 1 + 3) * state + part + fir_table_bytes(p);
 }
 
-// FFT-step plans: geometry of the reverse pass.
+// FFT-step plans: geometry of the reverse pass.  dense: the forward pass keeps every
+// block's field after each step's linear substep (n_passes x k slots per block), and the
+// reverse pass recomputes nothing; otherwise each reverse pass re-runs its steps from the
+// pass input, keeping k - 1 slots per block.
 struct FftGradGeo {
     int nb, V, halo, n_blk, n_wg, k, n_passes, nw;
+    bool dense;
     size_t state, window, xs, part;
 };
 
@@ -1175,13 +1179,21 @@ static FftGradGeo fft_grad_geo(const Plan* p) {
     f.nw = p->desc.method == DBP_ESSFM ? p->desc.n_taps : 0;
     f.state = p->state_bytes();
     f.window = (size_t)f.n_wg * p->desc.n_pol * f.nb * sizeof(float2);
-    f.xs = (size_t)(f.k - 1) * f.window;
+    // the kept fields come from the plan's own pass routine: dense only where that is the
+    // plain per-block kernel with the adjoint's values per thread (not the streaming or the
+    // polarization-split one), the FP64 phase argument, and the fields fit the budget
+    const size_t kept = (size_t)f.n_passes * f.k * f.window;
+    f.dense = !(p->desc.flags & DBP_FLAG_GRAD_SPARSE) && !p->launch_stream && !p->geo.split &&
+              p->geo.e == fft_adjoint_e(f.nb) && p->desc.precision == DBP_FP32_FP64PHASE &&
+              kept <= kDenseCheckpointBytes;
+    f.xs = f.dense ? kept : (size_t)(f.k - 1) * f.window;
     f.part = (size_t)p->geo.n_steps * f.nw * f.n_wg * sizeof(float);
     return f;
 }
 
-// Workspace of the FFT-step gradient: the inputs of passes 1.., the block
-// states of steps 1.. of a pass, two sets of window gradients, the partials.
+// Workspace of the FFT-step gradient: the inputs of passes 1.., the kept block
+// fields (every step of every pass, or steps 0..k-2 of one pass), two sets of
+// window gradients, the partials.
 static size_t fft_grad_ws_bytes(const Plan* p) {
     if (!fft_grad_supported(p)) return 0;
     const FftGradGeo f = fft_grad_geo(p);
@@ -1246,13 +1258,20 @@ static dbp_status fft_grad_forward(Plan* p, const void* in, void* out, const flo
     a.taps = p->desc.method == DBP_ESSFM ? (taps ? taps : p->d_taps) : nullptr;
     a.ntaps = p->desc.method == DBP_ESSFM ? p->desc.n_taps : 1;
     const int grid = p->launch_stream ? p->stream_grid : a.n_wg;
-    const int last = out ? f.n_passes : f.n_passes - 1;
+    float2* xs = (float2*)(w + (size_t)(f.n_passes - 1) * f.state);
+    const size_t per_pass = (size_t)f.k * f.window / sizeof(float2);
+    const int nt = tap_variant(p->desc.method, p->desc.n_taps);
+    // dense: every pass runs (its fields are kept), the last one into out or a scratch window
+    // (the first set of window gradients, not yet in use)
+    const int last = out || f.dense ? f.n_passes : f.n_passes - 1;
     for (int pass = 0; pass < last; ++pass) {
         a.in = ckpt(pass);
-        a.out = pass + 1 < f.n_passes ? (float2*)ckpt(pass + 1) : (float2*)out;
+        a.out = pass + 1 < f.n_passes ? (float2*)ckpt(pass + 1) : out ? (float2*)out : (float2*)((char*)xs + f.xs);
         a.s0 = pass * f.k;
         a.ks = std::min(f.k, p->geo.n_steps - a.s0);
-        if (fn(a, grid, s) != hipSuccess) return DBP_ERR_HIP;
+        const hipError_t e = f.dense ? launch_keep_pass(f.nb, p->desc.n_pol, nt, a, xs + pass * per_pass, f.k, s)
+                                     : fn(a, grid, s);
+        if (e != hipSuccess) return DBP_ERR_HIP;
     }
     return DBP_OK;
 }
@@ -1267,9 +1286,11 @@ static dbp_status fft_grad_reverse(Plan* p, const void* in, const float* taps, c
     float2* xs = (float2*)(w + (size_t)(f.n_passes - 1) * f.state);
     float2* G[2] = {(float2*)((char*)xs + f.xs), (float2*)((char*)xs + f.xs + f.window)};
     float* part = (float*)((char*)G[1] + f.window);
+    const size_t per_pass = (size_t)f.k * f.window / sizeof(float2);
     AdjArgs r{};
     r.xs = xs;
-    r.kmax = f.k;
+    r.slots = f.dense ? f.k : f.k - 1;
+    r.saved = f.dense ? 1 : 0;
     r.L = p->desc.n_samples;
     r.V = f.V;
     r.halo = f.halo;
@@ -1288,6 +1309,7 @@ static dbp_status fft_grad_reverse(Plan* p, const void* in, const float* taps, c
         r.gout = G[i & 1];
         r.s0 = pass * f.k;
         r.ks = std::min(f.k, p->geo.n_steps - r.s0);
+        if (f.dense) r.xs = xs + pass * per_pass;
         if (launch_fft_adjoint(f.nb, p->desc.n_pol, r, s) != hipSuccess) return DBP_ERR_HIP;
     }
     if (grad_in && launch_grad_gather(p->desc.n_pol, G[(f.n_passes - 1) & 1], (float2*)grad_in, r.L, f.nb, f.V,

@@ -166,11 +166,19 @@ __device__ __forceinline__ void load_block(float2 (&v)[NPOL][E], const float2* _
 // HLDS: every step of the pass uses one dispersion table, copied to hl in
 // LDS with each thread holding the entries of its own bins (so no barrier
 // orders the copy).  WF: the in-wave 1024-point transform (twiddles from
-// load_step_twiddles) instead of the Stockham one.  Every thread of the
-// workgroup must call this.
-template <int NB, int E, int NPOL, bool PHASE64, int NT, bool HLDS = false, bool WF = wave_fft_default<NB, E>>
+// load_step_twiddles) instead of the Stockham one.  keep(v, j) sees the field
+// after the linear substep of the pass's step j (the pass kernels keep
+// nothing; the forward pass that stores these fields for the reverse mode
+// passes a store).  Every thread of the workgroup must call this.
+struct KeepNothing {
+    template <typename F> __device__ __forceinline__ void operator()(const F&, int) const {}
+};
+
+template <int NB, int E, int NPOL, bool PHASE64, int NT, bool HLDS = false, bool WF = wave_fft_default<NB, E>,
+          typename Keep = KeepNothing>
 __device__ __forceinline__ void run_steps(float2 (&v)[NPOL][E], const BlockJob& a, const TwReg<NB, E>& twr,
-                                          BlockSmem<NB, E, NPOL, NT>& sm, const float2* __restrict__ hl) {
+                                          BlockSmem<NB, E, NPOL, NT>& sm, const float2* __restrict__ hl,
+                                          Keep keep = {}) {
     using S = FftShape<NB, E>;
     using X = Exchange<NB, E, NPOL>;
     constexpr int T = S::T;
@@ -239,6 +247,7 @@ __device__ __forceinline__ void run_steps(float2 (&v)[NPOL][E], const BlockJob& 
             if constexpr (S::TW_MEM) asm volatile("" : "+v"(ti));
             block_fft<NB, E, NPOL, true>(v, lds, twr, ti);
         }
+        keep(v, s - a.s0);
         // (iv) nonlinear phase driven by the total intensity, Eqs. (2)-(3)
         float J[E];
 #pragma unroll

@@ -55,12 +55,21 @@ def case(seed, batch, n_pol, n, n_spans, nc):
 ])
 def test_fft_grad_matches_oracle(dbp, nb, o, k, n_pol, nc, n_spans, n, batch):
     xs, taps, gout = case(nb + k, batch, n_pol, n, n_spans, nc)
-    p = dbp.plan(n, n_spans, 1, batch=batch, n_pol=n_pol, taps=None if taps is None else taps[0], block=nb,
-                 overlap=o, steps_per_pass=k, beta2_ps2_km=B2)
+    kw = dict(batch=batch, n_pol=n_pol, taps=None if taps is None else taps[0], block=nb, overlap=o,
+              steps_per_pass=k, beta2_ps2_km=B2)
+    p = dbp.plan(n, n_spans, 1, **kw)
     assert (p.block, p.overlap, p.steps_per_pass) == (nb, o, k)
     t_dev = None if taps is None else dev(taps, np.float32)
     gx, gt, gf = p.backprop_grad(dev(xs, np.complex64), dev(gout, np.complex64), taps=t_dev)
     assert gf is None
+    # the same gradients, bit for bit, when every reverse pass recomputes its steps from the
+    # pass input instead of reading the fields the forward pass kept (the same arithmetic)
+    q = dbp.plan(n, n_spans, 1, grad_sparse=True, **kw)
+    sx, st_, _ = q.backprop_grad(dev(xs, np.complex64), dev(gout, np.complex64), taps=t_dev)
+    kept = p.workspace_size(grad=True) > q.workspace_size(grad=True)
+    print(f"Nb={nb} O={o} k={k} pol={n_pol}: kernel {p.kernel}, fields kept by the forward pass: {kept}")
+    assert torch.equal(torch.view_as_real(gx), torch.view_as_real(sx))
+    assert (gt is None and st_ is None) or torch.equal(gt, st_)
     gx = gx.cpu().numpy().astype(np.complex128)
     base = R.schedule(n_spans, 80.0, 1, B2, siggen.GAMMA_W_KM, siggen.ALPHA_DB_KM)
     steps = [R.Step(b=st.b, phi=st.phi, w=None if taps is None else taps[s].astype(np.float64))
@@ -106,22 +115,35 @@ def test_fft_grad_is_deterministic_and_matches_autograd(dbp):
     assert torch.equal(tr.grad, a[1])
 
 
-def test_fft_saved_forward_then_reverse(dbp):
-    # the pass inputs kept by dbp_backprop_save give dbp_backprop_grad's gradients bit for bit
-    n, n_spans = 5000, 6
-    xs, taps, gout = case(8, 1, 2, n, n_spans, 4)
-    p = dbp.plan(n, n_spans, 1, batch=1, taps=taps[0], block=1024, overlap=256, steps_per_pass=2,
-                 beta2_ps2_km=B2)
-    x, t, g = dev(xs, np.complex64), dev(taps, np.float32), dev(gout, np.complex64)
+@pytest.mark.parametrize("nb,o,k,n_pol,nc,n,sparse", [
+    (1024, 256, 2, 2, 4, 5000, False),      # the fields of every step kept by the forward pass
+    (1024, 256, 2, 2, 4, 5000, True),       # pass inputs kept, the reverse recomputes
+    (256, 64, 3, 1, 3, 3000, False),        # one-wave blocks, 7 taps (run-time tap count)
+    (512, 128, 2, 2, None, 200000, False),  # SSFM on 521 blocks (not polarization-split)
+    (2048, 512, 2, 2, 4, 9000, False),
+    (4096, 1024, 2, 1, 4, 12000, False),
+])
+def test_fft_saved_forward_then_reverse(dbp, nb, o, k, n_pol, nc, n, sparse):
+    # what dbp_backprop_save keeps gives dbp_backprop_grad's gradients bit for bit, and its
+    # output is dbp_backprop's, bit for bit, in either mode
+    n_spans = 6
+    xs, taps, gout = case(8, 1, n_pol, n, n_spans, nc)
+    p = dbp.plan(n, n_spans, 1, batch=1, n_pol=n_pol, taps=None if taps is None else taps[0], block=nb,
+                 overlap=o, steps_per_pass=k, grad_sparse=sparse, beta2_ps2_km=B2)
+    x, g = dev(xs, np.complex64), dev(gout, np.complex64)
+    t = None if taps is None else dev(taps, np.float32)
     ref_out = p.backprop(x, taps=t)
     ref = p.backprop_grad(x, g, taps=t)
     out, ws = p.backprop_save(x, taps=t)
     got = p.backprop_grad_saved(x, out, ws, g, taps=t)
+    again = p.backprop_grad_saved(x, out, ws, g, taps=t)
     torch.cuda.synchronize()
+    print(f"Nb={nb} k={k} pol={n_pol} sparse={sparse}: {p.kernel}, grad workspace {p.workspace_size(grad=True)}")
     assert torch.equal(torch.view_as_real(out), torch.view_as_real(ref_out))
-    assert torch.equal(torch.view_as_real(got[0]), torch.view_as_real(ref[0]))
-    assert torch.equal(got[1], ref[1])
-    assert got[2] is None
+    for r in (got, again):
+        assert torch.equal(torch.view_as_real(r[0]), torch.view_as_real(ref[0]))
+        assert (r[1] is None and ref[1] is None) or torch.equal(r[1], ref[1])
+        assert r[2] is None
 
 
 def test_fft_grad_finite_difference_of_gpu_forward(dbp):
@@ -153,11 +175,16 @@ def test_fft_grad_argument_rules(dbp):
     p = dbp.plan(n, 4, 1, taps=np.full(9, 0.1, np.float32), block=1024, overlap=256, steps_per_pass=2,
                  beta2_ps2_km=B2)
     ws = p.workspace_size(grad=True)
-    # pass inputs 1..: one state; block states of step 2 of a pass, two window sets, partials
+    # pass inputs 1..: one state; the fields of the 4 steps kept by the forward pass (2 passes
+    # of 2 steps), two window sets, partials
     n_wg = -(-n // 768)
     state = 2 * n * 8
     window = n_wg * 2 * 1024 * 8
-    assert ws == state + window + 2 * window + 4 * 9 * n_wg * 4
+    assert ws == state + 4 * window + 2 * window + 4 * 9 * n_wg * 4
+    # recomputed passes: the fields of step 0 of one pass only
+    sp = dbp.plan(n, 4, 1, taps=np.full(9, 0.1, np.float32), block=1024, overlap=256, steps_per_pass=2,
+                  grad_sparse=True, beta2_ps2_km=B2)
+    assert sp.workspace_size(grad=True) == state + window + 2 * window + 4 * 9 * n_wg * 4
     x = torch.zeros(1, 2, n, dtype=torch.complex64, device="cuda")
     g = torch.zeros_like(x)
     L = dbp.lib()
