@@ -6,7 +6,8 @@ into the result; the guards of outputs hold a NaN pattern that arithmetic never 
 write past a buffer changes them.  Every guarded call is checked bit for bit against the same
 call on ordinary allocations, and every guard word afterwards.  Covers the pass kernels
 (blocked, whole-signal, the 8192-point blocks, both FIR paths), both reverse modes through the
-C ABI, the ragged batch, the receiver mode and the receiver DSP.
+C ABI (FFT steps from kept fields and recomputed), the ragged batch, the receiver mode and the
+receiver DSP.
 """
 import numpy as np
 import pytest
@@ -90,6 +91,9 @@ def field(seed, shape):
 
 PLANS = {
     "fft_essfm_1024_ragged_batch2": dict(n=5000, n_spans=6, spp=1, batch=2, taps=T9, block=1024, overlap=256),
+    # the reverse pass re-running its steps from the pass inputs instead of reading kept fields
+    "fft_essfm_1024_recompute": dict(n=5000, n_spans=6, spp=1, batch=2, taps=T9, block=1024, overlap=256,
+                                     grad_sparse=True),
     "fft_ssfm_512_one_pol": dict(n=3001, n_spans=4, spp=2, n_pol=1, block=512, overlap=128),
     "whole_signal_16384": dict(n=16384, n_spans=4, spp=1, n_pol=1, whole=True),
     "blocks_8192_essfm": dict(n=20000, n_spans=4, spp=1, taps=T9, block=8192, overlap=2048),
@@ -122,8 +126,8 @@ def test_backprop_stays_inside_its_buffers(dbp, name):
     p.close()
 
 
-@pytest.mark.parametrize("name", ["fft_essfm_1024_ragged_batch2", "fft_ssfm_512_one_pol", "fir_time_domain",
-                                  "fir_fft_blocks"])
+@pytest.mark.parametrize("name", ["fft_essfm_1024_ragged_batch2", "fft_essfm_1024_recompute", "fft_ssfm_512_one_pol",
+                                  "fir_time_domain", "fir_fft_blocks"])
 def test_backprop_grad_stays_inside_its_buffers(dbp, name):
     p = make(dbp, PLANS[name])
     x = field(2, p.shape)
