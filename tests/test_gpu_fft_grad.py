@@ -146,6 +146,36 @@ def test_fft_saved_forward_then_reverse(dbp, nb, o, k, n_pol, nc, n, sparse):
         assert r[2] is None
 
 
+def test_fft_kept_fields_budget_and_persistent_plans(dbp):
+    # 64 headline-size signals: the kept fields (8 passes x 5 steps x 342 blocks x 64 x 2 x
+    # 1024 x 8 B = 14.3 GB) exceed the 4 GiB budget, so the plan keeps pass inputs only
+    n, k, nb, V = 262144, 5, 1024, 768
+    big = dbp.plan(n, 40, 1, batch=64, taps=np.full(9, 0.1, np.float32), block=nb, overlap=nb - V,
+                   beta2_ps2_km=B2)
+    assert big.steps_per_pass == k
+    n_wg = -(-n // V) * 64
+    state = 64 * 2 * n * 8
+    window = n_wg * 2 * nb * 8
+    assert big.workspace_size(grad=True) == 7 * state + (k - 1) * window + 2 * window + 40 * 9 * n_wg * 4
+    big.close()
+    # a persistent-launch plan: the forward that keeps the fields gives its output bit for bit
+    n_spans = 6
+    xs, taps, gout = case(12, 1, 2, 20000, n_spans, 4)
+    p = dbp.plan(20000, n_spans, 1, taps=taps[0], block=1024, overlap=256, steps_per_pass=2, persistent=True,
+                 beta2_ps2_km=B2)
+    x, t, g = dev(xs, np.complex64), dev(taps, np.float32), dev(gout, np.complex64)
+    ref_out = p.backprop(x, taps=t)
+    out, ws = p.backprop_save(x, taps=t)
+    got = p.backprop_grad_saved(x, out, ws, g, taps=t)
+    ref = p.backprop_grad(x, g, taps=t)
+    torch.cuda.synchronize()
+    print(f"persistent plan: {p.kernel}")
+    assert torch.equal(torch.view_as_real(out), torch.view_as_real(ref_out))
+    assert torch.equal(torch.view_as_real(got[0]), torch.view_as_real(ref[0]))
+    assert torch.equal(got[1], ref[1])
+    p.close()
+
+
 def test_fft_grad_finite_difference_of_gpu_forward(dbp):
     # d/dw of <g, DBP(x; w)> along a tap direction, by central differences of the GPU forward
     n, n_spans = 4096, 4
