@@ -16,7 +16,9 @@
 // every block writes its window gradient to its own slot, and the earlier
 // pass (or the final gather) sums, for each sample, the slots of the blocks
 // whose window covers it, in block order: no atomics, the same result on
-// every run.
+// every run.  Each step's adjoint needs only the block's u: the forward pass
+// (dbp_keep_pass_kernel) stores u of every step, or the reverse launch
+// re-runs the pass's steps from the pass input to get it.
 #pragma once
 #include <hip/hip_runtime.h>
 
