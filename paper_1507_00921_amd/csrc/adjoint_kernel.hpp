@@ -72,6 +72,10 @@ __device__ __forceinline__ float2 gather_window_grad(const float2* __restrict__ 
     return acc;
 }
 
+// s_waitcnt immediate with vmcnt 0 and the other counters at their maximum (no wait on them):
+// vmcnt in bits 3:0 and 15:14, expcnt in 6:4, lgkmcnt in 11:8.
+constexpr int kVmcntZero = 0x0F70;
+
 template <int NB, int E, int NPOL, int NT> struct AdjSmem {
     static constexpr int NW = NB / E / 64 > 0 ? NB / E / 64 : 1;     // waves per block
     static constexpr int NR = NT > 0 ? NT : (NT == 0 ? 1 : DBP_MAX_TAPS);
@@ -150,7 +154,9 @@ __global__ __launch_bounds__(NB / E) void dbp_adjoint_kernel(AdjArgs a) {
             J[q] = in;
         }
         if constexpr (NT != 0) {
-            const float* __restrict__ w = a.taps + (long long)s * ntaps;
+            // the taps through the scalar path (uniform, never written here): their waits then
+            // do not hold up the vector loads in flight
+            const auto w = as_const(a.taps) + (long long)s * ntaps;
 #pragma unroll
             for (int q = 0; q < E; ++q) sm.inten[t + T * q] = J[q];
             __syncthreads();
@@ -170,7 +176,13 @@ __global__ __launch_bounds__(NB / E) void dbp_adjoint_kernel(AdjArgs a) {
     // reverse sweep below runs no forward transform.  When the forward pass kept u of every
     // step (a.saved), nothing is recomputed.
     float2 v[NPOL][E];
-    if (!a.saved) load_block<NB, E, NPOL>(v, xsig, L, start, t);
+    if (!a.saved) {
+        load_block<NB, E, NPOL>(v, xsig, L, start, t);
+        // the block's loads complete here, before the sweep: otherwise their first use puts
+        // vector-memory waits at the top of every step, where they would also wait for the
+        // previous step's field stores (the counter covers stores as well)
+        __builtin_amdgcn_s_waitcnt(kVmcntZero);
+    }
     for (int j = 0; !a.saved; ++j) {
         const StepDev st = load_step(a.steps + a.s0 + j);
         float2 h[E];
@@ -256,7 +268,7 @@ __global__ __launch_bounds__(NB / E) void dbp_adjoint_kernel(AdjArgs a) {
         // u of step s is in v: its I, J and the phase factor f = exp(-j phi J)
         float J[E];
         filtered(v, s, J);
-        const float* __restrict__ w = a.taps + (long long)s * ntaps;
+        const auto w = as_const(a.taps) + (long long)s * ntaps;
         // adjoint of the phase rotation: Jbar, and g <- g conj(f)
         float jb[E];
 #pragma unroll
