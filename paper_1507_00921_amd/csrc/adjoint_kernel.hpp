@@ -24,6 +24,7 @@
 
 #include "dbp.h"
 #include "step_kernel.hpp"
+#include "waitcnt.hpp"
 
 namespace dbp {
 
@@ -71,10 +72,6 @@ __device__ __forceinline__ float2 gather_window_grad(const float2* __restrict__ 
     }
     return acc;
 }
-
-// s_waitcnt immediate with vmcnt 0 and the other counters at their maximum (no wait on them):
-// vmcnt in bits 3:0 and 15:14, expcnt in 6:4, lgkmcnt in 11:8.
-constexpr int kVmcntZero = 0x0F70;
 
 template <int NB, int E, int NPOL, int NT> struct AdjSmem {
     static constexpr int NW = NB / E / 64 > 0 ? NB / E / 64 : 1;     // waves per block
@@ -181,7 +178,7 @@ __global__ __launch_bounds__(NB / E) void dbp_adjoint_kernel(AdjArgs a) {
         // the block's loads complete here, before the sweep: otherwise their first use puts
         // vector-memory waits at the top of every step, where they would also wait for the
         // previous step's field stores (the counter covers stores as well)
-        __builtin_amdgcn_s_waitcnt(kVmcntZero);
+        wait_vector_memory();
     }
     for (int j = 0; !a.saved; ++j) {
         const StepDev st = load_step(a.steps + a.s0 + j);
