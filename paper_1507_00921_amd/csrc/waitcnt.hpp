@@ -1,6 +1,7 @@
-// Explicit vector-memory waits.  On this GPU the vector-memory counter
-// (vmcnt) counts stores as well as loads, and the compiler's wait analysis
-// merges every path into a point: loads still in flight when a loop is
+// Explicit vector-memory waits.  On gfx950, as on the whole GFX9 family, the
+// vector-memory counter (vmcnt) counts stores as well as loads, and the
+// compiler's wait analysis merges every path into a point: loads still in
+// flight when a loop is
 // entered make it wait at the top of every iteration, which at run time also
 // waits for every store the previous iteration issued.  Waiting explicitly
 // before the loop, where the loads are needed anyway, tells the analysis that
