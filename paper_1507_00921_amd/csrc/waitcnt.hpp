@@ -1,11 +1,10 @@
 // Explicit vector-memory waits.  On gfx950, as on the whole GFX9 family, the
 // vector-memory counter (vmcnt) counts stores as well as loads, and the
 // compiler's wait analysis merges every path into a point: loads still in
-// flight when a loop is
-// entered make it wait at the top of every iteration, which at run time also
-// waits for every store the previous iteration issued.  Waiting explicitly
-// before the loop, where the loads are needed anyway, tells the analysis that
-// nothing but stores is pending inside it.
+// flight when a loop is entered make it wait at the top of every iteration,
+// which at run time also waits for every store the previous iteration issued.
+// Waiting explicitly before the loop, where the loads are needed anyway, tells
+// the analysis that nothing but stores is pending inside it.
 #pragma once
 #include <hip/hip_runtime.h>
 
